@@ -1,0 +1,195 @@
+"""Benchmark: two-layer (rANS + absolute-offset match) full-archive decode.
+
+Workload: 256 MiB of seeded synthetic FASTQ-like records, 16 KiB blocks,
+32-way interleaved rANS with 12-bit frequencies, encoded on the host by the
+library encoder; the archive is resident in HBM before timing starts.  One
+step = one whole-archive decode through both layers (every step of the
+hot path).  Prints one JSON line.
+
+Also reported: the roofline of the decode against MI355X HBM peak
+(algorithmic bytes = archive + output + match bytes read from earlier
+blocks), the CPU oracle's decode rate on this host, and seek latency
+(p50/p99) of single seeks, one launch sequence per seek, against the same
+requests decoded as one batch.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile", default="fastq")
+    ap.add_argument("--size", type=int, default=256 << 20)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--block", type=int, default=16384)
+    ap.add_argument("--interleave", type=int, default=32)
+    ap.add_argument("--min-match", type=int, default=20)
+    ap.add_argument("--max-level", type=int, default=16)
+    ap.add_argument("--mode", type=int, default=0, help="0 persistent, 1 one launch per level")
+    ap.add_argument("--seek-requests", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-seek", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build's decode path runs on a single "
+              "MI355X (see DESIGN.md for how it would shard); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2606_24531_amd import Archive, encode
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    x = gen.by_name(args.profile, args.size, args.seed)
+    _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
+    t0 = time.time()
+    a = encode(x, block_size=args.block, interleave=args.interleave, min_match=args.min_match,
+               hash_len=args.min_match, max_chain=32, max_level=args.max_level)
+    _log("encoded to %d bytes (ratio %.3f) in %.1fs" % (len(a), len(x) / len(a), time.time() - t0))
+
+    arc = Archive(a, device=dev)
+    ws = arc.workspace(arc.workspace_bytes())
+    out = torch.empty(arc.n_total, dtype=torch.uint8, device=dev)
+    tuning = dict(mode=args.mode)
+    stream = torch.cuda.current_stream()
+
+    # untimed: one decode checked against the original bytes, and its
+    # external-source byte count
+    arc.read_counters()
+    arc.decode_all(out=out, ws=ws, tuning=tuning)
+    arc.check()
+    ext = arc.read_counters()["ext_src_bytes"]
+    ok = bytes(out.cpu().numpy()) == x
+    if not ok:
+        _log("DECODE MISMATCH")
+        sys.exit(1)
+    _log("parity ok; depth %d, %d blocks, external source bytes %d" % (arc.depth, arc.n_blocks, ext))
+
+    for _ in range(args.warmup):
+        arc.decode_all(out=out, ws=ws, tuning=tuning)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        arc.decode_all(out=out, ws=ws, tuning=tuning)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    arc.check()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    gbs = len(x) / (ms * 1e-3) / 1e9
+    alg_bytes = len(a) + len(x) + ext
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    _log("decode %.3f ms/step, %.1f GB/s decompressed, %.1f GB/s algorithmic" % (ms, gbs, achieved))
+
+    result = {
+        "metric": "2-layer decode GB/s (full archive)",
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
+                args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level),
+            "n_total": len(x), "archive_bytes": len(a), "ratio": round(len(x) / len(a), 4),
+            "block_size": args.block, "interleave": args.interleave,
+            "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
+            "mode": "persistent" if args.mode == 0 else "per-level launches",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_step": alg_bytes, "ext_src_bytes": ext,
+        },
+    }
+
+    if not args.no_seek:
+        rng = np.random.default_rng(4)
+        n_req = args.seek_requests
+        lo, hi = gen.seek_requests(len(x), n_req, 4, max_len=4 << 20)
+        lens = (hi - lo).astype(np.int64)
+        # plain: one seek call (its own launches) per request, waited on
+        wsz = max(arc.workspace_bytes([int(l), int(h)]) for l, h in zip(lo[:50], hi[:50]))
+        ws_seek = torch.zeros(max(wsz, arc.workspace_bytes()), dtype=torch.uint8, device=dev)
+        buf = torch.empty(int(lens.max()), dtype=torch.uint8, device=dev)
+        lat = []
+        for i in range(n_req):
+            t = time.perf_counter()
+            arc.seek(int(lo[i]), int(hi[i]), out=buf, ws=ws_seek, tuning=tuning)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+        arc.check(ws_seek)
+        plain_total = sum(lat)
+        # batched: all requests in one call
+        ws_b = torch.zeros(arc.workspace_bytes((lo, hi)), dtype=torch.uint8, device=dev)
+        outb = torch.empty(int(lens.sum()), dtype=torch.uint8, device=dev)
+        arc.seek_batch((lo, hi), out=outb, ws=ws_b, tuning=tuning)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            t = time.perf_counter()
+            arc.seek_batch((lo, hi), out=outb, ws=ws_b, tuning=tuning)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        arc.check(ws_b)
+        bt = float(np.median(times))
+        result["seek"] = {
+            "requests": n_req, "len": "log-uniform 1 B..4 MiB", "bytes": int(lens.sum()),
+            "plain_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 4),
+            "plain_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+            "plain_req_per_s": round(n_req / plain_total, 1),
+            "batched_latency_ms": round(1e3 * bt, 4),
+            "batched_req_per_s": round(n_req / bt, 1),
+            "batched_vs_plain_throughput": round(plain_total / bt, 2),
+        }
+        _log("seek: plain p50 %.3f ms p99 %.3f ms; batch of %d in %.3f ms" % (
+            result["seek"]["plain_p50_ms"], result["seek"]["plain_p99_ms"], n_req, 1e3 * bt))
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        reps, t_total = 0, 0.0
+        while reps < 5 and t_total < 12.0:
+            t = time.perf_counter()
+            y = oracle.decode(a)
+            t_total += time.perf_counter() - t
+            reps += 1
+        assert y == x
+        result["cpu_baseline"] = {
+            "value": round(len(x) * reps / t_total / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d full sequential decode(s) of the same %d MiB archive" % (reps, len(x) >> 20),
+        }
+        _log("cpu oracle %.3f GB/s" % result["cpu_baseline"]["value"])
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * aceseek.h -- C ABI of libaceseek, a gfx950 (MI355X) decoder for archives
+ * of the two-layer absolute-offset codec: per-block interleaved rANS over
+ * three token streams (literals, lengths, absolute offsets), then an LZ77
+ * match layer whose back-references name absolute positions in the output.
+ *
+ * The paper's central operation is a seek: decode one absolute byte range
+ * through both layers, in isolation (Sections 3 and 5).  Section 2 gives the
+ * reason it is possible: offsets are absolute, so a block decodes as soon as
+ * the blocks holding its source bytes are present, whatever path led there.
+ * Section 7 adds range decoding of many blocks.
+ *
+ * Conventions
+ *  - Every function returns ACE_OK (0) or a negative ACE_E_* code and, on
+ *    error, leaves a description for ace_last_error() (per thread).
+ *  - Pointers named d_* are device (HBM) pointers, h_* are host pointers.
+ *    The caller owns every buffer; the library never allocates or frees
+ *    device memory.  An ace_archive owns only a host copy of the index.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    asynchronous on it; host-side validation errors are returned at once,
+ *    device-side ones (corrupt token streams) are sticky in the workspace
+ *    and read by ace_check().
+ *  - Calls on different streams must use different workspaces.  A fresh
+ *    workspace's first 256 bytes must be zero (its error word and counters);
+ *    ace_check() and ace_read_counters() clear what they read.
+ */
+#ifndef ACESEEK_H
+#define ACESEEK_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACE_OK 0
+#define ACE_E_ARG (-1)     /* null pointer, bad parameter, lo > hi */
+#define ACE_E_RANGE (-2)   /* range beyond the decompressed size */
+#define ACE_E_CORRUPT (-3) /* archive fails validation */
+#define ACE_E_NOSPACE (-4) /* output or workspace too small */
+#define ACE_E_HIP (-5)     /* HIP runtime error */
+#define ACE_E_TIMEOUT (-6) /* a bounded device wait expired */
+#define ACE_E_NOMEM (-7)   /* host allocation failed */
+
+/* Bytes of readable slack the device copy of an archive must have after its
+ * last byte (kernels stage stream data in 16-byte-aligned chunks). */
+#define ACE_ARCH_PAD 4096u
+
+/* Encoder parameters.  None of them affects how an archive decodes.
+ *  block_size  B, bytes per block, 1 .. 2^24
+ *  interleave  W, rANS states per stream, 1 .. 64
+ *  min_match   shortest match emitted (>= hash_len)
+ *  hash_len    bytes hashed per position, 1 .. 64
+ *  max_chain   hash-chain candidates examined per position
+ *  max_level   0 = unbounded; else every block's dependency level < max_level
+ *  flags       stream-mode policy: 0 = rANS only where smaller, 1 = always
+ *              rANS, 2 = always raw
+ *  n_threads   host threads for the parse (0 = all cores) */
+typedef struct {
+  uint32_t block_size, interleave, min_match, hash_len, max_chain, max_level, flags, n_threads;
+} ace_encode_params;
+
+/* A half-open range [lo, hi) of absolute positions in the decompressed data. */
+typedef struct {
+  uint64_t lo, hi;
+} ace_range;
+
+/* Launch shape.  Zero fields take the library defaults.
+ *  waves_per_block  wavefronts cooperating on one block's match expansion
+ *  blocks_per_wg    reserved (1)
+ *  lut_variant      0 = 4096 x u32 slot table in LDS
+ *  grid_wgs         workgroups of the persistent decoder (0 = fill the GPU)
+ *  mode             0 = persistent dependency-ordered kernel, 1 = one launch
+ *                   per dependency level (the always-correct fallback) */
+typedef struct {
+  uint32_t waves_per_block, blocks_per_wg, lut_variant, grid_wgs, mode;
+} ace_tuning;
+
+typedef struct ace_archive ace_archive;
+
+const char* ace_last_error(void);
+
+/* ---- host encoder (the paper's encoder runs on the CPU, Section 2) ---- */
+/* Upper bound on the archive size for n input bytes. */
+int ace_encode_bound(uint64_t n, const ace_encode_params* p, uint64_t* bound);
+/* Encodes h_src[0..n) into h_dst (capacity dst_cap); *dst_len receives the
+ * archive size (also when ACE_E_NOSPACE is returned). */
+int ace_encode_archive(const uint8_t* h_src, uint64_t n, const ace_encode_params* p,
+                       uint8_t* h_dst, uint64_t dst_cap, uint64_t* dst_len);
+
+/* ---- archive residency (Section 9: data stays compressed-resident) ----
+ * h_arch: the archive bytes in host memory (read during the call only);
+ * d_arch: the same bytes already copied to the device, with ACE_ARCH_PAD
+ * readable bytes after them, kept alive by the caller while the handle is
+ * used.  Validates the header, block table, dependency lists, levels and
+ * stream descriptors; token-level checks happen on the device. */
+int ace_archive_open(const uint8_t* h_arch, uint64_t len, const void* d_arch, ace_archive** out);
+void ace_archive_close(ace_archive* a);
+int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_t* block_size,
+                     uint32_t* n_blocks, uint32_t* depth);
+
+/* Workspace bytes needed to decode the given ranges (ranges == NULL and
+ * n_ranges == 0: the whole archive). */
+int ace_workspace_bytes(const ace_archive* a, const ace_range* ranges, uint32_t n_ranges,
+                        uint64_t* bytes);
+
+/* Whole-archive decode: writes n_total bytes at d_out (out_cap >= n_total). */
+int ace_decode_all(const ace_archive* a, uint8_t* d_out, uint64_t out_cap, void* d_ws,
+                   uint64_t ws_cap, const ace_tuning* t, void* stream);
+
+/* Seek (Section 5): writes exactly hi - lo bytes at d_out and nothing else in
+ * d_out.  Blocks that only supply sources are decoded into the workspace.
+ * An empty range returns ACE_OK without launching. */
+int ace_seek(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+             uint64_t ws_cap, const ace_tuning* t, void* stream);
+
+/* Batched seek: request i writes [lo_i, hi_i) at d_out + h_out_off[i].  All
+ * requests share one dependency-ordered decode of the union of their
+ * closures, then one gather. */
+int ace_seek_batch(const ace_archive* a, const ace_range* h_ranges, uint32_t n,
+                   uint8_t* d_out, const uint64_t* h_out_off, void* d_ws, uint64_t ws_cap,
+                   const ace_tuning* t, void* stream);
+
+/* Waits for the stream, reads and clears the workspace's sticky device error
+ * word: ACE_OK, ACE_E_CORRUPT (a token stream broke a format rule) or
+ * ACE_E_TIMEOUT (a bounded dependency wait expired). */
+int ace_check(void* d_ws, void* stream);
+
+/* Waits for the stream, then reads and clears the workspace's counter of
+ * match bytes that were copied from earlier blocks (the external source
+ * bytes of every decode since the last read).  With the archive size and the
+ * output size this gives the algorithmic HBM bytes of a decode. */
+int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

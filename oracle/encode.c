@@ -14,9 +14,13 @@
  *     recent first for at most max_chain candidates; a candidate q scores
  *     the common prefix of X[q..] and X[p..], capped at the block end and at
  *     65535 (overlap with p is allowed: the copy is byte-sequential);
- *   - with max_level > 0 a candidate is cut before the first earlier block
- *     of level >= max_level - 1 that its source touches, so every block ends
- *     with level < max_level;
+ *   - with max_level > 0 blocks are grouped in epochs of 64; block b may
+ *     take sources only from itself and from blocks of earlier epochs whose
+ *     level is <= max_level - 2 ("visible" blocks), so every level stays
+ *     below max_level.  Chain candidates in invisible blocks are passed over
+ *     without being counted (at most 8 * max_chain chain steps in all), and a
+ *     counted candidate is cut where its source first enters an invisible
+ *     block;
  *   - the longest candidate wins, ties to the first found (most recent);
  *     it is taken if it reaches min_match, else p is a literal.
  * The parse is encoder policy; any legal parse decodes to the same bytes.
@@ -399,17 +403,21 @@ int orc_encode(const uint8_t* src, uint64_t n, const orc_params* p, uint8_t* dst
       uint64_t best = 0, bestq = 0;
       if (pos + p->hash_len <= n && e - pos >= p->min_match) {
         uint64_t q = prev[pos];
-        uint32_t cand = 0;
+        uint32_t cand = 0, steps = 0;
         uint64_t lim = e - pos < 65535 ? e - pos : 65535;
-        while (q != NONE && cand < p->max_chain) {
+        /* first byte of this block's epoch: earlier blocks of the epoch are invisible */
+        uint64_t epoch0 = p->max_level > 0 ? (b / 64) * 64 * B : s;
+        for (; q != NONE && cand < p->max_chain && steps < 8 * p->max_chain; steps++, q = prev[q]) {
+          if (p->max_level > 0 && q < s && (q >= epoch0 || level[q / B] + 1 >= p->max_level))
+            continue; /* starts in an invisible block: passed over, not counted */
           cand++;
           uint64_t len = 0;
           while (len < lim && src[q + len] == src[pos + len]) len++;
           if (p->max_level > 0) {
-            /* cut before the first earlier block that is too deep */
+            /* cut where the source first enters an invisible block */
             uint64_t end = q + len < s ? q + len : s;
             for (uint64_t c = q / B; c * B < end; c++)
-              if (level[c] + 1 >= p->max_level) {
+              if (c * B >= epoch0 || level[c] + 1 >= p->max_level) {
                 len = c * B > q ? c * B - q : 0;
                 break;
               }
@@ -418,7 +426,6 @@ int orc_encode(const uint8_t* src, uint64_t n, const orc_params* p, uint8_t* dst
             best = len;
             bestq = q;
           }
-          q = prev[q];
         }
       }
       if (best >= p->min_match) {

@@ -1,0 +1,246 @@
+"""Python binding of libaceseek (argument marshalling only).
+
+Every decode step runs in the library's HIP kernels; torch supplies device
+memory and streams.  Entry points mirror include/aceseek.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libaceseek.so")
+
+ARCH_PAD = 4096
+OK, E_ARG, E_RANGE, E_CORRUPT, E_NOSPACE, E_HIP, E_TIMEOUT, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+
+EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_archive_open",
+           "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
+           "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters"]
+
+
+class AceError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"aceseek error {code}: {msg}")
+        self.code = code
+
+
+class EncodeParams(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("block_size", "interleave", "min_match", "hash_len",
+                                          "max_chain", "max_level", "flags", "n_threads")]
+
+
+class Range(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("waves_per_block", "blocks_per_wg", "lut_variant",
+                                          "grid_wgs", "mode")]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def lib():
+    """The loaded libaceseek; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            raise ImportError("libaceseek.so is not built (run __graft_entry__.build() or "
+                              "python paper_2606_24531_amd/build.py)")
+        L = C.CDLL(_LIB)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        u64p, u32p = C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
+        L.ace_last_error.restype = C.c_char_p
+        L.ace_encode_bound.argtypes = [u64, C.POINTER(EncodeParams), u64p]
+        L.ace_encode_archive.argtypes = [vp, u64, C.POINTER(EncodeParams), vp, u64, u64p]
+        L.ace_archive_open.argtypes = [vp, u64, vp, C.POINTER(vp)]
+        L.ace_archive_close.argtypes = [vp]
+        L.ace_archive_close.restype = None
+        L.ace_archive_info.argtypes = [vp, u64p, u32p, u32p, u32p]
+        L.ace_workspace_bytes.argtypes = [vp, vp, u32, u64p]
+        L.ace_decode_all.argtypes = [vp, vp, u64, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_seek.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_seek_batch.argtypes = [vp, vp, u32, vp, vp, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_check.argtypes = [vp, vp]
+        L.ace_read_counters.argtypes = [vp, vp, u64p]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise AceError(rc, lib().ace_last_error().decode(errors="replace"))
+
+
+def _params(block_size=16384, interleave=32, min_match=20, hash_len=20, max_chain=32,
+            max_level=0, flags=0, n_threads=0) -> EncodeParams:
+    return EncodeParams(block_size, interleave, min_match, hash_len, max_chain, max_level,
+                        flags, n_threads)
+
+
+def encode_bound(n: int, **kw) -> int:
+    p = _params(**kw)
+    b = C.c_uint64(0)
+    _check(lib().ace_encode_bound(n, C.byref(p), C.byref(b)))
+    return b.value
+
+
+def encode(x, **kw) -> bytes:
+    """Host encoder of the library (multi-threaded)."""
+    p = _params(**kw)
+    src = np.frombuffer(x, dtype=np.uint8) if not isinstance(x, np.ndarray) else x
+    bound = encode_bound(len(src), **kw)
+    out = np.empty(max(bound, 1), dtype=np.uint8)
+    ln = C.c_uint64(0)
+    rc = lib().ace_encode_archive(src.ctypes.data_as(C.c_void_p), len(src), C.byref(p),
+                                  out.ctypes.data_as(C.c_void_p), out.size, C.byref(ln))
+    if rc == E_NOSPACE:
+        out = np.empty(ln.value, dtype=np.uint8)
+        rc = lib().ace_encode_archive(src.ctypes.data_as(C.c_void_p), len(src), C.byref(p),
+                                      out.ctypes.data_as(C.c_void_p), out.size, C.byref(ln))
+    _check(rc)
+    return out[:ln.value].tobytes()
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Archive:
+    """A compressed archive resident in HBM, with a reusable workspace."""
+
+    def __init__(self, data, device="cuda"):
+        import torch
+        self._torch = torch
+        host = np.frombuffer(data, dtype=np.uint8) if not isinstance(data, np.ndarray) else data
+        self.nbytes = int(host.size)
+        self.device = torch.device(device)
+        d = torch.zeros(self.nbytes + ARCH_PAD, dtype=torch.uint8, device=self.device)
+        if self.nbytes:
+            d[:self.nbytes].copy_(torch.from_numpy(np.array(host, dtype=np.uint8, copy=True)))
+        self.d_arch = d
+        h = C.c_void_p()
+        _check(lib().ace_archive_open(host.ctypes.data_as(C.c_void_p), self.nbytes,
+                                      C.c_void_p(d.data_ptr()), C.byref(h)))
+        self._h = h
+        n, B, nb, depth = C.c_uint64(0), C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
+        _check(lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)))
+        self.n_total, self.block_size, self.n_blocks, self.depth = n.value, B.value, nb.value, depth.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_archive_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspace
+    def workspace_bytes(self, ranges=None) -> int:
+        b = C.c_uint64(0)
+        if ranges is None:
+            _check(lib().ace_workspace_bytes(self._h, None, 0, C.byref(b)))
+        else:
+            r = self._ranges(ranges)
+            _check(lib().ace_workspace_bytes(self._h, r.ctypes.data_as(C.c_void_p), len(r) // 2,
+                                             C.byref(b)))
+        return b.value
+
+    def workspace(self, nbytes: int):
+        """A zero-initialised device workspace of at least nbytes (reused)."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = self._torch.zeros(max(nbytes, 256), dtype=self._torch.uint8,
+                                         device=self.device)
+        return self._ws
+
+    @staticmethod
+    def _ranges(ranges):
+        if isinstance(ranges, tuple) and len(ranges) == 2 and hasattr(ranges[0], "__len__"):
+            lo, hi = ranges
+            r = np.empty(2 * len(lo), dtype=np.uint64)
+            r[0::2] = lo
+            r[1::2] = hi
+            return r
+        r = np.asarray(ranges, dtype=np.uint64).reshape(-1)
+        return np.ascontiguousarray(r)
+
+    @staticmethod
+    def _tuning(t):
+        if t is None:
+            return None
+        if isinstance(t, Tuning):
+            return C.byref(t)
+        return C.byref(Tuning(**t))
+
+    # -- decode
+    def decode_all(self, out=None, ws=None, tuning=None, stream=None):
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.n_total, dtype=torch.uint8, device=self.device)
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes())
+        _check(lib().ace_decode_all(self._h, C.c_void_p(out.data_ptr()), out.numel(),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), self._tuning(tuning),
+                                    _stream_ptr(stream)))
+        return out
+
+    def seek(self, lo: int, hi: int, out=None, ws=None, tuning=None, stream=None):
+        torch = self._torch
+        if out is None:
+            out = torch.empty(max(hi - lo, 0), dtype=torch.uint8, device=self.device)
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes([lo, hi]) if hi > lo else 256)
+        _check(lib().ace_seek(self._h, lo, hi, C.c_void_p(out.data_ptr()),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), self._tuning(tuning),
+                              _stream_ptr(stream)))
+        return out
+
+    def seek_batch(self, ranges, out=None, out_offsets=None, ws=None, tuning=None, stream=None):
+        """ranges: (lo array, hi array) or a flat [lo0, hi0, lo1, hi1, ...]."""
+        torch = self._torch
+        r = self._ranges(ranges)
+        n = len(r) // 2
+        lens = r[1::2].astype(np.int64) - r[0::2].astype(np.int64)
+        if out_offsets is None:
+            out_offsets = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+        offs = np.ascontiguousarray(out_offsets, dtype=np.uint64)
+        if out is None:
+            total = int(lens.sum()) if n else 0
+            out = torch.empty(max(total, 1), dtype=torch.uint8, device=self.device)
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes(r))
+        _check(lib().ace_seek_batch(self._h, r.ctypes.data_as(C.c_void_p), n,
+                                    C.c_void_p(out.data_ptr()), offs.ctypes.data_as(C.c_void_p),
+                                    C.c_void_p(ws.data_ptr()), ws.numel(), self._tuning(tuning),
+                                    _stream_ptr(stream)))
+        return out
+
+    def read_counters(self, ws=None, stream=None) -> dict:
+        """Synchronises, returns and clears the workspace counters."""
+        ws = self._ws if ws is None else ws
+        v = C.c_uint64(0)
+        _check(lib().ace_read_counters(C.c_void_p(ws.data_ptr()), _stream_ptr(stream),
+                                       C.byref(v)))
+        return {"ext_src_bytes": v.value}
+
+    def check(self, ws=None, stream=None):
+        """Synchronises and raises if the device flagged a corrupt stream."""
+        ws = self._ws if ws is None else ws
+        if ws is None:
+            return
+        _check(lib().ace_check(C.c_void_p(ws.data_ptr()), _stream_ptr(stream)))

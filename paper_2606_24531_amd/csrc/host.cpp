@@ -1,0 +1,504 @@
+// Host side of libaceseek: archive validation, the seek planner and the C
+// ABI entry points declared in include/aceseek.h.
+//
+// Planner (paper Sections 2, 3, 5 and 7).  A range [lo, hi) names target
+// blocks floor(lo/B) .. floor((hi-1)/B).  Because every back-reference is an
+// absolute position, a block can be decoded as soon as the blocks holding its
+// source bytes are present; the index lists those blocks for each block, so
+// the set of blocks a seek needs is the closure of the targets under that
+// relation, and a valid order is by increasing dependency level.  Target
+// blocks that the range covers whole are decoded straight into the caller's
+// output; every other block of the closure goes to a workspace slot, and the
+// partial first and last blocks are clipped out of their slots afterwards.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/aceseek.h"
+#include "common.h"
+
+using namespace ace;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+inline uint16_t h16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+inline uint32_t h32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+inline uint64_t h64(const uint8_t* p) { return (uint64_t)h32(p) | ((uint64_t)h32(p + 4) << 32); }
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(ACE_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct BlockInfo {
+  uint32_t n_seq, level, dep_off, dep_cnt;
+};
+
+struct ace_archive {
+  const uint8_t* d_arch = nullptr;
+  uint64_t len = 0, n = 0;
+  uint32_t B = 0, W = 0, ow = 0, nb = 0, depth = 0;
+  std::vector<BlockInfo> blk;
+  std::vector<uint32_t> deps;
+  // whole-archive plan: blocks by level, their token slots, level boundaries
+  std::vector<PlanEntry> all_plan;
+  std::vector<uint32_t> all_levels;
+  uint64_t all_seq = 0;
+  PlanEntry* all_plan_pinned = nullptr;
+  std::mutex pin_mu;
+  ~ace_archive() {
+    if (all_plan_pinned) (void)hipHostFree(all_plan_pinned);
+  }
+};
+
+extern "C" const char* ace_last_error(void) { return g_err.c_str(); }
+extern "C" void ace_internal_set_error(const char* msg) { g_err = msg; }
+
+// ---------------------------------------------------------------------------
+// open / validate
+// ---------------------------------------------------------------------------
+static int validate(const uint8_t* a, uint64_t len, ace_archive* A) {
+  if (len < kHdr) return fail(ACE_E_CORRUPT, "archive shorter than its 64-byte header");
+  if (h32(a) != kMagic) return fail(ACE_E_CORRUPT, "bad magic");
+  if (h16(a + 4) != 1) return fail(ACE_E_CORRUPT, "unsupported version %u", h16(a + 4));
+  A->B = h32(a + 8);
+  A->W = h16(a + 12);
+  A->ow = a[15];
+  A->n = h64(a + 16);
+  A->nb = h32(a + 24);
+  A->depth = h32(a + 28);
+  const uint32_t max_level = h32(a + 32), n_deps = h32(a + 36);
+  if (a[14] != kProbBits) return fail(ACE_E_CORRUPT, "probability bits %u (expected 12)", a[14]);
+  if (A->B < 1 || A->B > (1u << 24)) return fail(ACE_E_CORRUPT, "block size %u out of range", A->B);
+  if (A->W < 1 || A->W > 64) return fail(ACE_E_CORRUPT, "interleave %u out of range", A->W);
+  if (A->ow != 4 && A->ow != 8) return fail(ACE_E_CORRUPT, "offset width %u", A->ow);
+  if (A->ow == 4 && A->n > (1ull << 32)) return fail(ACE_E_CORRUPT, "4-byte offsets for more than 4 GiB");
+  const uint64_t nb = A->n ? (A->n - 1) / A->B + 1 : 0;
+  if (nb != A->nb) return fail(ACE_E_CORRUPT, "block count %u does not match ceil(N/B) = %llu", A->nb,
+                               (unsigned long long)nb);
+  if (h64(a + 40) != kHdr) return fail(ACE_E_CORRUPT, "block table must follow the header");
+  const uint64_t deps_at = kHdr + (uint64_t)kBlk * A->nb, pay_at = h64(a + 48);
+  if (deps_at + 4ull * n_deps > len || pay_at < deps_at + 4ull * n_deps || pay_at > len)
+    return fail(ACE_E_CORRUPT, "index does not fit the archive");
+  A->deps.resize(n_deps);
+  for (uint32_t i = 0; i < n_deps; i++) A->deps[i] = h32(a + deps_at + 4ull * i);
+  A->blk.resize(A->nb);
+  uint32_t max_lv_plus1 = 0;
+  for (uint32_t b = 0; b < A->nb; b++) {
+    const uint8_t* e = a + kHdr + (uint64_t)kBlk * b;
+    const uint64_t pay = h64(e);
+    const uint32_t plen = h32(e + 8);
+    BlockInfo& bi = A->blk[b];
+    bi.n_seq = h32(e + 12);
+    bi.level = h32(e + 16);
+    bi.dep_off = h32(e + 20);
+    bi.dep_cnt = h32(e + 24);
+    if (h32(e + 28) != 0) return fail(ACE_E_CORRUPT, "block %u: reserved field is not zero", b);
+    if (pay % 16 || pay < pay_at || pay + plen > len || plen < 3 * kSDesc)
+      return fail(ACE_E_CORRUPT, "block %u: payload outside the archive", b);
+    const uint64_t bs = (uint64_t)b * A->B;
+    const uint32_t blen = (uint32_t)std::min<uint64_t>(A->B, A->n - bs);
+    if (bi.n_seq == 0 || bi.n_seq > blen) return fail(ACE_E_CORRUPT, "block %u: %u sequences", b, bi.n_seq);
+    if ((uint64_t)bi.dep_off + bi.dep_cnt > n_deps)
+      return fail(ACE_E_CORRUPT, "block %u: dependency list outside the index", b);
+    uint32_t lv = 0;
+    for (uint32_t j = 0; j < bi.dep_cnt; j++) {
+      const uint32_t d = A->deps[bi.dep_off + j];
+      if (d >= b) return fail(ACE_E_CORRUPT, "block %u: dependency %u is not an earlier block", b, d);
+      if (j && d <= A->deps[bi.dep_off + j - 1])
+        return fail(ACE_E_CORRUPT, "block %u: dependencies not strictly ascending", b);
+      lv = std::max(lv, A->blk[d].level + 1);
+    }
+    if (lv != bi.level) return fail(ACE_E_CORRUPT, "block %u: level %u, dependencies give %u", b, bi.level, lv);
+    max_lv_plus1 = std::max(max_lv_plus1, lv + 1);
+    const uint32_t want[3] = {0, 4 * bi.n_seq, A->ow * bi.n_seq};
+    for (int t = 0; t < 3; t++) {
+      const uint8_t* d = a + pay + kSDesc * t;
+      const uint32_t mode = d[0], nsym = h32(d + 4), clen = h32(d + 8), off = h32(d + 12);
+      if (d[1] | d[2] | d[3]) return fail(ACE_E_CORRUPT, "block %u stream %d: padding not zero", b, t);
+      if (mode > 1) return fail(ACE_E_CORRUPT, "block %u stream %d: unknown mode %u", b, t, mode);
+      if (off % 4 || off < 3 * kSDesc || (uint64_t)off + clen > plen)
+        return fail(ACE_E_CORRUPT, "block %u stream %d: data outside the payload", b, t);
+      if (t == 0 ? nsym > blen : nsym != want[t])
+        return fail(ACE_E_CORRUPT, "block %u stream %d: %u symbols", b, t, nsym);
+      if (mode == 0 && clen != nsym) return fail(ACE_E_CORRUPT, "block %u stream %d: raw size mismatch", b, t);
+      if (mode == 1 && (nsym == 0 || clen < 36 + 4 * A->W))
+        return fail(ACE_E_CORRUPT, "block %u stream %d: rANS stream too short", b, t);
+    }
+  }
+  if (max_lv_plus1 != A->depth)
+    return fail(ACE_E_CORRUPT, "stored depth %u, levels give %u", A->depth, max_lv_plus1);
+  if (max_level && A->depth > max_level)
+    return fail(ACE_E_CORRUPT, "depth %u exceeds the stated level cap %u", A->depth, max_level);
+  A->len = len;
+  return ACE_OK;
+}
+
+// Level order of a set of blocks (counting sort, stable by block id).
+static void level_order(const ace_archive* A, const std::vector<uint32_t>& blocks,
+                        std::vector<uint32_t>& order, std::vector<uint32_t>& lstart) {
+  lstart.assign(A->depth + 1, 0);
+  for (uint32_t b : blocks) lstart[A->blk[b].level + 1]++;
+  for (uint32_t l = 0; l < A->depth; l++) lstart[l + 1] += lstart[l];
+  std::vector<uint32_t> pos(lstart.begin(), lstart.end() - 1);
+  order.resize(blocks.size());
+  for (uint32_t b : blocks) order[pos[A->blk[b].level]++] = b;
+}
+
+extern "C" int ace_archive_open(const uint8_t* h_arch, uint64_t len, const void* d_arch,
+                                ace_archive** out) {
+  if (!h_arch || !out) return fail(ACE_E_ARG, "null argument");
+  ace_archive* A = new (std::nothrow) ace_archive();
+  if (!A) return fail(ACE_E_NOMEM, "out of memory");
+  int rc = validate(h_arch, len, A);
+  if (rc) {
+    delete A;
+    return rc;
+  }
+  A->d_arch = static_cast<const uint8_t*>(d_arch);
+  std::vector<uint32_t> all(A->nb), order;
+  for (uint32_t b = 0; b < A->nb; b++) all[b] = b;
+  level_order(A, all, order, A->all_levels);
+  A->all_plan.resize(A->nb);
+  uint64_t seq = 0;
+  for (uint32_t i = 0; i < A->nb; i++) {
+    const uint32_t b = order[i];
+    A->all_plan[i] = PlanEntry{b, (uint32_t)seq, (uint64_t)b * A->B};
+    seq += A->blk[b].n_seq;
+  }
+  if (seq > 0xFFFFFFFFull) {
+    delete A;
+    return fail(ACE_E_CORRUPT, "more than 2^32 sequences");
+  }
+  A->all_seq = seq;
+  *out = A;
+  return ACE_OK;
+}
+
+extern "C" void ace_archive_close(ace_archive* a) { delete a; }
+
+extern "C" int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_t* block_size,
+                                uint32_t* n_blocks, uint32_t* depth) {
+  if (!a) return fail(ACE_E_ARG, "null archive");
+  if (n_total) *n_total = a->n;
+  if (block_size) *block_size = a->B;
+  if (n_blocks) *n_blocks = a->nb;
+  if (depth) *depth = a->depth;
+  return ACE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planning and workspace layout
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kWsHeader = 256;  // error word, work counter
+
+struct Layout {
+  uint64_t plan, loc, done, lit, lens, offs, slots, items, total;
+};
+
+Layout layout(const ace_archive* A, uint64_t n_plan, uint64_t n_seq, uint64_t n_slots,
+              uint64_t n_items) {
+  Layout L;
+  uint64_t o = kWsHeader;
+  L.plan = o;  o = align_up(o + sizeof(PlanEntry) * n_plan, 256);
+  L.loc = o;   o = align_up(o + 8ull * A->nb, 256);
+  L.done = o;  o = align_up(o + 4ull * A->nb, 256);
+  L.lit = o;   o = align_up(o + (uint64_t)A->B * n_plan, 256);
+  L.lens = o;  o = align_up(o + 4ull * n_seq, 256);
+  L.offs = o;  o = align_up(o + (uint64_t)A->ow * n_seq, 256);
+  L.slots = o; o = align_up(o + (uint64_t)A->B * n_slots, 256);
+  L.items = o; o = align_up(o + sizeof(CopyItem) * n_items, 256);
+  L.total = o;
+  return L;
+}
+
+struct Plan {
+  std::vector<PlanEntry> entries;  // level order
+  std::vector<uint32_t> lstart;    // level boundaries in entries
+  std::vector<CopyItem> items;
+  uint64_t n_seq = 0;
+  uint64_t n_slots = 0;
+  bool use_slots_for_all = false;
+};
+
+// Marks the closure of the marked targets (dependencies are always earlier
+// blocks, so one descending sweep from the highest target closes the set).
+void close_set(const ace_archive* A, std::vector<uint8_t>& need, uint32_t top,
+               std::vector<uint32_t>& blocks) {
+  for (uint32_t b = top + 1; b-- > 0;) {
+    if (!need[b]) continue;
+    blocks.push_back(b);
+    const BlockInfo& bi = A->blk[b];
+    for (uint32_t j = 0; j < bi.dep_cnt; j++) need[A->deps[bi.dep_off + j]] = 1;
+  }
+}
+
+// Closure of one range by a stack walk (touches only the closure).
+void close_range(const ace_archive* A, uint32_t t0, uint32_t t1, std::vector<uint32_t>& blocks) {
+  std::vector<uint32_t> stack;
+  std::vector<uint8_t> seen(A->nb, 0);
+  for (uint32_t b = t0; b <= t1; b++) {
+    seen[b] = 1;
+    stack.push_back(b);
+  }
+  while (!stack.empty()) {
+    uint32_t b = stack.back();
+    stack.pop_back();
+    blocks.push_back(b);
+    const BlockInfo& bi = A->blk[b];
+    for (uint32_t j = 0; j < bi.dep_cnt; j++) {
+      uint32_t d = A->deps[bi.dep_off + j];
+      if (!seen[d]) {
+        seen[d] = 1;
+        stack.push_back(d);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// execution
+// ---------------------------------------------------------------------------
+static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
+               const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
+               const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
+               hipStream_t s, bool entries_pinned) {
+  (void)entries_pinned;
+  DecodeArgs a{};
+  a.arch = A->d_arch;
+  a.plan = reinterpret_cast<const PlanEntry*>(ws + L.plan);
+  a.n_plan = (uint32_t)n_plan;
+  a.B = A->B;
+  a.W = A->W;
+  a.ow = A->ow;
+  a.n_blocks = A->nb;
+  a.n_total = A->n;
+  a.dst_base = dst_base;
+  a.loc = reinterpret_cast<uint64_t*>(ws + L.loc);
+  a.lit = ws + L.lit;
+  a.lens = ws + L.lens;
+  a.offs = ws + L.offs;
+  a.err = reinterpret_cast<uint32_t*>(ws);
+  a.ext_bytes = reinterpret_cast<unsigned long long*>(ws + 8);
+  a.queue = reinterpret_cast<uint32_t*>(ws + 4);
+  a.done = reinterpret_cast<uint32_t*>(ws + L.done);
+  a.epoch = 1;
+  a.spin_limit = 1u << 22;
+  if (n_plan) HIP_TRY(hipMemcpyAsync(ws + L.plan, entries, sizeof(PlanEntry) * n_plan,
+                                     hipMemcpyHostToDevice, s));
+  if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,
+                                      hipMemcpyHostToDevice, s));
+  const uint32_t mode = t ? t->mode : 0;
+  bool done = false;
+  if (mode == 0 && n_plan) {
+    HIP_TRY(launch_fill_u32(a.done, 0u, A->nb, s));
+    HIP_TRY(launch_fill_u32(a.queue, 0u, 1, s));
+    hipError_t e = launch_persistent(a, t ? t->grid_wgs : 0, s);
+    if (e == hipSuccess) done = true;
+    else if (e != hipErrorNotSupported) return fail(ACE_E_HIP, "persistent launch: %s", hipGetErrorString(e));
+    else (void)hipGetLastError();
+  }
+  if (!done && n_plan) {
+    HIP_TRY(launch_rans(a, s));
+    for (size_t l = 0; l + 1 < lstart.size(); l++)
+      HIP_TRY(launch_expand_level(a, lstart[l], lstart[l + 1], s));
+  }
+  if (n_items)
+    HIP_TRY(launch_copy(a, reinterpret_cast<const CopyItem*>(ws + L.items), (uint32_t)n_items, s));
+  return ACE_OK;
+}
+
+extern "C" int ace_workspace_bytes(const ace_archive* A, const ace_range* r, uint32_t n,
+                                   uint64_t* bytes) {
+  if (!A || !bytes || (n && !r)) return fail(ACE_E_ARG, "null argument");
+  if (n == 0) {
+    *bytes = layout(A, A->nb, A->all_seq, 0, 0).total;
+    return ACE_OK;
+  }
+  std::vector<uint8_t> need(A->nb, 0);
+  uint32_t top = 0;
+  uint64_t items = 0;
+  bool any = false;
+  for (uint32_t i = 0; i < n; i++) {
+    if (r[i].lo > r[i].hi) return fail(ACE_E_ARG, "range %u is inverted", i);
+    if (r[i].hi > A->n) return fail(ACE_E_RANGE, "range %u ends beyond %llu", i, (unsigned long long)A->n);
+    if (r[i].lo == r[i].hi) continue;
+    uint32_t t0 = (uint32_t)(r[i].lo / A->B), t1 = (uint32_t)((r[i].hi - 1) / A->B);
+    for (uint32_t b = t0; b <= t1; b++) need[b] = 1;
+    top = std::max(top, t1);
+    items += (r[i].hi - r[i].lo + 65535) / 65536 + 2;
+    any = true;
+  }
+  std::vector<uint32_t> blocks;
+  if (any) close_set(A, need, top, blocks);
+  uint64_t seq = 0;
+  for (uint32_t b : blocks) seq += A->blk[b].n_seq;
+  *bytes = layout(A, blocks.size(), seq, blocks.size(), items).total;
+  return ACE_OK;
+}
+
+extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out_cap, void* d_ws,
+                              uint64_t ws_cap, const ace_tuning* t, void* stream) {
+  if (!A || (!d_out && A->n) || !d_ws) return fail(ACE_E_ARG, "null argument");
+  if (out_cap < A->n) return fail(ACE_E_NOSPACE, "output needs %llu bytes", (unsigned long long)A->n);
+  Layout L = layout(A, A->nb, A->all_seq, 0, 0);
+  if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
+  if (A->nb == 0) return ACE_OK;
+  ace_archive* M = const_cast<ace_archive*>(A);
+  const PlanEntry* entries = A->all_plan.data();
+  {
+    std::lock_guard<std::mutex> g(M->pin_mu);
+    if (!M->all_plan_pinned) {
+      void* p = nullptr;
+      if (hipHostMalloc(&p, sizeof(PlanEntry) * A->nb, hipHostMallocDefault) == hipSuccess) {
+        memcpy(p, A->all_plan.data(), sizeof(PlanEntry) * A->nb);
+        M->all_plan_pinned = static_cast<PlanEntry*>(p);
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    if (M->all_plan_pinned) entries = M->all_plan_pinned;
+  }
+  return run(A, entries, A->nb, A->all_levels, nullptr, 0, L, static_cast<uint8_t*>(d_ws),
+             (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), true);
+}
+
+extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+                        uint64_t ws_cap, const ace_tuning* t, void* stream) {
+  if (!A) return fail(ACE_E_ARG, "null archive");
+  if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
+                           (unsigned long long)hi);
+  if (hi > A->n) return fail(ACE_E_RANGE, "range end %llu beyond %llu", (unsigned long long)hi,
+                             (unsigned long long)A->n);
+  if (lo == hi) return ACE_OK;
+  if (!d_out || !d_ws) return fail(ACE_E_ARG, "null argument");
+  const uint32_t t0 = (uint32_t)(lo / A->B), t1 = (uint32_t)((hi - 1) / A->B);
+  std::vector<uint32_t> blocks, order, lstart;
+  close_range(A, t0, t1, blocks);
+  level_order(A, blocks, order, lstart);
+  // locations: whole target blocks go straight to the output
+  std::vector<PlanEntry> entries(order.size());
+  std::vector<CopyItem> items;
+  uint64_t seq = 0, n_slots = 0;
+  std::vector<uint8_t> direct(order.size(), 0);
+  for (size_t i = 0; i < order.size(); i++) {
+    const uint32_t b = order[i];
+    const uint64_t bs = (uint64_t)b * A->B, be = std::min<uint64_t>(bs + A->B, A->n);
+    direct[i] = b >= t0 && b <= t1 && bs >= lo && be <= hi;
+    if (!direct[i]) n_slots++;
+    entries[i].block = b;
+    entries[i].seq_base = (uint32_t)seq;
+    seq += A->blk[b].n_seq;
+  }
+  for (uint32_t b : {t0, t1}) {
+    const uint64_t bs = (uint64_t)b * A->B, be = std::min<uint64_t>(bs + A->B, A->n);
+    if (bs >= lo && be <= hi) continue;
+    if (b == t1 && t1 == t0 && !items.empty()) continue;
+    const uint64_t s0 = std::max(lo, bs), s1 = std::min(hi, be);
+    items.push_back(CopyItem{s0, (uint64_t)(uintptr_t)d_out + (s0 - lo), (uint32_t)(s1 - s0), 0});
+  }
+  Layout L = layout(A, order.size(), seq, n_slots, items.size());
+  if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  uint64_t slot = 0;
+  for (size_t i = 0; i < order.size(); i++) {
+    const uint64_t bs = (uint64_t)order[i] * A->B;
+    entries[i].dst = direct[i] ? (uint64_t)(uintptr_t)d_out + (bs - lo)
+                               : (uint64_t)(uintptr_t)(ws + L.slots) + (slot++) * A->B;
+  }
+  return run(A, entries.data(), entries.size(), lstart, items.data(), items.size(), L, ws, 0, t,
+             static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t n, uint8_t* d_out,
+                              const uint64_t* out_off, void* d_ws, uint64_t ws_cap,
+                              const ace_tuning* t, void* stream) {
+  if (!A || (n && (!r || !out_off))) return fail(ACE_E_ARG, "null argument");
+  std::vector<uint8_t> need(A->nb, 0);
+  uint32_t top = 0;
+  bool any = false;
+  std::vector<CopyItem> items;
+  for (uint32_t i = 0; i < n; i++) {
+    if (r[i].lo > r[i].hi) return fail(ACE_E_ARG, "range %u is inverted", i);
+    if (r[i].hi > A->n) return fail(ACE_E_RANGE, "range %u ends beyond %llu", i, (unsigned long long)A->n);
+    if (r[i].lo == r[i].hi) continue;
+    if (!d_out || !d_ws) return fail(ACE_E_ARG, "null argument");
+    const uint32_t t0 = (uint32_t)(r[i].lo / A->B), t1 = (uint32_t)((r[i].hi - 1) / A->B);
+    for (uint32_t b = t0; b <= t1; b++) need[b] = 1;
+    top = std::max(top, t1);
+    any = true;
+    for (uint64_t s0 = r[i].lo; s0 < r[i].hi; s0 += 65536) {
+      const uint64_t s1 = std::min<uint64_t>(s0 + 65536, r[i].hi);
+      items.push_back(CopyItem{s0, (uint64_t)(uintptr_t)d_out + out_off[i] + (s0 - r[i].lo),
+                               (uint32_t)(s1 - s0), 0});
+    }
+  }
+  if (!any) return ACE_OK;
+  std::vector<uint32_t> blocks, order, lstart;
+  close_set(A, need, top, blocks);
+  level_order(A, blocks, order, lstart);
+  uint64_t seq = 0;
+  for (uint32_t b : order) seq += A->blk[b].n_seq;
+  Layout L = layout(A, order.size(), seq, order.size(), items.size());
+  if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  std::vector<PlanEntry> entries(order.size());
+  uint64_t sq = 0;
+  for (size_t i = 0; i < order.size(); i++) {
+    entries[i] = PlanEntry{order[i], (uint32_t)sq, (uint64_t)(uintptr_t)(ws + L.slots) + i * (uint64_t)A->B};
+    sq += A->blk[order[i]].n_seq;
+  }
+  return run(A, entries.data(), entries.size(), lstart, items.data(), items.size(), L, ws, 0, t,
+             static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" int ace_check(void* d_ws, void* stream) {
+  if (!d_ws) return fail(ACE_E_ARG, "null workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  uint32_t err = 0, zero = 0;
+  HIP_TRY(hipMemcpy(&err, d_ws, 4, hipMemcpyDeviceToHost));
+  if (err) HIP_TRY(hipMemcpy(d_ws, &zero, 4, hipMemcpyHostToDevice));
+  if (err & kErrTimeout) return fail(ACE_E_TIMEOUT, "a dependency wait on the device expired");
+  if (err & kErrCorrupt) return fail(ACE_E_CORRUPT, "a token stream broke a format rule");
+  return ACE_OK;
+}
+
+extern "C" int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_bytes) {
+  if (!d_ws || !ext_src_bytes) return fail(ACE_E_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  uint64_t v = 0, zero = 0;
+  HIP_TRY(hipMemcpy(&v, static_cast<uint8_t*>(d_ws) + 8, 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d_ws) + 8, &zero, 8, hipMemcpyHostToDevice));
+  *ext_src_bytes = v;
+  return ACE_OK;
+}

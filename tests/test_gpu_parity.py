@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for
+bit, plus the paper's three-phase seek check (Section 5).
+
+Sizes are chosen so the oracle finishes in seconds while the archives still
+span many blocks and end in a short (ragged) last block."""
+import numpy as np
+import pytest
+
+import gen
+from harness import three_phase
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MODES = [dict(mode=0), dict(mode=1)]  # persistent, one launch per level
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ace():
+    from paper_2606_24531_amd import aceseek
+    aceseek.lib()
+    return aceseek
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().tobytes()
+
+
+CASES = [
+    # profile, n, B, W, cap, flags, min_match
+    ("genome", 1 << 20, 16384, 32, 0, 0, 20),        # the small workload: 64 blocks
+    ("genome", 1_000_003, 16384, 32, 8, 0, 20),
+    ("fastq", 2_000_001, 16384, 32, 16, 0, 20),
+    ("fastq", 1_500_000, 4096, 64, 0, 0, 20),
+    ("text", 1_234_567, 16384, 32, 8, 0, 16),
+    ("text", 700_000, 65536, 32, 0, 0, 16),
+    ("random", 300_001, 16384, 32, 0, 0, 16),
+    ("mixed", 2_500_000, 16384, 32, 8, 0, 16),
+    ("mixed", 1_000_000, 65536, 64, 0, 1, 16),        # every stream rANS
+    ("fastq", 600_000, 16384, 1, 4, 1, 20),           # one lane per stream
+    ("genome", 500_000, 1000, 7, 0, 2, 20),           # non-power-of-two blocks, raw
+    ("text", 100_000, 37, 3, 0, 0, 4),                # tiny blocks, thousands of them
+]
+
+
+def _case_id(c):
+    return "%s-n%d-B%d-W%d-cap%d-f%d" % c[:6]
+
+
+@pytest.fixture(scope="module")
+def archives(orc):
+    out = {}
+    for c in CASES:
+        name, n, B, W, cap, flags, mm = c
+        x = gen.by_name(name, n, 31)
+        a = orc.encode(x, block_size=B, interleave=W, min_match=mm, hash_len=min(mm, 16),
+                       max_level=cap, flags=flags)
+        out[c] = (x, a, orc.decode(a))
+    return out
+
+
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+@pytest.mark.parametrize("tuning", MODES, ids=["persistent", "levels"])
+def test_decode_all_matches_oracle(dev, ace, archives, case, tuning):
+    x, a, ref = archives[case]
+    assert ref == x
+    arc = ace.Archive(a, device=dev)
+    out = arc.decode_all(tuning=tuning)
+    arc.check()
+    got = _host(out)
+    assert len(got) == len(ref)
+    if got != ref:
+        bad = np.nonzero(np.frombuffer(got, np.uint8) != np.frombuffer(ref, np.uint8))[0]
+        pytest.fail("first mismatch at %d (block %d), %d bytes differ" %
+                    (bad[0], bad[0] // case[2], bad.size))
+
+
+def test_small_workload_three_phase_every_block(dev, ace, orc):
+    """Every block of the 1 MiB genome archive sought singly: the output
+    buffer holds a sentinel before, the block after, and nothing else moved.
+    The device holds only the archive, never the original bytes."""
+    x = gen.genome(1 << 20, 1)
+    a = orc.encode(x, block_size=16384, interleave=32, min_match=20, hash_len=20, max_chain=32)
+    arc = ace.Archive(a, device=dev)
+    B = 16384
+    for tuning in MODES:
+        for b in range(64):
+            def run(buf, lo, hi):
+                d = torch.from_numpy(buf).to(dev)
+                arc.seek(lo, hi, out=d[lo:], tuning=tuning)
+                arc.check()
+                return d.cpu().numpy()
+            three_phase(run, x, b * B, (b + 1) * B, seed=b, fnv=orc.fnv1a64)
+
+
+def test_seek_ranges_match_oracle(dev, ace, archives, orc):
+    rng = np.random.default_rng(5)
+    for c in CASES[:8]:
+        x, a, _ = archives[c]
+        arc = ace.Archive(a, device=dev)
+        n, B = len(x), c[2]
+        ranges = [(0, n), (0, 1), (n - 1, n), (B - 1, B + 1), (B, 2 * B), (n // 2, n // 2)]
+        for _ in range(25):
+            lo = int(rng.integers(0, n))
+            hi = int(min(n, lo + int(np.exp(rng.uniform(0, np.log(4 * B + 1))))))
+            ranges.append((lo, hi))
+        for lo, hi in ranges:
+            got = _host(arc.seek(lo, hi, tuning=MODES[int(rng.integers(2))]))
+            arc.check()
+            assert got == x[lo:hi], (c[0], lo, hi)
+
+
+def test_seek_batch_alone_equals_mix(dev, ace, archives):
+    """Each request's bytes are the same decoded alone and inside a batch."""
+    c = CASES[7]
+    x, a, _ = archives[c]
+    arc = ace.Archive(a, device=dev)
+    lo, hi = gen.seek_requests(len(x), 300, 9, max_len=200_000)
+    out = arc.seek_batch((lo, hi))
+    arc.check()
+    got = _host(out)
+    pos = 0
+    for i in range(len(lo)):
+        l, h = int(lo[i]), int(hi[i])
+        assert got[pos:pos + h - l] == x[l:h], i
+        if i % 30 == 0:
+            solo = _host(arc.seek(l, h))
+            assert solo == got[pos:pos + h - l]
+        pos += h - l
+    # explicit output offsets with gaps stay untouched between requests
+    offs = np.arange(len(lo), dtype=np.uint64) * np.uint64(200_016)
+    buf = torch.full((int(offs[-1]) + 200_016,), 0xA5, dtype=torch.uint8, device=dev)
+    arc.seek_batch((lo, hi), out=buf, out_offsets=offs)
+    arc.check()
+    hb = _host(buf)
+    for i in range(len(lo)):
+        l, h, o = int(lo[i]), int(hi[i]), int(offs[i])
+        assert hb[o:o + h - l] == x[l:h]
+        assert hb[o + h - l:o + 200_016] == b"\xa5" * (200_016 - (h - l))
+
+
+def test_degenerate_inputs(dev, ace, orc):
+    # all-zero input: a chain of dependencies through every block
+    x = bytes(64 * 300)
+    a = orc.encode(x, block_size=64, interleave=4, min_match=4, hash_len=4, max_chain=4)
+    arc = ace.Archive(a, device=dev)
+    assert arc.depth == 300
+    for t in MODES:
+        assert _host(arc.decode_all(tuning=t)) == x
+        arc.check()
+    assert _host(arc.seek(64 * 299 + 3, 64 * 300)) == x[64 * 299 + 3:]
+    # a single byte, and an empty archive
+    for x in (b"Q", b""):
+        a = orc.encode(x, block_size=16, interleave=2, min_match=4, hash_len=4)
+        arc = ace.Archive(a, device=dev)
+        assert _host(arc.decode_all()) == x
+        arc.check()

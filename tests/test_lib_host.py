@@ -1,0 +1,117 @@
+"""CPU tests of libaceseek's host side: exported symbols, the host encoder
+(byte-identical to the oracle's encoder under the same policy), archive
+validation at open, and argument errors that are reported before any device
+work.  No kernel runs here."""
+import ctypes as C
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_24531_amd import aceseek
+    return aceseek
+
+
+def test_every_declared_symbol_is_exported(lib):
+    hdr = open(os.path.join(ROOT, "include", "aceseek.h")).read()
+    declared = set(re.findall(r"\b(ace_[a-z_]+)\s*\(", hdr))
+    assert declared == set(lib.EXPORTS)
+    L = C.CDLL(lib.library_path())
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("name,mm", [("genome", 20), ("fastq", 20), ("text", 16), ("random", 16),
+                                     ("mixed", 16)])
+@pytest.mark.parametrize("B,W,cap,flags", [(16384, 32, 0, 0), (16384, 32, 8, 0), (4096, 64, 3, 1),
+                                           (1000, 7, 0, 2), (65536, 1, 16, 0)])
+def test_encoder_matches_oracle_encoder(orc, lib, name, mm, B, W, cap, flags):
+    x = gen.by_name(name, 400_000, 21)
+    kw = dict(block_size=B, interleave=W, min_match=mm, hash_len=mm, max_chain=32,
+              max_level=cap, flags=flags)
+    a = lib.encode(x, **kw)
+    assert a == orc.encode(x, **kw)
+    assert orc.decode(a) == x
+
+
+def test_encoder_threads_do_not_change_output(lib):
+    x = gen.fastq(1 << 21, 4)
+    outs = {lib.encode(x, max_level=8, n_threads=t) for t in (1, 2, 7)}
+    assert len(outs) == 1
+
+
+def test_encoder_edge_sizes(orc, lib):
+    for n in (0, 1, 2, 19, 20, 21, 4095, 4096, 4097):
+        x = gen.text(n, 1)
+        a = lib.encode(x, block_size=4096, interleave=32, min_match=8, hash_len=8)
+        assert orc.decode(a) == x
+
+
+def _open(lib, a: bytes):
+    L = lib.lib()
+    h = C.c_void_p()
+    buf = np.frombuffer(a, dtype=np.uint8) if a else np.zeros(1, dtype=np.uint8)
+    rc = L.ace_archive_open(buf.ctypes.data_as(C.c_void_p), len(a), None, C.byref(h))
+    return rc, h
+
+
+def test_open_validates_index(lib):
+    x = gen.genome(1 << 18, 3)
+    a = lib.encode(x, block_size=4096, interleave=32, flags=2)
+    rc, h = _open(lib, a)
+    assert rc == 0
+    n, B, nb, depth = C.c_uint64(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+    assert lib.lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)) == 0
+    assert (n.value, B.value, nb.value) == (len(x), 4096, 64)
+    lib.lib().ace_archive_close(h)
+
+    def patched(at, fmt, v):
+        b = bytearray(a)
+        struct.pack_into(fmt, b, at, v)
+        return bytes(b)
+
+    bad = {
+        "magic": patched(0, "<I", 1),
+        "version": patched(4, "<H", 2),
+        "interleave": patched(12, "<H", 65),
+        "prob bits": patched(14, "<B", 13),
+        "block count": patched(24, "<I", 65),
+        "depth": patched(28, "<I", 99),
+        "level": patched(64 + 32 * 63 + 16, "<I", 77),
+        "reserved": patched(64 + 32 * 5 + 28, "<I", 1),
+        "n_seq zero": patched(64 + 32 * 5 + 12, "<I", 0),
+        "dep list": patched(64 + 32 * 63 + 20, "<I", 0xFFFFFF),
+        "truncated": a[:len(a) - 1],
+        "short": a[:40],
+    }
+    for name, b in bad.items():
+        rc, h = _open(lib, b)
+        assert rc == lib.E_CORRUPT, name
+
+
+def test_argument_errors_before_device_work(lib):
+    x = gen.text(100_000, 2)
+    a = lib.encode(x, block_size=4096, interleave=8, min_match=8, hash_len=8)
+    rc, h = _open(lib, a)
+    assert rc == 0
+    L = lib.lib()
+    dummy = C.c_void_p(0x1000)
+    assert L.ace_seek(h, 10, 100_001, dummy, dummy, 1 << 30, None, None) == lib.E_RANGE
+    assert L.ace_seek(h, 11, 10, dummy, dummy, 1 << 30, None, None) == lib.E_ARG
+    assert L.ace_seek(h, 500, 500, None, None, 0, None, None) == 0  # empty: no launch
+    assert L.ace_decode_all(h, dummy, 10, dummy, 1 << 30, None, None) == lib.E_NOSPACE
+    ws = C.c_uint64()
+    assert L.ace_workspace_bytes(h, None, 0, C.byref(ws)) == 0
+    assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value - 1, None, None) == lib.E_NOSPACE
+    r = np.array([0, 100_001], dtype=np.uint64)
+    assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), 1, C.byref(ws)) == lib.E_RANGE
+    L.ace_archive_close(h)
