@@ -50,7 +50,7 @@ struct DecodeArgs {
   uint32_t* queue;      // work counter
   uint32_t* done;       // per-block completion epochs
   uint32_t epoch;
-  uint32_t spin_limit;  // bounded wait (iterations) before flagging a timeout
+  uint64_t wait_ticks;  // bound of one dependency wait, in 100 MHz clock ticks
 };
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.

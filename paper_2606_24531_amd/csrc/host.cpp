@@ -311,7 +311,7 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.queue = reinterpret_cast<uint32_t*>(ws + 4);
   a.done = reinterpret_cast<uint32_t*>(ws + L.done);
   a.epoch = 1;
-  a.spin_limit = 1u << 22;
+  a.wait_ticks = 10000000ull;  // 100 ms
   if (n_plan) HIP_TRY(hipMemcpyAsync(ws + L.plan, entries, sizeof(PlanEntry) * n_plan,
                                      hipMemcpyHostToDevice, s));
   if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,

@@ -29,10 +29,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
 #pragma unroll
@@ -54,30 +50,35 @@ __device__ __forceinline__ void flag(uint32_t* err, uint32_t bit) { atomicOr(err
 // ---------------------------------------------------------------------------
 // Entropy layer: one wavefront decodes one rANS stream.
 //
-// LDS: a 4096-entry slot table (entry = symbol | (f-1) << 8 | (slot-cum) << 20)
-// and a 4 KiB ring of renormalisation words refilled 1 KiB at a time from a
-// register prefetch, so the decode loop never waits on HBM latency.  Lane j
-// owns state j; each step decodes symbols t*W .. t*W+W-1, and the lanes that
-// renormalise take consecutive words in lane order: word index = running base
-// + mbcnt(ballot(need)).
+// LDS holds the stream's 12-bit table as a 4096-byte slot -> symbol map plus
+// one packed word per symbol ((f-1) << 16 | cum), and a 4 KiB ring of
+// renormalisation words refilled 1 KiB at a time from a register prefetch,
+// so the decode loop never waits on HBM latency.  Lane j owns state j; each
+// step decodes symbols t*W .. t*W+W-1, and the lanes that renormalise take
+// consecutive words in lane order: word = running position +
+// mbcnt(ballot(need)).  The loop body is branch-free apart from the
+// wave-uniform ring refill.
 // ---------------------------------------------------------------------------
 struct RansSmem {
-  uint32_t lut[4096];
-  uint4 ring[256];            // 4 chunks x 64 lanes x 16 B
-  uint32_t pk[256];           // per present symbol (by rank): s | (f-1)<<8 | cum<<20
+  uint8_t sym[4096];              // slot -> symbol
+  uint4 ring[256];                // 4 chunks x 64 lanes x 16 B
+  uint32_t fc[256];               // symbol -> (f-1) << 16 | cum
+  uint8_t by_rank[256];           // k-th present symbol
   unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
 };
 
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Returns false (wave-uniform) when the stream breaks a format rule.
-__device__ bool rans_decode_wave(const uint8_t* src, uint32_t clen, uint32_t n, uint32_t W,
+__device__ __forceinline__ bool rans_decode_wave(const uint8_t* src, uint32_t clen, uint32_t n, uint32_t W,
                                  uint8_t* dst, RansSmem& sm, uint32_t lane) {
   // ---- frequency table: 32-byte presence bitmap, then f-1 per present symbol
   if (clen < 32) return false;
-  uint32_t nib = ((uint32_t)src[lane >> 1] >> ((lane & 1) * 4)) & 0xFu;
-  uint32_t cnt = __popc(nib);
-  uint32_t before = wave_incl_sum(cnt, lane) - cnt;
-  uint32_t present = wave_total(cnt);
-  uint32_t tsz = (32 + 2 * present + 3) & ~3u;
+  const uint32_t nib = ((uint32_t)src[lane >> 1] >> ((lane & 1) * 4)) & 0xFu;
+  const uint32_t cnt = __popc(nib);
+  const uint32_t before = wave_incl_sum(cnt, lane) - cnt;
+  const uint32_t present = uniform(wave_total(cnt));
+  const uint32_t tsz = (32 + 2 * present + 3) & ~3u;
   if (present == 0 || tsz + 4 * W > clen || ((clen - tsz - 4 * W) & 1)) return false;
   uint32_t f[4], mysum = 0, k = before;
 #pragma unroll
@@ -86,42 +87,47 @@ __device__ bool rans_decode_wave(const uint8_t* src, uint32_t clen, uint32_t n, 
     mysum += f[j];
   }
   uint32_t cum = wave_incl_sum(mysum, lane) - mysum;
-  if (wave_total(mysum) != kM) return false;
+  if (uniform(wave_total(mysum)) != kM) return false;
   sm.starts[lane] = 0ull;
   wave_sync();
   k = before;
 #pragma unroll
   for (int j = 0; j < 4; j++) {
+    const uint32_t s = 4 * lane + j;
+    sm.fc[s] = f[j] ? ((f[j] - 1) << 16) | cum : 0u;
     if (f[j]) {
-      sm.pk[k++] = (4 * lane + j) | ((f[j] - 1) << 8) | (cum << 20);
+      sm.by_rank[k++] = (uint8_t)s;
       atomicOr(&sm.starts[cum >> 6], 1ull << (cum & 63));
     }
     cum += f[j];
   }
   wave_sync();
-  // ---- slot table: lane l fills slots 64l .. 64l+63.  The symbol of slot t
-  // is the one of rank (starts at or before t) - 1; the visiting order is
-  // rotated per lane so that the 64 lanes write 64 different banks.
+  // ---- slot -> symbol: lane l fills slots 64l .. 64l+63 in order, the rank
+  // of the covering symbol advancing at every interval start
   {
-    unsigned long long w = sm.starts[lane];
-    uint32_t pc = __popcll(w);
-    uint32_t rank0 = wave_incl_sum(pc, lane) - pc;
-    for (uint32_t t = 0; t < 64; t++) {
-      uint32_t tt = t ^ lane;
-      uint32_t rank = rank0 + __popcll(w & (~0ull >> (63 - tt))) - 1;
-      uint32_t e = sm.pk[rank];
-      uint32_t slot = 64 * lane + tt;
-      sm.lut[slot] = (e & 0xFFFFFu) | ((slot - (e >> 20)) << 20);
+    const unsigned long long w = sm.starts[lane];
+    const uint32_t pc = __popcll(w);
+    int rank = (int)(wave_incl_sum(pc, lane) - pc) - 1;
+    uint32_t* out32 = reinterpret_cast<uint32_t*>(sm.sym) + 16 * lane;
+    uint32_t cur = rank >= 0 ? sm.by_rank[rank] : 0u;
+    for (uint32_t q = 0; q < 16; q++) {
+      uint32_t word = 0;
+#pragma unroll
+      for (uint32_t b = 0; b < 4; b++) {
+        if ((w >> (4 * q + b)) & 1) cur = sm.by_rank[++rank];
+        word |= cur << (8 * b);
+      }
+      out32[q] = word;
     }
   }
   // ---- states and word ring
   const uint8_t* wsrc = src + tsz + 4 * W;
-  uint32_t nwords = (clen - tsz - 4 * W) >> 1;
+  const uint32_t nwords = (clen - tsz - 4 * W) >> 1;
   uint32_t x = lane < W ? ld32(src + tsz + 4 * lane) : kL;
   if (__ballot(lane < W && x < kL)) return false;
   const uintptr_t a0 = (uintptr_t)wsrc & ~(uintptr_t)15;
-  const uint32_t hw = (uint32_t)((uintptr_t)wsrc - a0) >> 1;  // word 0's position in chunk 0
-  const uint32_t nchunks = (2 * (hw + nwords) + 1023) >> 10;
+  const uint32_t hw = uniform((uint32_t)((uintptr_t)wsrc - a0) >> 1);  // word 0 in chunk 0
+  const uint32_t nchunks = uniform((2 * (hw + nwords) + 1023) >> 10);
   const uint4* gch = reinterpret_cast<const uint4*>(a0);
   uint32_t committed = 0;
   for (; committed < 3 && committed < nchunks; committed++)
@@ -130,33 +136,36 @@ __device__ bool rans_decode_wave(const uint8_t* src, uint32_t clen, uint32_t n, 
   if (committed < nchunks) pf = gch[committed * 64 + lane];
   wave_sync();
   const uint16_t* ring16 = reinterpret_cast<const uint16_t*>(sm.ring);
-  uint32_t wpos = 0;
-  bool over = false;
-  const uint32_t nsteps = (n + W - 1) / W;
+  uint32_t rp = hw;  // ring position (in words) of the next unread word
+  const bool lane_on = lane < W;
+  const uint32_t nsteps = uniform((n + W - 1) / W);
+  uint32_t i = lane;
   for (uint32_t t = 0; t < nsteps; t++) {
-    if (2 * (hw + wpos + 64) > committed * 1024 && committed < nchunks) {
+    if (rp + 64 > committed * 512 && committed < nchunks) {  // wave-uniform
       sm.ring[(committed & 3) * 64 + lane] = pf;
       committed++;
       if (committed < nchunks) pf = gch[committed * 64 + lane];
       wave_sync();
     }
-    uint32_t i = t * W + lane;
-    bool act = lane < W && i < n;
-    uint32_t e = sm.lut[x & (kM - 1)];
-    uint32_t xn = (((e >> 8) & 0xFFFu) + 1) * (x >> kProbBits) + (e >> 20);
-    bool need = act && xn < kL;
-    uint64_t m = __ballot(need);
-    if (need) {
-      uint32_t kk = wpos + mbcnt64(m);
-      over |= kk >= nwords;
-      x = (xn << 16) | ring16[(hw + kk) & 2047];
-    } else if (act) {
-      x = xn;
-    }
-    wpos += __popcll(m);
-    if (act) dst[i] = (uint8_t)e;
+    const bool act = lane_on && i < n;
+    const uint32_t slot = x & (kM - 1);
+    const uint32_t s = sm.sym[slot];
+    const uint32_t e = sm.fc[s];
+    const uint32_t xs = x >> kProbBits;
+    const uint32_t xn = __umul24(e >> 16, xs) + xs + slot - (e & 0xFFFu);
+    const bool need = act && xn < kL;
+    const uint64_t m = __ballot(need);
+    const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, rp));
+    uint32_t wd = ring16[pos & 2047];
+    __asm__ volatile("" : "+v"(wd));  // read for every lane: keeps the update branch-free
+    const uint32_t xa = act ? xn : x;
+    x = need ? ((xn << 16) | wd) : xa;
+    rp += (uint32_t)__popcll(m);
+    if (act) dst[i] = (uint8_t)s;
+    i += W;
   }
-  bool bad = over || wpos != nwords || (lane < W && x != kL);
+  const bool bad = rp - hw != nwords || (lane_on && x != kL);
   return __ballot(bad) == 0;
 }
 
@@ -184,29 +193,35 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Match layer: expansion of one block by a 256-thread workgroup.
+// Match layer: expansion of one block by a workgroup of kTile threads.
 //
-// Sequences are taken 256 at a time (one per thread); a workgroup scan of
+// Sequences are taken kTile at a time (one per thread).  A workgroup scan of
 // L_k + M_k and L_k gives every sequence its block-relative start and its
-// first literal.  Then every output byte of the tile is produced by its own
-// thread: the sequence holding it is found by binary search; a literal is
-// read from the decoded LIT stream; a match byte i of sequence k reads
-// absolute position O_k + (i mod (dst_k - O_k)) (overlapping matches repeat
-// with that period), which lies before the match.  A source in an earlier
-// block is read through the location table; one in an earlier tile of this
-// block is already written; one inside this tile is followed further (to a
-// literal, an earlier tile or an earlier block) -- each step moves strictly
-// backwards, so the walk ends.
+// first literal, and each thread classifies its sequence's source once: a
+// match byte i of sequence k reads absolute position O_k + (i mod d_k), with
+// d_k = (match start) - O_k, so overlapping matches repeat with that period
+// and every source lies before the match.  When all of a match's source
+// bytes sit in one earlier block (found through the location table) or in an
+// earlier tile of this block, a single base address serves every byte.
+// Then every thread produces 16 contiguous output bytes at a time: one binary
+// search for the first byte's sequence, then a forward walk; literal and
+// match bytes each cost one address and one byte load, and a whole aligned
+// chunk is written as one 16-byte store.  Sources that span blocks, or lie
+// inside the tile being produced, take the slow path: follow the source back
+// (to a literal, an earlier tile or an earlier block) -- each step moves
+// strictly backwards, so the walk ends.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kPoison = 0x80000000u;
+constexpr uint32_t kPoison = 1u, kSlow = 2u;
 
 template <uint32_t kTile>
 struct ExpandSmem {
-  uint32_t dst[kTile];  // block-relative start of the sequence
-  uint32_t L[kTile];
-  uint32_t M[kTile];    // bit 31: poisoned (a format rule failed)
-  uint32_t lit[kTile];  // index of the first literal
+  uint32_t dst[kTile];   // block-relative start of the sequence
+  uint32_t lm[kTile];    // L | M << 16
+  uint32_t dist[kTile];  // match start - O
+  uint32_t flags[kTile]; // kPoison, kSlow
   uint64_t O[kTile];
+  uint64_t lit[kTile];   // address of the sequence's first literal
+  uint64_t mbase[kTile]; // address of absolute position 0 for this match's source
   uint32_t scan[8];
 };
 
@@ -265,10 +280,42 @@ __device__ __forceinline__ bool dep_listed(const uint32_t* deps, uint32_t cnt, u
   return false;
 }
 
-// Expands plan entry i with kTile threads.  Sources in earlier blocks must be
-// complete and visible.
+struct BlockCtx {
+  uint64_t bs;       // absolute start of the block
+  uint32_t blen, n_lit, d0, cnt;
+  uint8_t* out;      // the block's first byte
+  bool ext_ok;
+};
+
+// Slow path: the byte at block-relative p, following sources back.
 template <uint32_t kTile>
-__device__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>& sm) {
+__device__ uint8_t resolve_slow(const DecodeArgs& a, const ExpandSmem<kTile>& sm, const BlockCtx& c,
+                                uint32_t p, uint32_t& n_ext) {
+  for (;;) {
+    const uint32_t s = find_seq(sm.dst, c.cnt, p);
+    if (sm.flags[s] & kPoison) return 0;
+    const uint32_t r = p - sm.dst[s];
+    const uint32_t Ls = sm.lm[s] & 0xFFFFu;
+    if (r < Ls) return *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
+    const uint32_t ii = r - Ls, d = sm.dist[s];
+    const uint64_t src = sm.O[s] + (ii < d ? ii : ii % d);
+    if (src < c.bs) {
+      if (!c.ext_ok) return 0;  // a dependency never published: read nothing
+      const uint64_t blk = src / a.B;
+      n_ext++;
+      return reinterpret_cast<const uint8_t*>(a.loc[blk])[src - blk * a.B];
+    }
+    const uint32_t q = (uint32_t)(src - c.bs);
+    if (q < c.d0) return c.out[q];
+    p = q;
+  }
+}
+
+// Expands plan entry i.  Sources in earlier blocks must be complete and
+// visible (unless ext_ok is false, after a timed-out wait).
+template <uint32_t kTile>
+__device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>& sm,
+                                             bool ext_ok = true) {
   const uint32_t tid = threadIdx.x;
   const PlanEntry pe = a.plan[i];
   const uint32_t b = pe.block;
@@ -276,13 +323,16 @@ __device__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>&
   const uint64_t pay = ld64(be);
   const uint32_t n_seq = ld32(be + 12), dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
   const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
-  const uint32_t n_lit = ld32(a.arch + pay + 4);
-  const uint64_t bs = (uint64_t)b * a.B;
-  const uint32_t blen = (uint32_t)((a.n_total - bs) < a.B ? (a.n_total - bs) : a.B);
-  uint8_t* out = reinterpret_cast<uint8_t*>(a.dst_base + pe.dst);
+  BlockCtx c;
+  c.n_lit = ld32(a.arch + pay + 4);
+  c.bs = (uint64_t)b * a.B;
+  c.blen = (uint32_t)((a.n_total - c.bs) < a.B ? (a.n_total - c.bs) : a.B);
+  c.out = reinterpret_cast<uint8_t*>(a.dst_base + pe.dst);
+  c.ext_ok = ext_ok;
   const uint8_t* lit = a.lit + (uint64_t)i * a.B;
   const uint8_t* lens = a.lens + 4ull * pe.seq_base;
   const uint8_t* offs = a.offs + (uint64_t)a.ow * pe.seq_base;
+  const bool aligned = (((uintptr_t)c.out) & 15) == 0;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kTile) {
@@ -291,7 +341,7 @@ __device__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>&
     uint32_t L = 0, M = 0;
     uint64_t O = 0;
     if (valid) {
-      uint32_t lm = ld32(lens + 4ull * k);
+      const uint32_t lm = ld32(lens + 4ull * k);
       L = lm & 0xFFFFu;
       M = lm >> 16;
       O = a.ow == 4 ? (uint64_t)ld32(offs + 4ull * k) : ld64(offs + 8ull * k);
@@ -300,84 +350,105 @@ __device__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>&
     wg_scan2<kTile>(L + M, L, ip, il, tp, tl, sm.scan);
     const uint32_t dst = carry_pos + ip - (L + M);
     const uint32_t litk = carry_lit + il - L;
-    uint32_t mflag = M;
+    const uint32_t d0 = carry_pos;
+    uint32_t fl = 0, dist = 0;
+    uint64_t mbase = 0;
     if (valid) {
-      const uint64_t mabs = bs + dst + L;
-      bool poison = (uint64_t)dst + L + M > blen || (uint64_t)litk + L > n_lit;
-      if (M) {
+      const uint64_t mabs = c.bs + dst + L;
+      if ((uint64_t)dst + L + M > c.blen || (uint64_t)litk + L > c.n_lit) fl = kPoison;
+      if (M && !fl) {
         if (O >= mabs) {
-          poison = true;
-        } else if (O < bs) {
-          // every earlier block the source touches must be a listed dependency
-          uint64_t end = O + M < bs ? O + M : bs;
-          for (uint64_t c = O / a.B; c * a.B < end; c++)
-            if (!dep_listed(deps, dep_cnt, (uint32_t)c)) {
-              poison = true;
-              break;
+          fl = kPoison;
+        } else {
+          dist = (uint32_t)((mabs - O) < 0xFFFFFFFFull ? (mabs - O) : 0xFFFFFFFFull);
+          const uint64_t src_hi = O + (M < dist ? M : dist);  // bytes actually read
+          if (O < c.bs) {
+            // every earlier block the source touches must be a listed dependency
+            const uint64_t end = src_hi < c.bs ? src_hi : c.bs;
+            for (uint64_t blk = O / a.B; blk * a.B < end; blk++)
+              if (!dep_listed(deps, dep_cnt, (uint32_t)blk)) {
+                fl = kPoison;
+                break;
+              }
+          }
+          if (!fl) {
+            const uint64_t b0 = O / a.B, b1 = (src_hi - 1) / a.B;
+            if (src_hi <= c.bs && b0 == b1 && ext_ok) {
+              mbase = a.loc[b0] - b0 * a.B;  // one earlier block
+              n_ext += M;
+            } else if (O >= c.bs && src_hi - c.bs <= d0) {
+              mbase = (uint64_t)(uintptr_t)c.out - c.bs;  // an earlier tile of this block
+            } else {
+              fl = kSlow;
             }
+          }
         }
-      } else if (O != 0) {
+      } else if (!M && O != 0) {
         bad = true;
       }
-      if (poison) {
-        bad = true;
-        mflag |= kPoison;
-      }
+      if (fl & kPoison) bad = true;
     }
     sm.dst[tid] = dst;
-    sm.L[tid] = L;
-    sm.M[tid] = mflag;
-    sm.lit[tid] = litk;
+    sm.lm[tid] = L | (M << 16);
+    sm.dist[tid] = dist;
+    sm.flags[tid] = fl;
     sm.O[tid] = O;
+    sm.lit[tid] = (uint64_t)(uintptr_t)lit + litk;
+    sm.mbase[tid] = mbase;
     __syncthreads();
-    const uint32_t cnt = (n_seq - t0) < kTile ? (n_seq - t0) : kTile;
-    const uint32_t d0 = carry_pos;
+    c.d0 = d0;
+    c.cnt = (n_seq - t0) < kTile ? (n_seq - t0) : kTile;
     const uint64_t d1w = (uint64_t)carry_pos + tp;
-    const uint32_t d1 = d1w < blen ? (uint32_t)d1w : blen;
-    for (uint32_t p0 = d0 + tid; p0 < d1; p0 += kTile) {
-      uint32_t p = p0;
-      uint8_t v = 0;
-      for (;;) {
-        const uint32_t s = find_seq(sm.dst, cnt, p);
-        const uint32_t r = p - sm.dst[s];
-        const uint32_t Ls = sm.L[s];
-        if (r < Ls) {
-          uint32_t li = sm.lit[s] + r;
-          v = li < n_lit ? lit[li] : 0;
-          break;
+    const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
+    const uint32_t base = d0 & ~15u;
+    for (uint32_t cb = base + 16 * tid; cb < d1; cb += 16 * kTile) {
+      const uint32_t p0 = cb < d0 ? d0 : cb;
+      const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
+      uint32_t s = find_seq(sm.dst, c.cnt, p0);
+      uint32_t s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+      uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (uint32_t j = 0; j < 16; j++) {
+        const uint32_t p = cb + j;
+        uint32_t v = 0;
+        if (p >= p0 && p < pe1) {
+          while (p >= s_end) {
+            s++;
+            s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+          }
+          const uint32_t r = p - sm.dst[s];
+          const uint32_t Ls = sm.lm[s] & 0xFFFFu;
+          const uint32_t f = sm.flags[s];
+          if (f & kPoison) {
+            v = 0;  // a format rule failed: write zeros, read nothing
+          } else if (r < Ls) {
+            v = *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
+          } else if (f == 0) {
+            const uint32_t ii = r - Ls, d = sm.dist[s];
+            v = *reinterpret_cast<const uint8_t*>(sm.mbase[s] + sm.O[s] + (ii < d ? ii : ii % d));
+          } else {
+            v = resolve_slow<kTile>(a, sm, c, p, n_ext);
+          }
         }
-        const uint32_t Ms = sm.M[s];
-        if (Ms & kPoison) break;
-        const uint32_t ii = r - Ls;
-        const uint64_t mabs = bs + sm.dst[s] + Ls;
-        const uint64_t Os = sm.O[s];
-        const uint64_t dist = mabs - Os;
-        const uint64_t src = Os + (ii < dist ? ii : (uint64_t)(ii % (uint32_t)dist));
-        if (src < bs) {
-          const uint64_t c = src / a.B;
-          v = reinterpret_cast<const uint8_t*>(a.loc[c])[src - c * a.B];
-          n_ext++;
-          break;
-        }
-        const uint32_t q = (uint32_t)(src - bs);
-        if (q < d0) {
-          v = out[q];
-          break;
-        }
-        p = q;
+        acc[j >> 2] |= v << (8 * (j & 3));
       }
-      out[p0] = v;
+      if (aligned && p0 == cb && pe1 == cb + 16) {
+        *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+      } else {
+#pragma unroll
+        for (uint32_t j = 0; j < 16; j++)
+          if (cb + j >= p0 && cb + j < pe1) c.out[cb + j] = (uint8_t)(acc[j >> 2] >> (8 * (j & 3)));
+      }
     }
-    carry_pos = (uint32_t)((uint64_t)carry_pos + tp > 0xFFFFFFFFull ? 0xFFFFFFFFu : carry_pos + tp);
+    carry_pos = (uint32_t)(d1w > 0xFFFFFFFFull ? 0xFFFFFFFFu : d1w);
     carry_lit += tl;
-    if ((uint64_t)carry_pos > blen) bad = true;
     __syncthreads();
-    if ((uint64_t)carry_pos >= blen) {
-      if (t0 + kTile < n_seq) bad = true;  // sequences beyond the block end
+    if ((uint64_t)carry_pos > c.blen) {
+      bad = true;
       break;
     }
   }
-  if (tid == 0 && (carry_pos != blen || carry_lit > n_lit)) bad = true;
+  if (tid == 0 && (carry_pos != c.blen || carry_lit > c.n_lit)) bad = true;
   if (bad) flag(a.err, kErrCorrupt);
   n_ext = wave_total(n_ext);
   if ((tid & 63) == 0 && n_ext) atomicAdd(a.ext_bytes, (unsigned long long)n_ext);
@@ -434,21 +505,28 @@ __global__ __launch_bounds__(64) void k_persist(DecodeArgs a) {
     const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
     const uint32_t dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
     const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
+    // Poll with relaxed loads (no cache invalidation per poll), then acquire
+    // once.  The wait is bounded in time (the 100 MHz constant clock), and
+    // once any wave has given up every other wait gives up at once, so the
+    // kernel always drains.
     bool timeout = false;
+    const uint64_t t_start = wall_clock64();
     for (uint32_t j = lane; j < dep_cnt; j += kWave) {
-      uint32_t* f = a.done + deps[j];
-      uint32_t spins = 0;
-      while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
-        if (++spins > a.spin_limit) {
+      const uint32_t* f = a.done + deps[j];
+      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
+        if (wall_clock64() - t_start > a.wait_ticks ||
+            (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)) {
           timeout = true;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(8);
       }
     }
-    if (__ballot(timeout) && lane == 0) flag(a.err, kErrTimeout);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool late = __ballot(timeout) != 0;
+    if (late && lane == 0) flag(a.err, kErrTimeout);
     __syncthreads();  // streams of this block written, dependencies visible to all lanes
-    expand_block<64>(a, i, es);
+    expand_block<64>(a, i, es, !late);
     __syncthreads();
     if (lane == 0) __hip_atomic_store(a.done + pe.block, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }

@@ -1,0 +1,85 @@
+"""Device-side validation: token streams that pass the host's index checks but
+break a format rule are reported as ACE_E_CORRUPT by ace_check(), the
+kernels write zeros instead of reading out of place, and a later clean
+decode in the same workspace is unaffected.  Each damaged archive is made on
+the CPU from an oracle archive; the damage stays inside the stream data the
+kernels bound-check (states, lengths, offsets)."""
+import struct
+
+import pytest
+
+import gen
+from harness import block_entry, stream_desc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ace():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_24531_amd import aceseek
+    return aceseek
+
+
+def _patch(a, at, fmt, v):
+    b = bytearray(a)
+    struct.pack_into(fmt, b, at, v)
+    return bytes(b)
+
+
+def _expect_corrupt(ace, a, mode):
+    arc = ace.Archive(a, device="cuda:0")
+    arc.decode_all(tuning=dict(mode=mode))
+    with pytest.raises(ace.AceError) as e:
+        arc.check()
+    assert e.value.code == ace.E_CORRUPT
+    arc.check()  # the sticky word was cleared by the read
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "levels"])
+def test_damaged_rans_state(ace, orc, mode):
+    x = gen.genome(1 << 18, 6)
+    a = orc.encode(x, block_size=4096, interleave=32, flags=1)
+    sd = stream_desc(a, 5, 0)
+    nsym = sum(1 for s in range(256) if (a[sd["data_at"] + s // 8] >> (s % 8)) & 1)
+    st = sd["data_at"] + ((32 + 2 * nsym + 3) & ~3)
+    bad = _patch(a, st + 4, "<I", struct.unpack_from("<I", a, st + 4)[0] ^ 0x100)
+    _expect_corrupt(ace, bad, mode)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "levels"])
+def test_offset_not_before_destination(ace, orc, mode):
+    x = gen.genome(1 << 18, 7)
+    a = orc.encode(x, block_size=4096, interleave=32, min_match=20, hash_len=20, flags=2)
+    for b in range(1, 64):
+        _, L, M, O = orc.block_tokens(a, b)
+        ks = [k for k in range(len(M)) if M[k]]
+        if ks:
+            k = ks[0]
+            break
+    offs = stream_desc(a, b, 2)
+    dst = b * 4096 + int(sum(L[:k + 1]) + sum(M[:k]))
+    _expect_corrupt(ace, _patch(a, offs["data_at"] + 4 * k, "<I", dst + 5), mode)
+    # a source in an earlier block that is not a listed dependency
+    e = block_entry(a, b)
+    nb = len(x) // 4096
+    dep_at = 64 + 32 * nb + 4 * e["dep_off"]
+    deps = set(struct.unpack_from("<%dI" % e["dep_cnt"], a, dep_at)) if e["dep_cnt"] else set()
+    free = [c for c in range(b) if c not in deps]
+    if free:
+        _expect_corrupt(ace, _patch(a, offs["data_at"] + 4 * k, "<I", free[0] * 4096), mode)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "levels"])
+def test_lengths_that_miss_the_block(ace, orc, mode):
+    x = gen.text(1 << 18, 8)
+    a = orc.encode(x, block_size=4096, interleave=32, min_match=16, hash_len=16, flags=2)
+    lens = stream_desc(a, 9, 1)
+    L0 = struct.unpack_from("<H", a, lens["data_at"])[0]
+    _expect_corrupt(ace, _patch(a, lens["data_at"], "<H", L0 + 3000), mode)
+    # and a clean archive decodes correctly afterwards in a fresh process state
+    arc = ace.Archive(a, device="cuda:0")
+    assert arc.decode_all(tuning=dict(mode=mode)).cpu().numpy().tobytes() == x
+    arc.check()

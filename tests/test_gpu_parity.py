@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 MODES = [dict(mode=0), dict(mode=1)]  # persistent, one launch per level
+MODE_IDS = ["persistent", "levels"]
 
 
 @pytest.fixture(scope="module")
@@ -69,7 +70,7 @@ def archives(orc):
 
 
 @pytest.mark.parametrize("case", CASES, ids=_case_id)
-@pytest.mark.parametrize("tuning", MODES, ids=["persistent", "levels"])
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
 def test_decode_all_matches_oracle(dev, ace, archives, case, tuning):
     x, a, ref = archives[case]
     assert ref == x
@@ -84,7 +85,8 @@ def test_decode_all_matches_oracle(dev, ace, archives, case, tuning):
                     (bad[0], bad[0] // case[2], bad.size))
 
 
-def test_small_workload_three_phase_every_block(dev, ace, orc):
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
+def test_small_workload_three_phase_every_block(dev, ace, orc, tuning):
     """Every block of the 1 MiB genome archive sought singly: the output
     buffer holds a sentinel before, the block after, and nothing else moved.
     The device holds only the archive, never the original bytes."""
@@ -92,7 +94,7 @@ def test_small_workload_three_phase_every_block(dev, ace, orc):
     a = orc.encode(x, block_size=16384, interleave=32, min_match=20, hash_len=20, max_chain=32)
     arc = ace.Archive(a, device=dev)
     B = 16384
-    for tuning in MODES:
+    if True:
         for b in range(64):
             def run(buf, lo, hi):
                 d = torch.from_numpy(buf).to(dev)
@@ -102,7 +104,8 @@ def test_small_workload_three_phase_every_block(dev, ace, orc):
             three_phase(run, x, b * B, (b + 1) * B, seed=b, fnv=orc.fnv1a64)
 
 
-def test_seek_ranges_match_oracle(dev, ace, archives, orc):
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
+def test_seek_ranges_match_oracle(dev, ace, archives, orc, tuning):
     rng = np.random.default_rng(5)
     for c in CASES[:8]:
         x, a, _ = archives[c]
@@ -114,18 +117,19 @@ def test_seek_ranges_match_oracle(dev, ace, archives, orc):
             hi = int(min(n, lo + int(np.exp(rng.uniform(0, np.log(4 * B + 1))))))
             ranges.append((lo, hi))
         for lo, hi in ranges:
-            got = _host(arc.seek(lo, hi, tuning=MODES[int(rng.integers(2))]))
+            got = _host(arc.seek(lo, hi, tuning=tuning))
             arc.check()
             assert got == x[lo:hi], (c[0], lo, hi)
 
 
-def test_seek_batch_alone_equals_mix(dev, ace, archives):
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
+def test_seek_batch_alone_equals_mix(dev, ace, archives, tuning):
     """Each request's bytes are the same decoded alone and inside a batch."""
     c = CASES[7]
     x, a, _ = archives[c]
     arc = ace.Archive(a, device=dev)
     lo, hi = gen.seek_requests(len(x), 300, 9, max_len=200_000)
-    out = arc.seek_batch((lo, hi))
+    out = arc.seek_batch((lo, hi), tuning=tuning)
     arc.check()
     got = _host(out)
     pos = 0
@@ -133,13 +137,13 @@ def test_seek_batch_alone_equals_mix(dev, ace, archives):
         l, h = int(lo[i]), int(hi[i])
         assert got[pos:pos + h - l] == x[l:h], i
         if i % 30 == 0:
-            solo = _host(arc.seek(l, h))
+            solo = _host(arc.seek(l, h, tuning=tuning))
             assert solo == got[pos:pos + h - l]
         pos += h - l
     # explicit output offsets with gaps stay untouched between requests
     offs = np.arange(len(lo), dtype=np.uint64) * np.uint64(200_016)
     buf = torch.full((int(offs[-1]) + 200_016,), 0xA5, dtype=torch.uint8, device=dev)
-    arc.seek_batch((lo, hi), out=buf, out_offsets=offs)
+    arc.seek_batch((lo, hi), out=buf, out_offsets=offs, tuning=tuning)
     arc.check()
     hb = _host(buf)
     for i in range(len(lo)):
@@ -148,19 +152,19 @@ def test_seek_batch_alone_equals_mix(dev, ace, archives):
         assert hb[o + h - l:o + 200_016] == b"\xa5" * (200_016 - (h - l))
 
 
-def test_degenerate_inputs(dev, ace, orc):
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
+def test_degenerate_inputs(dev, ace, orc, tuning):
     # all-zero input: a chain of dependencies through every block
     x = bytes(64 * 300)
     a = orc.encode(x, block_size=64, interleave=4, min_match=4, hash_len=4, max_chain=4)
     arc = ace.Archive(a, device=dev)
     assert arc.depth == 300
-    for t in MODES:
-        assert _host(arc.decode_all(tuning=t)) == x
-        arc.check()
-    assert _host(arc.seek(64 * 299 + 3, 64 * 300)) == x[64 * 299 + 3:]
+    assert _host(arc.decode_all(tuning=tuning)) == x
+    arc.check()
+    assert _host(arc.seek(64 * 299 + 3, 64 * 300, tuning=tuning)) == x[64 * 299 + 3:]
     # a single byte, and an empty archive
     for x in (b"Q", b""):
         a = orc.encode(x, block_size=16, interleave=2, min_match=4, hash_len=4)
         arc = ace.Archive(a, device=dev)
-        assert _host(arc.decode_all()) == x
+        assert _host(arc.decode_all(tuning=tuning)) == x
         arc.check()
