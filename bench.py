@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--seek-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seek", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="also run one device copy of this many MiB (a known-size kernel "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,6 +103,13 @@ def main():
     alg_bytes = len(a) + len(x) + ext
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     _log("decode %.3f ms/step, %.1f GB/s decompressed, %.1f GB/s algorithmic" % (ms, gbs, achieved))
+
+    if args.calib_copy:
+        src = torch.empty(args.calib_copy << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("calibration copy of %d MiB done" % args.calib_copy)
 
     result = {
         "metric": "2-layer decode GB/s (full archive)",

@@ -125,6 +125,26 @@ int ace_seek_batch(const ace_archive* a, const ace_range* h_ranges, uint32_t n,
  * ACE_E_TIMEOUT (a bounded dependency wait expired). */
 int ace_check(void* d_ws, void* stream);
 
+/* ---- batched seek as one replayed HIP graph ----
+ * A batch context owns a HIP graph captured once on `stream`.  Each run
+ * uploads the request descriptors (one small host-to-device copy) and
+ * replays the graph: device-side planning (targets of every request, their
+ * dependency closure, a level-ordered plan), one persistent decode of the
+ * union into workspace slots, and a gather of every request to its output
+ * offset.  Capacity is fixed at creation; counts are read on the device, so
+ * any batch up to the capacity replays the same graph.  The workspace must
+ * stay dedicated to the context.  Runs are asynchronous on the stream; a run
+ * waits for the previous run of the same context to have started reading its
+ * descriptors.  Errors are read with ace_check(d_ws, stream). */
+typedef struct ace_batch ace_batch;
+int ace_batch_workspace_bytes(const ace_archive* a, uint32_t max_requests, uint64_t* bytes);
+int ace_batch_create(const ace_archive* a, uint32_t max_requests, void* d_ws, uint64_t ws_cap,
+                     const ace_tuning* t, void* stream, ace_batch** out);
+/* Request i writes [lo_i, hi_i) at d_out + h_out_off[i]. */
+int ace_batch_run(ace_batch* b, const ace_range* h_ranges, uint32_t n, uint8_t* d_out,
+                  const uint64_t* h_out_off);
+void ace_batch_destroy(ace_batch* b);
+
 /* Waits for the stream, then reads and clears the workspace's counter of
  * match bytes that were copied from earlier blocks (the external source
  * bytes of every decode since the last read).  With the archive size and the

@@ -18,7 +18,8 @@ OK, E_ARG, E_RANGE, E_CORRUPT, E_NOSPACE, E_HIP, E_TIMEOUT, E_NOMEM = 0, -1, -2,
 
 EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_archive_open",
            "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
-           "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters"]
+           "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters",
+           "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy"]
 
 
 class AceError(RuntimeError):
@@ -71,6 +72,11 @@ def lib():
         L.ace_seek_batch.argtypes = [vp, vp, u32, vp, vp, vp, u64, C.POINTER(Tuning), vp]
         L.ace_check.argtypes = [vp, vp]
         L.ace_read_counters.argtypes = [vp, vp, u64p]
+        L.ace_batch_workspace_bytes.argtypes = [vp, u32, u64p]
+        L.ace_batch_create.argtypes = [vp, u32, vp, u64, C.POINTER(Tuning), vp, C.POINTER(vp)]
+        L.ace_batch_run.argtypes = [vp, vp, u32, vp, vp]
+        L.ace_batch_destroy.argtypes = [vp]
+        L.ace_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -230,6 +236,10 @@ class Archive:
                                     _stream_ptr(stream)))
         return out
 
+    def batch(self, max_requests: int, tuning=None, stream=None):
+        """A graph-replayed batched-seek context with its own workspace."""
+        return Batch(self, max_requests, tuning, stream)
+
     def read_counters(self, ws=None, stream=None) -> dict:
         """Synchronises, returns and clears the workspace counters."""
         ws = self._ws if ws is None else ws
@@ -244,3 +254,45 @@ class Archive:
         if ws is None:
             return
         _check(lib().ace_check(C.c_void_p(ws.data_ptr()), _stream_ptr(stream)))
+
+
+class Batch:
+    """Batched seek replayed as one captured HIP graph (see ace_batch_create)."""
+
+    def __init__(self, arc: Archive, max_requests: int, tuning=None, stream=None):
+        torch = arc._torch
+        self.arc = arc
+        self.cap = int(max_requests)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        b = C.c_uint64(0)
+        _check(lib().ace_batch_workspace_bytes(arc._h, self.cap, C.byref(b)))
+        self.ws = torch.zeros(b.value, dtype=torch.uint8, device=arc.device)
+        h = C.c_void_p()
+        _check(lib().ace_batch_create(arc._h, self.cap, C.c_void_p(self.ws.data_ptr()), b.value,
+                                      arc._tuning(tuning), _stream_ptr(self.stream), C.byref(h)))
+        self._h = h
+
+    def run(self, ranges, out, out_offsets=None):
+        r = Archive._ranges(ranges)
+        n = len(r) // 2
+        if out_offsets is None:
+            lens = r[1::2].astype(np.int64) - r[0::2].astype(np.int64)
+            out_offsets = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+        offs = np.ascontiguousarray(out_offsets, dtype=np.uint64)
+        _check(lib().ace_batch_run(self._h, r.ctypes.data_as(C.c_void_p), n,
+                                   C.c_void_p(out.data_ptr()), offs.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def check(self):
+        _check(lib().ace_check(C.c_void_p(self.ws.data_ptr()), _stream_ptr(self.stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

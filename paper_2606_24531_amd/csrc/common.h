@@ -51,6 +51,27 @@ struct DecodeArgs {
   uint32_t* done;       // per-block completion epochs
   uint32_t epoch;
   uint64_t wait_ticks;  // bound of one dependency wait, in 100 MHz clock ticks
+  // device-planned batches: plan length and level boundaries live in device
+  // memory (null for host-planned calls)
+  const uint32_t* n_plan_dev;
+  const uint32_t* lvl_dev;
+};
+
+// Device-side planning of a batch of seeks (captured once in a HIP graph).
+// Per call, `desc` holds: u64 n, u64 d_out, then n x (lo, hi, out_off).
+struct BatchArgs {
+  const uint8_t* arch;
+  uint32_t B, n_blocks, depth, cap;
+  uint64_t n_total;
+  const uint32_t* order;   // all blocks by level (static)
+  const uint32_t* lstart;  // level boundaries in `order` (depth + 1, static)
+  uint8_t* need;           // per block: needed by this batch
+  uint32_t* pre;           // per position in `order`: needed blocks before it
+  const uint64_t* desc;
+  PlanEntry* plan;
+  uint32_t* n_plan_dev;
+  uint32_t* lvl_dev;       // depth + 1 plan boundaries per level
+  uint64_t* loc;
 };
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
@@ -61,5 +82,13 @@ hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+// batch planning and gather (device-side counts; grids sized for capacity)
+hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s);
+hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s);
+hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s);
+hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStream_t s);
+hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width,
+                                   hipStream_t s);
 
 }  // namespace ace

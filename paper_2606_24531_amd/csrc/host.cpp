@@ -502,3 +502,204 @@ extern "C" int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_byt
   *ext_src_bytes = v;
   return ACE_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batched seek as one replayed HIP graph (device-side planning).
+// ---------------------------------------------------------------------------
+struct ace_batch {
+  const ace_archive* A = nullptr;
+  uint32_t cap = 0;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  uint64_t off_desc = 0;
+  uint64_t* staging = nullptr;  // pinned host copy of the descriptors
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+namespace {
+struct BatchLayout {
+  uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, done, lit, lens, offs, slots, desc, total;
+};
+
+BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
+  BatchLayout L;
+  uint64_t o = kWsHeader;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.order = take(4ull * A->nb);
+  L.lstart = take(4ull * (A->depth + 1));
+  L.need = take(align_up(A->nb, 4));
+  L.pre = take(4ull * A->nb);
+  L.plan = take(sizeof(PlanEntry) * A->nb);
+  L.nplan = take(4);
+  L.lvl = take(4ull * (A->depth + 1));
+  L.loc = take(8ull * A->nb);
+  L.done = take(4ull * A->nb);
+  L.lit = take((uint64_t)A->B * A->nb);
+  L.lens = take(4ull * A->all_seq);
+  L.offs = take((uint64_t)A->ow * A->all_seq);
+  L.slots = take((uint64_t)A->B * A->nb);
+  L.desc = take(16 + 24ull * cap);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" int ace_batch_workspace_bytes(const ace_archive* A, uint32_t max_requests,
+                                         uint64_t* bytes) {
+  if (!A || !bytes) return fail(ACE_E_ARG, "null argument");
+  *bytes = batch_layout(A, max_requests).total;
+  return ACE_OK;
+}
+
+extern "C" void ace_batch_destroy(ace_batch* b) {
+  if (!b) return;
+  if (b->pending) (void)hipEventSynchronize(b->done);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->staging) (void)hipHostFree(b->staging);
+  delete b;
+}
+
+extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, uint64_t ws_cap,
+                                const ace_tuning* t, void* stream, ace_batch** out) {
+  if (!A || !d_ws || !out || cap == 0) return fail(ACE_E_ARG, "null argument or zero capacity");
+  const BatchLayout L = batch_layout(A, cap);
+  if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
+  ace_batch* b = new (std::nothrow) ace_batch();
+  if (!b) return fail(ACE_E_NOMEM, "out of memory");
+  b->A = A;
+  b->cap = cap;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->ws = static_cast<uint8_t*>(d_ws);
+  b->off_desc = L.desc;
+  hipStream_t s = b->stream;
+  int rc = ACE_OK;
+  do {
+    if (hipHostMalloc((void**)&b->staging, 16 + 24ull * cap, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+      rc = fail(ACE_E_HIP, "pinned staging or event allocation failed");
+      break;
+    }
+    // static planning data: all blocks by level, and the level boundaries
+    std::vector<uint32_t> order(A->nb);
+    for (uint32_t i = 0; i < A->nb; i++) order[i] = A->all_plan[i].block;
+    uint32_t widest = 0;
+    for (uint32_t l = 0; l < A->depth; l++)
+      widest = std::max(widest, A->all_levels[l + 1] - A->all_levels[l]);
+    if (hipMemcpyAsync(b->ws + L.order, order.data(), 4ull * A->nb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->ws + L.lstart, A->all_levels.data(), 4ull * (A->depth + 1),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(ACE_E_HIP, "upload of the level order failed");
+      break;
+    }
+    BatchArgs ba{};
+    ba.arch = A->d_arch;
+    ba.B = A->B;
+    ba.n_blocks = A->nb;
+    ba.depth = A->depth;
+    ba.cap = cap;
+    ba.n_total = A->n;
+    ba.order = reinterpret_cast<const uint32_t*>(b->ws + L.order);
+    ba.lstart = reinterpret_cast<const uint32_t*>(b->ws + L.lstart);
+    ba.need = b->ws + L.need;
+    ba.pre = reinterpret_cast<uint32_t*>(b->ws + L.pre);
+    ba.desc = reinterpret_cast<const uint64_t*>(b->ws + L.desc);
+    ba.plan = reinterpret_cast<PlanEntry*>(b->ws + L.plan);
+    ba.n_plan_dev = reinterpret_cast<uint32_t*>(b->ws + L.nplan);
+    ba.lvl_dev = reinterpret_cast<uint32_t*>(b->ws + L.lvl);
+    ba.loc = reinterpret_cast<uint64_t*>(b->ws + L.loc);
+    DecodeArgs a{};
+    a.arch = A->d_arch;
+    a.plan = ba.plan;
+    a.n_plan = A->nb;  // capacity: the real count is read on the device
+    a.B = A->B;
+    a.W = A->W;
+    a.ow = A->ow;
+    a.n_blocks = A->nb;
+    a.n_total = A->n;
+    a.dst_base = (uint64_t)(uintptr_t)(b->ws + L.slots);
+    a.loc = ba.loc;
+    a.lit = b->ws + L.lit;
+    a.lens = b->ws + L.lens;
+    a.offs = b->ws + L.offs;
+    a.err = reinterpret_cast<uint32_t*>(b->ws);
+    a.ext_bytes = reinterpret_cast<unsigned long long*>(b->ws + 8);
+    a.queue = reinterpret_cast<uint32_t*>(b->ws + 4);
+    a.done = reinterpret_cast<uint32_t*>(b->ws + L.done);
+    a.epoch = 1;
+    a.wait_ticks = 10000000ull;
+    a.n_plan_dev = ba.n_plan_dev;
+    a.lvl_dev = ba.lvl_dev;
+    const uint32_t mode = t ? t->mode : 0;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(ACE_E_HIP, "graph capture could not start");
+      break;
+    }
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ba.need), 0u, align_up(A->nb, 4) / 4, s);
+    if (e == hipSuccess) e = launch_fill_u32(a.done, 0u, A->nb, s);
+    if (e == hipSuccess) e = launch_fill_u32(a.queue, 0u, 1, s);
+    if (e == hipSuccess) e = launch_batch_mark(ba, s);
+    for (uint32_t l = A->depth; e == hipSuccess && l-- > 1;)
+      e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
+    if (e == hipSuccess) e = launch_batch_compact(ba, s);
+    if (e == hipSuccess) {
+      if (mode == 0) {
+        e = launch_persistent(a, t ? t->grid_wgs : 0, s);
+      } else {
+        e = launch_rans_dev(a, A->nb, s);
+        for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++)
+          e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], s);
+      }
+    }
+    if (e == hipSuccess) e = launch_batch_gather(ba, a, s);
+    hipError_t e2 = hipStreamEndCapture(s, &b->graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      rc = fail(ACE_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      break;
+    }
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+      rc = fail(ACE_E_HIP, "graph instantiation failed");
+      break;
+    }
+    (void)widest;
+  } while (0);
+  if (rc) {
+    ace_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return ACE_OK;
+}
+
+extern "C" int ace_batch_run(ace_batch* b, const ace_range* r, uint32_t n, uint8_t* d_out,
+                             const uint64_t* out_off) {
+  if (!b || (n && (!r || !out_off || !d_out))) return fail(ACE_E_ARG, "null argument");
+  if (n > b->cap) return fail(ACE_E_ARG, "%u requests exceed the batch capacity %u", n, b->cap);
+  for (uint32_t i = 0; i < n; i++) {
+    if (r[i].lo > r[i].hi) return fail(ACE_E_ARG, "range %u is inverted", i);
+    if (r[i].hi > b->A->n) return fail(ACE_E_RANGE, "range %u ends beyond %llu", i, (unsigned long long)b->A->n);
+  }
+  // the staging buffer is reused: the previous replay must have read it
+  if (b->pending) HIP_TRY(hipEventSynchronize(b->done));
+  b->staging[0] = n;
+  b->staging[1] = (uint64_t)(uintptr_t)d_out;
+  for (uint32_t i = 0; i < n; i++) {
+    b->staging[2 + 3 * i] = r[i].lo;
+    b->staging[3 + 3 * i] = r[i].hi;
+    b->staging[4 + 3 * i] = out_off[i];
+  }
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_desc, b->staging, 16 + 24ull * n, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  HIP_TRY(hipEventRecord(b->done, b->stream));
+  b->pending = true;
+  return ACE_OK;
+}

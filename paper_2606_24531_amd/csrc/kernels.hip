@@ -175,6 +175,7 @@ __device__ __forceinline__ bool rans_decode_wave(const uint8_t* src, uint32_t cl
 __global__ __launch_bounds__(64) void k_rans(DecodeArgs a) {
   __shared__ RansSmem sm;
   const uint32_t i = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+  if (a.n_plan_dev && i >= *a.n_plan_dev) return;
   const PlanEntry pe = a.plan[i];
   const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
   const uint64_t pay = ld64(be);
@@ -454,9 +455,16 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   if ((tid & 63) == 0 && n_ext) atomicAdd(a.ext_bytes, (unsigned long long)n_ext);
 }
 
-__global__ __launch_bounds__(256) void k_expand(DecodeArgs a, uint32_t plan_lo) {
+// level < 0: plan entries plan_lo + blockIdx.x; else the level's plan range
+// is read from device memory.
+__global__ __launch_bounds__(256) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
   __shared__ ExpandSmem<256> sm;
-  expand_block<256>(a, plan_lo + blockIdx.x, sm);
+  uint32_t i = plan_lo + blockIdx.x;
+  if (level >= 0) {
+    i = a.lvl_dev[level] + blockIdx.x;
+    if (i >= a.lvl_dev[level + 1]) return;
+  }
+  expand_block<256>(a, i, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -491,11 +499,12 @@ __global__ __launch_bounds__(64) void k_persist(DecodeArgs a) {
   __shared__ RansSmem rs;
   __shared__ ExpandSmem<64> es;
   const uint32_t lane = threadIdx.x;
+  const uint32_t n_plan = a.n_plan_dev ? *a.n_plan_dev : a.n_plan;
   for (;;) {
     uint32_t i = 0;
     if (lane == 0) i = atomicAdd(a.queue, 1u);
     i = __shfl(i, 0, 64);
-    if (i >= a.n_plan) break;
+    if (i >= n_plan) break;
     const PlanEntry pe = a.plan[i];
     if (lane == 0) a.loc[pe.block] = a.dst_base + pe.dst;
     decode_stream(a, pe, i, 1, rs, lane);
@@ -557,6 +566,108 @@ __global__ __launch_bounds__(256) void k_copy(DecodeArgs a, const CopyItem* item
   }
 }
 
+// ---------------------------------------------------------------------------
+// Device-side planning of a seek batch.  Mark the target blocks of every
+// request; close the set under the dependency lists level by level from the
+// top (dependencies always sit at lower levels); compact the marked blocks,
+// in level order, into a plan whose entries decode into workspace slots;
+// after the decode, gather each request's range to its output offset.
+// ---------------------------------------------------------------------------
+__global__ void k_bmark(BatchArgs b) {
+  const uint64_t n = b.desc[0];
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = b.desc[2 + 3 * r], hi = b.desc[3 + 3 * r];
+    if (hi <= lo || hi > b.n_total) continue;
+    for (uint64_t blk = lo / b.B; blk <= (hi - 1) / b.B; blk++) b.need[blk] = 1;
+  }
+}
+
+__global__ void k_bclose(BatchArgs b, uint32_t level) {
+  const uint32_t j0 = b.lstart[level], j1 = b.lstart[level + 1];
+  for (uint32_t j = j0 + blockIdx.x * blockDim.x + threadIdx.x; j < j1; j += gridDim.x * blockDim.x) {
+    const uint32_t blk = b.order[j];
+    if (!b.need[blk]) continue;
+    const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
+    const uint32_t dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
+    const uint32_t* deps = reinterpret_cast<const uint32_t*>(b.arch + kHdr + (uint64_t)kBlk * b.n_blocks) + dep_off;
+    for (uint32_t k = 0; k < dep_cnt; k++) b.need[deps[k]] = 1;
+  }
+}
+
+// One workgroup of 1024 threads: running scans of "needed" and of n_seq.
+__global__ __launch_bounds__(1024) void k_bcompact(BatchArgs b) {
+  __shared__ uint32_t sh_cnt[16], sh_seq[16];
+  __shared__ uint32_t base_cnt, base_seq;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    base_cnt = 0;
+    base_seq = 0;
+  }
+  __syncthreads();
+  for (uint32_t j0 = 0; j0 < b.n_blocks; j0 += 1024) {
+    const uint32_t j = j0 + tid;
+    uint32_t blk = 0, f = 0, ns = 0;
+    if (j < b.n_blocks) {
+      blk = b.order[j];
+      f = b.need[blk] ? 1u : 0u;
+      ns = f ? ld32(b.arch + kHdr + (uint64_t)kBlk * blk + 12) : 0u;
+    }
+    const uint32_t ic = wave_incl_sum(f, lane), is = wave_incl_sum(ns, lane);
+    if (lane == 63) {
+      sh_cnt[w] = ic;
+      sh_seq[w] = is;
+    }
+    __syncthreads();
+    uint32_t oc = base_cnt, os = base_seq, tc = 0, ts = 0;
+    for (uint32_t k = 0; k < 16; k++) {
+      if (k < w) {
+        oc += sh_cnt[k];
+        os += sh_seq[k];
+      }
+      tc += sh_cnt[k];
+      ts += sh_seq[k];
+    }
+    const uint32_t pos = oc + ic - f, seq = os + is - ns;
+    if (j < b.n_blocks) b.pre[j] = pos;
+    if (f) b.plan[pos] = PlanEntry{blk, seq, (uint64_t)pos * b.B};
+    __syncthreads();
+    if (tid == 0) {
+      base_cnt += tc;
+      base_seq += ts;
+    }
+    __syncthreads();
+  }
+  if (tid <= b.depth) b.lvl_dev[tid] = tid < b.depth ? b.pre[b.lstart[tid]] : base_cnt;
+  if (tid == 0) *b.n_plan_dev = base_cnt;
+}
+
+// One workgroup per request: copy [lo, hi) from the decoded slots.
+__global__ __launch_bounds__(256) void k_bgather(BatchArgs b, DecodeArgs a) {
+  const uint64_t n = b.desc[0];
+  const uint64_t r = blockIdx.x;
+  if (r >= n) return;
+  const uint64_t lo = b.desc[2 + 3 * r], hi = b.desc[3 + 3 * r];
+  if (hi <= lo || hi > b.n_total) return;
+  uint8_t* dst = reinterpret_cast<uint8_t*>(b.desc[1] + b.desc[4 + 3 * r]);
+  const uint64_t len = hi - lo;
+  for (uint64_t j0 = threadIdx.x * 16ull; j0 < len; j0 += 256 * 16) {
+    uint64_t pos = lo + j0;
+    uint64_t c = pos / a.B;
+    uint64_t cend = (c + 1) * a.B;
+    const uint8_t* base = reinterpret_cast<const uint8_t*>(b.loc[c]) - c * a.B;
+    const uint64_t jn = j0 + 16 < len ? j0 + 16 : len;
+    for (uint64_t j = j0; j < jn; j++, pos++) {
+      if (pos >= cend) {
+        c++;
+        cend += a.B;
+        base = reinterpret_cast<const uint8_t*>(b.loc[c]) - c * a.B;
+      }
+      dst[j] = base[pos];
+    }
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
   for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n;
        j += (uint64_t)gridDim.x * blockDim.x)
@@ -573,7 +684,44 @@ hipError_t launch_rans(const DecodeArgs& a, hipStream_t s) {
 
 hipError_t launch_expand_level(const DecodeArgs& a, uint32_t lo, uint32_t hi, hipStream_t s) {
   if (hi <= lo) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3(hi - lo), dim3(256), 0, s, a, lo);
+  hipLaunchKernelGGL(k_expand, dim3(hi - lo), dim3(256), 0, s, a, lo, -1);
+  return hipGetLastError();
+}
+
+hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rans, dim3(grid, 3), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width,
+                                   hipStream_t s) {
+  if (width == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand, dim3(width), dim3(256), 0, s, a, 0u, (int)level);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s) {
+  const uint32_t g = (b.cap + 255) / 256;
+  hipLaunchKernelGGL(k_bmark, dim3(g < 1024 ? (g ? g : 1) : 1024), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s) {
+  const uint32_t g = (width + 255) / 256;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bclose, dim3(g < 1024 ? g : 1024), dim3(256), 0, s, b, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcompact, dim3(1), dim3(1024), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStream_t s) {
+  if (b.cap == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bgather, dim3(b.cap), dim3(256), 0, s, b, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,36 @@
+"""The graph-replayed batched seek: device-side planning plus one decode of
+the union of closures plus one gather, replayed for batches of different
+sizes; every request must equal the original bytes and its solo seek."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("mode", [1, 0], ids=["levels", "persistent"])
+def test_graph_batch_replays(orc, mode):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_24531_amd import Archive, encode
+    x = gen.mixed(3 << 20, 12)
+    a = encode(x, block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=8)
+    arc = Archive(a, device="cuda:0")
+    bt = arc.batch(500, tuning=dict(mode=mode))
+    for it, (count, max_len, seed) in enumerate([(500, 200_000, 1), (37, 1 << 20, 2),
+                                                 (1, 5, 3), (0, 10, 4), (400, 30_000, 5)]):
+        lo, hi = gen.seek_requests(len(x), max(count, 1), seed, max_len=max_len)
+        lo, hi = lo[:count], hi[:count]
+        lens = (hi - lo).astype(np.int64)
+        out = torch.full((max(int(lens.sum()), 1),), 0x5A, dtype=torch.uint8, device="cuda:0")
+        bt.run((lo, hi), out)
+        bt.check()
+        got = out.cpu().numpy().tobytes()
+        pos = 0
+        for i in range(count):
+            l, h = int(lo[i]), int(hi[i])
+            assert got[pos:pos + h - l] == x[l:h], (it, i)
+            pos += h - l
+    bt.close()

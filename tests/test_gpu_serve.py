@@ -1,0 +1,37 @@
+"""Continuous batching on the GPU: requests arriving while others run are
+admitted into free slots (each slot its own HIP stream and workspace), and
+every result is byte-identical alone and in the mix."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_results_same_alone_and_in_mix(orc):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_24531_amd import Archive, encode
+    from paper_2606_24531_amd.serve import GpuBackend, Server, latency_report, poisson_run
+    xs = {"genome": gen.genome(3 << 20, 51), "fastq": gen.fastq(2 << 20, 52),
+          "text": gen.text(2 << 20, 53)}
+    arcs = {k: Archive(encode(v, block_size=16384, interleave=32, min_match=16, hash_len=16,
+                              max_level=8), device="cuda:0") for k, v in xs.items()}
+    srv = Server(GpuBackend(arcs, slots=3), budget_bytes=8 << 20, slots=3, max_batch=64)
+    reqs, wall = poisson_run(srv, list(xs), {k: len(v) for k, v in xs.items()}, rate=3000.0,
+                             count=400, seed=5, min_len=16, max_len=1 << 20)
+    rep = latency_report(reqs, wall)
+    assert rep["requests"] == 400
+    assert srv.peak_used <= 8 << 20 and srv.used == 0
+    assert srv.batches < 400  # requests were actually batched
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for r in reqs:
+        got = r.result.cpu().numpy().tobytes()
+        assert got == xs[r.archive][r.lo:r.hi], r.rid
+    for r in rng.choice(reqs, size=20, replace=False):
+        solo = arcs[r.archive].seek(r.lo, r.hi, tuning=dict(mode=1))
+        arcs[r.archive].check()
+        assert solo.cpu().numpy().tobytes() == r.result.cpu().numpy().tobytes()
