@@ -69,8 +69,10 @@ typedef struct {
  *  blocks_per_wg    reserved (1)
  *  lut_variant      0 = 4096 x u32 slot table in LDS
  *  grid_wgs         workgroups of the persistent decoder (0 = fill the GPU)
- *  mode             0 = persistent dependency-ordered kernel, 1 = one launch
- *                   per dependency level (the always-correct fallback) */
+ *  mode             0 and 1: entropy decode of every planned block in one
+ *                   launch, then one match-expansion launch per dependency
+ *                   level; 2: the persistent dependency-ordered kernel, which
+ *                   is disabled in this build (ACE_E_ARG) */
 typedef struct {
   uint32_t waves_per_block, blocks_per_wg, lut_variant, grid_wgs, mode;
 } ace_tuning;
@@ -150,6 +152,14 @@ void ace_batch_destroy(ace_batch* b);
  * bytes of every decode since the last read).  With the archive size and the
  * output size this gives the algorithmic HBM bytes of a decode. */
 int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_bytes);
+
+/* Phase timing for measurement: with timing on, every decode on the calling
+ * thread records HIP events on its stream before and after the entropy
+ * launch and after the last match-expansion launch (no work is skipped).
+ * ace_last_timings waits for the last timed decode and returns the two
+ * phases' durations in milliseconds. */
+int ace_set_timing(int on);
+int ace_last_timings(float* ms_entropy, float* ms_match);
 
 #ifdef __cplusplus
 }

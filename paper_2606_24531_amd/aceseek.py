@@ -19,7 +19,8 @@ OK, E_ARG, E_RANGE, E_CORRUPT, E_NOSPACE, E_HIP, E_TIMEOUT, E_NOMEM = 0, -1, -2,
 EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_archive_open",
            "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
            "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters",
-           "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy"]
+           "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
+           "ace_set_timing", "ace_last_timings"]
 
 
 class AceError(RuntimeError):
@@ -77,6 +78,8 @@ def lib():
         L.ace_batch_run.argtypes = [vp, vp, u32, vp, vp]
         L.ace_batch_destroy.argtypes = [vp]
         L.ace_batch_destroy.restype = None
+        L.ace_set_timing.argtypes = [C.c_int]
+        L.ace_last_timings.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
         _lib = L
     return _lib
 
@@ -114,6 +117,34 @@ def encode(x, **kw) -> bytes:
                                       out.ctypes.data_as(C.c_void_p), out.size, C.byref(ln))
     _check(rc)
     return out[:ln.value].tobytes()
+
+
+def archive_facts(data) -> dict:
+    """Sizes read from an archive's index: blocks, sequences, literal count,
+    and the decoded token bytes (literals + 4-byte lengths + offsets)."""
+    import struct
+    b = bytes(data[:64]) if not isinstance(data, (bytes, bytearray)) else data
+    nb = struct.unpack_from("<I", b, 24)[0]
+    ow = b[15]
+    arr = np.frombuffer(data, dtype=np.uint8)
+    tbl = arr[64:64 + 32 * nb].view("<u4").reshape(nb, 8) if nb else np.zeros((0, 8), np.uint32)
+    pay = tbl[:, 0].astype(np.uint64) | (tbl[:, 1].astype(np.uint64) << np.uint64(32))
+    n_seq = tbl[:, 3].astype(np.int64)
+    n_lit = np.array([int(np.frombuffer(arr[int(p) + 4:int(p) + 8].tobytes(), "<u4")[0])
+                      for p in pay], dtype=np.int64) if nb else np.zeros(0, np.int64)
+    return {"n_blocks": nb, "n_seq": int(n_seq.sum()), "n_lit": int(n_lit.sum()),
+            "token_bytes": int(n_lit.sum() + (4 + ow) * n_seq.sum())}
+
+
+def set_timing(on: bool):
+    _check(lib().ace_set_timing(1 if on else 0))
+
+
+def last_timings():
+    """(entropy ms, match ms) of the last timed decode on this thread."""
+    a, b = C.c_float(0), C.c_float(0)
+    _check(lib().ace_last_timings(C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def _stream_ptr(stream):

@@ -216,7 +216,17 @@ extern "C" int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_
 // ---------------------------------------------------------------------------
 namespace {
 
+// Optional phase timing (per thread): events around the entropy launch and
+// around the expansion launches of the last decode on this thread.
+struct PhaseTimer {
+  bool on = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  bool recorded = false;
+};
+thread_local PhaseTimer g_timer;
+
 constexpr uint64_t kWsHeader = 256;  // error word, work counter
+constexpr uint32_t kModePersistent = 2;
 
 struct Layout {
   uint64_t plan, loc, done, lit, lens, offs, slots, items, total;
@@ -292,6 +302,11 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
                hipStream_t s, bool entries_pinned) {
   (void)entries_pinned;
+  const uint32_t mode = t ? t->mode : 0;
+  if (mode == kModePersistent)
+    return fail(ACE_E_ARG, "the persistent dependency-ordered kernel is disabled in this build: "
+                           "it did not complete on the GPU and its cause is not yet found");
+  if (mode > 1) return fail(ACE_E_ARG, "unknown mode %u", mode);
   DecodeArgs a{};
   a.arch = A->d_arch;
   a.plan = reinterpret_cast<const PlanEntry*>(ws + L.plan);
@@ -316,20 +331,17 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                                      hipMemcpyHostToDevice, s));
   if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,
                                       hipMemcpyHostToDevice, s));
-  const uint32_t mode = t ? t->mode : 0;
-  bool done = false;
-  if (mode == 0 && n_plan) {
-    HIP_TRY(launch_fill_u32(a.done, 0u, A->nb, s));
-    HIP_TRY(launch_fill_u32(a.queue, 0u, 1, s));
-    hipError_t e = launch_persistent(a, t ? t->grid_wgs : 0, s);
-    if (e == hipSuccess) done = true;
-    else if (e != hipErrorNotSupported) return fail(ACE_E_HIP, "persistent launch: %s", hipGetErrorString(e));
-    else (void)hipGetLastError();
-  }
-  if (!done && n_plan) {
+  if (n_plan) {
+    const bool timed = g_timer.on;
+    if (timed) HIP_TRY(hipEventRecord(g_timer.ev[0], s));
     HIP_TRY(launch_rans(a, s));
+    if (timed) HIP_TRY(hipEventRecord(g_timer.ev[1], s));
     for (size_t l = 0; l + 1 < lstart.size(); l++)
       HIP_TRY(launch_expand_level(a, lstart[l], lstart[l + 1], s));
+    if (timed) {
+      HIP_TRY(hipEventRecord(g_timer.ev[2], s));
+      g_timer.recorded = true;
+    }
   }
   if (n_items)
     HIP_TRY(launch_copy(a, reinterpret_cast<const CopyItem*>(ws + L.items), (uint32_t)n_items, s));
@@ -640,6 +652,10 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.n_plan_dev = ba.n_plan_dev;
     a.lvl_dev = ba.lvl_dev;
     const uint32_t mode = t ? t->mode : 0;
+    if (mode == kModePersistent || mode > 1) {
+      rc = fail(ACE_E_ARG, "mode %u is not available (the persistent kernel is disabled)", mode);
+      break;
+    }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       rc = fail(ACE_E_HIP, "graph capture could not start");
       break;
@@ -652,13 +668,9 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
       e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
     if (e == hipSuccess) e = launch_batch_compact(ba, s);
     if (e == hipSuccess) {
-      if (mode == 0) {
-        e = launch_persistent(a, t ? t->grid_wgs : 0, s);
-      } else {
-        e = launch_rans_dev(a, A->nb, s);
-        for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++)
-          e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], s);
-      }
+      e = launch_rans_dev(a, A->nb, s);
+      for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++)
+        e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], s);
     }
     if (e == hipSuccess) e = launch_batch_gather(ba, a, s);
     hipError_t e2 = hipStreamEndCapture(s, &b->graph);
@@ -701,5 +713,22 @@ extern "C" int ace_batch_run(ace_batch* b, const ace_range* r, uint32_t n, uint8
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   HIP_TRY(hipEventRecord(b->done, b->stream));
   b->pending = true;
+  return ACE_OK;
+}
+
+extern "C" int ace_set_timing(int on) {
+  if (on && !g_timer.ev[0])
+    for (auto& e : g_timer.ev) HIP_TRY(hipEventCreate(&e));
+  g_timer.on = on != 0;
+  g_timer.recorded = false;
+  return ACE_OK;
+}
+
+extern "C" int ace_last_timings(float* ms_entropy, float* ms_match) {
+  if (!ms_entropy || !ms_match) return fail(ACE_E_ARG, "null argument");
+  if (!g_timer.recorded) return fail(ACE_E_ARG, "no timed decode on this thread");
+  HIP_TRY(hipEventSynchronize(g_timer.ev[2]));
+  HIP_TRY(hipEventElapsedTime(ms_entropy, g_timer.ev[0], g_timer.ev[1]));
+  HIP_TRY(hipEventElapsedTime(ms_match, g_timer.ev[1], g_timer.ev[2]));
   return ACE_OK;
 }

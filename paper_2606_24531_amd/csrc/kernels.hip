@@ -638,7 +638,7 @@ __global__ __launch_bounds__(1024) void k_bcompact(BatchArgs b) {
     }
     __syncthreads();
   }
-  if (tid <= b.depth) b.lvl_dev[tid] = tid < b.depth ? b.pre[b.lstart[tid]] : base_cnt;
+  for (uint32_t l = tid; l <= b.depth; l += 1024) b.lvl_dev[l] = l < b.depth ? b.pre[b.lstart[l]] : base_cnt;
   if (tid == 0) *b.n_plan_dev = base_cnt;
 }
 

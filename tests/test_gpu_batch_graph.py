@@ -7,10 +7,16 @@ import pytest
 import gen
 
 pytestmark = pytest.mark.gpu
+
+# The persistent dependency-ordered kernel did not complete on the GPU in two
+# runs and its cause has not been found; the library refuses that mode.
+PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not complete on the "
+                                          "GPU, cause not yet found")
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("mode", [1, 0], ids=["levels", "persistent"])
+@pytest.mark.parametrize("mode", [1, pytest.param(2, marks=PERSISTENT_SKIP)],
+                         ids=["levels", "persistent"])
 def test_graph_batch_replays(orc, mode):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -112,6 +112,9 @@ def test_argument_errors_before_device_work(lib):
     ws = C.c_uint64()
     assert L.ace_workspace_bytes(h, None, 0, C.byref(ws)) == 0
     assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value - 1, None, None) == lib.E_NOSPACE
+    t = lib.Tuning(0, 0, 0, 0, 2)
+    assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(t), None) == lib.E_ARG
+    assert b"disabled" in L.ace_last_error()
     r = np.array([0, 100_001], dtype=np.uint64)
     assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), 1, C.byref(ws)) == lib.E_RANGE
     L.ace_archive_close(h)
