@@ -294,7 +294,8 @@ class Batch:
         torch = arc._torch
         self.arc = arc
         self.cap = int(max_requests)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # graph capture needs a stream of its own (not the legacy default stream)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=arc.device)
         b = C.c_uint64(0)
         _check(lib().ace_batch_workspace_bytes(arc._h, self.cap, C.byref(b)))
         self.ws = torch.zeros(b.value, dtype=torch.uint8, device=arc.device)
@@ -310,8 +311,12 @@ class Batch:
             lens = r[1::2].astype(np.int64) - r[0::2].astype(np.int64)
             out_offsets = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
         offs = np.ascontiguousarray(out_offsets, dtype=np.uint64)
+        torch = self.arc._torch
+        cur = torch.cuda.current_stream(self.arc.device)
+        self.stream.wait_stream(cur)  # `out` was made on the caller's stream
         _check(lib().ace_batch_run(self._h, r.ctypes.data_as(C.c_void_p), n,
                                    C.c_void_p(out.data_ptr()), offs.ctypes.data_as(C.c_void_p)))
+        cur.wait_stream(self.stream)  # later work on the caller's stream sees the bytes
         return out
 
     def check(self):

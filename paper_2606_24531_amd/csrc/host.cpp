@@ -583,6 +583,7 @@ extern "C" void ace_batch_destroy(ace_batch* b) {
 extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, uint64_t ws_cap,
                                 const ace_tuning* t, void* stream, ace_batch** out) {
   if (!A || !d_ws || !out || cap == 0) return fail(ACE_E_ARG, "null argument or zero capacity");
+  if (!stream) return fail(ACE_E_ARG, "a batch needs a stream of its own: the default stream cannot be captured");
   const BatchLayout L = batch_layout(A, cap);
   if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
   ace_batch* b = new (std::nothrow) ace_batch();
