@@ -136,6 +136,33 @@ def archive_facts(data) -> dict:
             "token_bytes": int(n_lit.sum() + (4 + ow) * n_seq.sum())}
 
 
+def stream_table(data) -> dict:
+    """Per-stream sizes summed over an archive's blocks (the paper's Table 2
+    view): for LIT, LEN and OFF the decoded bytes, the stored bytes, the
+    ratio raw/stored (< 1: the entropy coder inflated the stream) and the
+    share of blocks that store the stream rANS-coded."""
+    import struct
+    arr = np.frombuffer(data, dtype=np.uint8)
+    nb = struct.unpack_from("<I", bytes(arr[:64]), 24)[0]
+    out = {}
+    names = ("LIT", "LEN", "OFF")
+    raw = np.zeros(3, np.int64)
+    stored = np.zeros(3, np.int64)
+    rans = np.zeros(3, np.int64)
+    for b in range(nb):
+        pay = int(arr[64 + 32 * b:64 + 32 * b + 8].view("<u8")[0])
+        d = arr[pay:pay + 48].view("<u4").reshape(3, 4)
+        for t in range(3):
+            raw[t] += int(d[t, 1])
+            stored[t] += int(d[t, 2])
+            rans[t] += int(d[t, 0] & 0xFF) == 1
+    for t, nm in enumerate(names):
+        out[nm] = {"raw": int(raw[t]), "stored": int(stored[t]),
+                   "ratio": round(float(raw[t]) / max(1, int(stored[t])), 4),
+                   "rans_share": round(float(rans[t]) / max(1, nb), 4)}
+    return out
+
+
 def set_timing(on: bool):
     _check(lib().ace_set_timing(1 if on else 0))
 

@@ -239,7 +239,7 @@ Layout layout(const ace_archive* A, uint64_t n_plan, uint64_t n_seq, uint64_t n_
   L.plan = o;  o = align_up(o + sizeof(PlanEntry) * n_plan, 256);
   L.loc = o;   o = align_up(o + 8ull * A->nb, 256);
   L.done = o;  o = align_up(o + 4ull * A->nb, 256);
-  L.lit = o;   o = align_up(o + (uint64_t)A->B * n_plan, 256);
+  L.lit = o;   o = align_up(o + (uint64_t)A->B * n_plan + 64, 256);  // +64: aligned over-read slack
   L.lens = o;  o = align_up(o + 4ull * n_seq, 256);
   L.offs = o;  o = align_up(o + (uint64_t)A->ow * n_seq, 256);
   L.slots = o; o = align_up(o + (uint64_t)A->B * n_slots, 256);
@@ -553,7 +553,7 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   L.lvl = take(4ull * (A->depth + 1));
   L.loc = take(8ull * A->nb);
   L.done = take(4ull * A->nb);
-  L.lit = take((uint64_t)A->B * A->nb);
+  L.lit = take((uint64_t)A->B * A->nb + 64);
   L.lens = take(4ull * A->all_seq);
   L.offs = take((uint64_t)A->ow * A->all_seq);
   L.slots = take((uint64_t)A->B * A->nb);

@@ -216,6 +216,9 @@ constexpr uint32_t kPoison = 1u, kSlow = 2u;
 
 template <uint32_t kTile>
 struct ExpandSmem {
+  static constexpr uint32_t kRound = 4 * kTile;  // chunks sorted per round
+  uint32_t list[kRound]; // chunk << 8 | sequence: copy chunks first, per-byte chunks from the back
+  uint32_t nvec, nbyte;
   uint32_t dst[kTile];   // block-relative start of the sequence
   uint32_t lm[kTile];    // L | M << 16
   uint32_t dist[kTile];  // match start - O
@@ -334,6 +337,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const uint8_t* lens = a.lens + 4ull * pe.seq_base;
   const uint8_t* offs = a.offs + (uint64_t)a.ow * pe.seq_base;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
+  constexpr uint32_t kRound = ExpandSmem<kTile>::kRound;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kTile) {
@@ -401,45 +405,108 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     c.cnt = (n_seq - t0) < kTile ? (n_seq - t0) : kTile;
     const uint64_t d1w = (uint64_t)carry_pos + tp;
     const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
+    // Output is produced in 16-byte chunks, 4 per thread per round.  Each
+    // round first sorts its chunks: a chunk whose 16 bytes come from one
+    // contiguous source (all literals of one sequence, or one match with no
+    // period wrap) is copied with five aligned dword loads and one 16-byte
+    // store; the others go through the per-byte path.  Sorting keeps the two
+    // kinds of work in separate passes, so a wavefront does not pay for both.
     const uint32_t base = d0 & ~15u;
-    for (uint32_t cb = base + 16 * tid; cb < d1; cb += 16 * kTile) {
-      const uint32_t p0 = cb < d0 ? d0 : cb;
-      const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-      uint32_t s = find_seq(sm.dst, c.cnt, p0);
-      uint32_t s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
-      uint32_t acc[4] = {0, 0, 0, 0};
-#pragma unroll
-      for (uint32_t j = 0; j < 16; j++) {
-        const uint32_t p = cb + j;
-        uint32_t v = 0;
-        if (p >= p0 && p < pe1) {
-          while (p >= s_end) {
-            s++;
-            s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
-          }
-          const uint32_t r = p - sm.dst[s];
-          const uint32_t Ls = sm.lm[s] & 0xFFFFu;
-          const uint32_t f = sm.flags[s];
-          if (f & kPoison) {
-            v = 0;  // a format rule failed: write zeros, read nothing
-          } else if (r < Ls) {
-            v = *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
-          } else if (f == 0) {
-            const uint32_t ii = r - Ls, d = sm.dist[s];
-            v = *reinterpret_cast<const uint8_t*>(sm.mbase[s] + sm.O[s] + (ii < d ? ii : ii % d));
+    const uint32_t nch = d1 > base ? (d1 - base + 15) / 16 : 0;
+    const bool pow2 = (a.B & (a.B - 1)) == 0;
+    for (uint32_t k0 = 0; k0 < nch; k0 += kRound) {
+      const uint32_t kn = nch - k0 < kRound ? nch - k0 : kRound;
+      if (tid == 0) {
+        sm.nvec = 0;
+        sm.nbyte = 0;
+      }
+      __syncthreads();
+      for (uint32_t k = k0 + tid; k < k0 + kn; k += kTile) {
+        const uint32_t cb = base + 16 * k;
+        const uint32_t p0 = cb < d0 ? d0 : cb;
+        const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
+        const uint32_t sq = find_seq(sm.dst, c.cnt, p0);
+        bool vec = aligned && p0 == cb && pe1 == cb + 16 && !(sm.flags[sq] & kPoison);
+        if (vec) {
+          const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
+          const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
+          if (cb + 16 > end_s) {
+            vec = false;
+          } else if (r0 + 16 <= Ls) {
+            vec = true;  // all literals (the literal scratch has readable slack)
+          } else if (r0 >= Ls && sm.flags[sq] == 0 && pow2) {
+            // the five aligned dwords must stay inside the source block's bytes
+            const uint32_t ii0 = r0 - Ls;
+            const uint64_t src = sm.O[sq] + ii0;
+            const uint32_t off = (uint32_t)(src & (a.B - 1));
+            const uint32_t shp = (uint32_t)((sm.mbase[sq] + src) & 3);
+            const uint32_t limit = src >= c.bs ? c.blen : a.B;
+            vec = ii0 + 16 <= sm.dist[sq] && off >= shp && off - shp + 20 <= limit;
           } else {
-            v = resolve_slow<kTile>(a, sm, c, p, n_ext);
+            vec = false;
           }
         }
-        acc[j >> 2] |= v << (8 * (j & 3));
+        const uint32_t e = (k << 8) | sq;
+        if (vec) sm.list[atomicAdd(&sm.nvec, 1u)] = e;
+        else sm.list[kRound - 1 - atomicAdd(&sm.nbyte, 1u)] = e;
       }
-      if (aligned && p0 == cb && pe1 == cb + 16) {
-        *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
-      } else {
+      __syncthreads();
+      const uint32_t nv = sm.nvec, nby = sm.nbyte;
+      for (uint32_t ei = tid; ei < nv; ei += kTile) {
+        const uint32_t e = sm.list[ei], k = e >> 8, sq = e & 0xFFu;
+        const uint32_t cb = base + 16 * k;
+        const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
+        const uint8_t* src = r0 < Ls ? reinterpret_cast<const uint8_t*>(sm.lit[sq] + r0)
+                                     : reinterpret_cast<const uint8_t*>(sm.mbase[sq] + sm.O[sq] + (r0 - Ls));
+        const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(src - sh);
+        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
+        *reinterpret_cast<uint4*>(c.out + cb) =
+            make_uint4(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
+                       __builtin_amdgcn_alignbyte(w3, w2, sh), __builtin_amdgcn_alignbyte(w4, w3, sh));
+      }
+      for (uint32_t ei = tid; ei < nby; ei += kTile) {
+        const uint32_t e = sm.list[kRound - 1 - ei], k = e >> 8;
+        const uint32_t cb = base + 16 * k;
+        const uint32_t p0 = cb < d0 ? d0 : cb;
+        const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
+        uint32_t s = e & 0xFFu;
+        uint32_t s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+        uint32_t acc[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (uint32_t j = 0; j < 16; j++)
-          if (cb + j >= p0 && cb + j < pe1) c.out[cb + j] = (uint8_t)(acc[j >> 2] >> (8 * (j & 3)));
+        for (uint32_t j = 0; j < 16; j++) {
+          const uint32_t p = cb + j;
+          uint32_t v = 0;
+          if (p >= p0 && p < pe1) {
+            while (p >= s_end) {
+              s++;
+              s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+            }
+            const uint32_t r = p - sm.dst[s];
+            const uint32_t Ls = sm.lm[s] & 0xFFFFu;
+            const uint32_t f = sm.flags[s];
+            if (f & kPoison) {
+              v = 0;  // a format rule failed: write zeros, read nothing
+            } else if (r < Ls) {
+              v = *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
+            } else if (f == 0) {
+              const uint32_t ii = r - Ls, d = sm.dist[s];
+              v = *reinterpret_cast<const uint8_t*>(sm.mbase[s] + sm.O[s] + (ii < d ? ii : ii % d));
+            } else {
+              v = resolve_slow<kTile>(a, sm, c, p, n_ext);
+            }
+          }
+          acc[j >> 2] |= v << (8 * (j & 3));
+        }
+        if (aligned && p0 == cb && pe1 == cb + 16) {
+          *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+        } else {
+#pragma unroll
+          for (uint32_t j = 0; j < 16; j++)
+            if (cb + j >= p0 && cb + j < pe1) c.out[cb + j] = (uint8_t)(acc[j >> 2] >> (8 * (j & 3)));
+        }
       }
+      __syncthreads();
     }
     carry_pos = (uint32_t)(d1w > 0xFFFFFFFFull ? 0xFFFFFFFFu : d1w);
     carry_lit += tl;
