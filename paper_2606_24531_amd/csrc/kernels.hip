@@ -186,10 +186,7 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a) {
                : t == 1 ? a.lens + 4ull * pe.seq_base
                         : a.offs + (uint64_t)a.ow * pe.seq_base;
   const uint8_t* src = a.arch + pay + off;
-  if (mode == 0) {
-    for (uint32_t j = lane; j < n; j += kWave) dst[j] = src[j];
-    return;
-  }
+  if (mode == 0) return;  // raw streams are read in place by the expansion
   if (!rans_decode_wave(src, clen, n, a.W, dst, sm, lane) && lane == 0) flag(a.err, kErrCorrupt);
 }
 
@@ -333,9 +330,11 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   c.blen = (uint32_t)((a.n_total - c.bs) < a.B ? (a.n_total - c.bs) : a.B);
   c.out = reinterpret_cast<uint8_t*>(a.dst_base + pe.dst);
   c.ext_ok = ext_ok;
-  const uint8_t* lit = a.lit + (uint64_t)i * a.B;
-  const uint8_t* lens = a.lens + 4ull * pe.seq_base;
-  const uint8_t* offs = a.offs + (uint64_t)a.ow * pe.seq_base;
+  // each stream is read in place when stored raw, else from its decoded copy
+  const uint8_t* pl = a.arch + pay;
+  const uint8_t* lit = pl[0] == 0 ? pl + ld32(pl + 12) : a.lit + (uint64_t)i * a.B;
+  const uint8_t* lens = pl[16] == 0 ? pl + ld32(pl + 28) : a.lens + 4ull * pe.seq_base;
+  const uint8_t* offs = pl[32] == 0 ? pl + ld32(pl + 44) : a.offs + (uint64_t)a.ow * pe.seq_base;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
   constexpr uint32_t kRound = ExpandSmem<kTile>::kRound;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
