@@ -14,10 +14,14 @@
  *     recent first for at most max_chain candidates; a candidate q scores
  *     the common prefix of X[q..] and X[p..], capped at the block end and at
  *     65535 (overlap with p is allowed: the copy is byte-sequential);
- *   - with max_level > 0 blocks are grouped in epochs of 64; block b may
- *     take sources only from itself and from blocks of earlier epochs whose
- *     level is <= max_level - 2 ("visible" blocks), so every level stays
- *     below max_level.  Chain candidates in invisible blocks are passed over
+ *   - with max_level > 0 blocks are grouped in epochs of 64 (E epochs in
+ *     all); a block of epoch e may take sources only from itself and from
+ *     blocks of earlier epochs whose level is below
+ *         lambda(e) = min(max_level - 1, floor(log2(e + 1)),
+ *                         max(1, floor(log2(E + 1)) - 1))
+ *     ("visible" blocks), so every level stays below max_level and the
+ *     levels grow geometrically in size (the last level holds at least half
+ *     of the epochs).  Chain candidates in invisible blocks are passed over
  *     without being counted (at most 8 * max_chain chain steps in all), and a
  *     counted candidate is cut where its source first enters an invisible
  *     block;
@@ -366,6 +370,24 @@ int orc_encode_bound(uint64_t n, const orc_params* p, uint64_t* bound) {
   return ORC_OK;
 }
 
+/* floor(log2(v)) for v >= 1 */
+static uint32_t ilog2(uint64_t v) {
+  uint32_t r = 0;
+  while (v >>= 1) r++;
+  return r;
+}
+
+/* Level budget of epoch e of E under cap max_level: blocks of the epoch see
+ * only earlier-epoch blocks whose level is below this value. */
+static uint32_t level_budget(uint64_t e, uint64_t E, uint32_t max_level) {
+  uint32_t lam = ilog2(e + 1);
+  uint32_t top = ilog2(E + 1);
+  top = top >= 2 ? top - 1 : 1;
+  if (lam > top) lam = top;
+  if (lam > max_level - 1) lam = max_level - 1;
+  return lam;
+}
+
 int orc_encode(const uint8_t* src, uint64_t n, const orc_params* p, uint8_t* dst,
                uint64_t cap, uint64_t* out_len) {
   int rc = check_params(n, p);
@@ -407,8 +429,9 @@ int orc_encode(const uint8_t* src, uint64_t n, const orc_params* p, uint8_t* dst
         uint64_t lim = e - pos < 65535 ? e - pos : 65535;
         /* first byte of this block's epoch: earlier blocks of the epoch are invisible */
         uint64_t epoch0 = p->max_level > 0 ? (b / 64) * 64 * B : s;
+        uint32_t lam = p->max_level > 0 ? level_budget(b / 64, (nb + 63) / 64, p->max_level) : 0;
         for (; q != NONE && cand < p->max_chain && steps < 8 * p->max_chain; steps++, q = prev[q]) {
-          if (p->max_level > 0 && q < s && (q >= epoch0 || level[q / B] + 1 >= p->max_level))
+          if (p->max_level > 0 && q < s && (q >= epoch0 || level[q / B] >= lam))
             continue; /* starts in an invisible block: passed over, not counted */
           cand++;
           uint64_t len = 0;
@@ -417,7 +440,7 @@ int orc_encode(const uint8_t* src, uint64_t n, const orc_params* p, uint8_t* dst
             /* cut where the source first enters an invisible block */
             uint64_t end = q + len < s ? q + len : s;
             for (uint64_t c = q / B; c * B < end; c++)
-              if (c * B >= epoch0 || level[c] + 1 >= p->max_level) {
+              if (c * B >= epoch0 || level[c] >= lam) {
                 len = c * B > q ? c * B - q : 0;
                 break;
               }

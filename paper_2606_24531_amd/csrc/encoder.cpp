@@ -10,9 +10,11 @@
 //   for at most max_chain candidates; a candidate's length is its common
 //   prefix with p (overlap allowed) capped at the block end and 65535.
 //   Longest wins, ties to the first found; taken if it reaches
-//   min_match.  With a level cap, blocks are grouped in epochs of 64: block
-//   b takes sources only from itself and from blocks of earlier epochs whose
-//   level is <= cap - 2; chain candidates elsewhere are passed over without
+//   min_match.  With a level cap, blocks are grouped in epochs of 64 (E in
+//   all): a block of epoch e takes sources only from itself and from blocks
+//   of earlier epochs whose level is below min(cap - 1, floor(log2(e + 1)),
+//   max(1, floor(log2(E + 1)) - 1)), so levels stay below the cap and grow
+//   geometrically in size; chain candidates elsewhere are passed over without
 //   being counted (at most 8 * max_chain chain steps), and a counted
 //   candidate is cut where its source first enters such a block.
 //   Frequencies are normalised to 4096 with f = max(1,
@@ -141,9 +143,19 @@ struct ParseCtx {
   uint64_t n;
   const ace_encode_params* p;
   const Chains* C;
-  // level cap: sorted blocks of earlier epochs whose level is >= cap - 1
+  // level cap: sorted blocks of earlier epochs at or above the epoch's level budget
   const std::vector<uint32_t>* deep;
 };
+
+uint32_t level_budget(uint64_t e, uint64_t n_ep, uint32_t cap) {
+  auto lg = [](uint64_t v) {
+    uint32_t r = 0;
+    while (v >>= 1) r++;
+    return r;
+  };
+  const uint32_t top = std::max<uint32_t>(1, lg(n_ep + 1) >= 1 ? lg(n_ep + 1) - 1 : 0);
+  return std::min({lg(e + 1), top, cap - 1});
+}
 
 void push_seq(std::vector<Seq>& out, uint64_t lits, uint32_t M, uint64_t O) {
   while (lits > 65535) {
@@ -354,18 +366,26 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
   std::vector<uint32_t> deep;
   ParseCtx pc{x, n, p, &C, &deep};
   if (p->max_level) {
-    // epochs of 64 blocks: blocks of one epoch see only earlier epochs
+    // epochs of 64 blocks: blocks of one epoch see only earlier epochs, below
+    // the epoch's level budget
+    const uint64_t n_ep = (nb + 63) / 64;
+    uint32_t lam = 0;
     for (uint64_t e0 = 0; e0 < nb; e0 += 64) {
       const uint64_t e1 = std::min<uint64_t>(nb, e0 + 64);
+      const uint32_t l = level_budget(e0 / 64, n_ep, p->max_level);
+      if (l != lam) {  // the budget only grows: drop blocks that became visible
+        lam = l;
+        deep.erase(std::remove_if(deep.begin(), deep.end(), [&](uint32_t b) { return level[b] < lam; }),
+                   deep.end());
+      }
       parallel_for(e1 - e0, T, [&](uint64_t i) { parse_block(pc, e0 + i, true, seqs[e0 + i]); });
       for (uint64_t b = e0; b < e1; b++) {
         deps_of(seqs[b], b, B, deps[b]);
         uint32_t lv = 0;
         for (uint32_t d : deps[b]) lv = std::max(lv, level[d] + 1);
         level[b] = lv;
+        if (lv >= lam) deep.push_back((uint32_t)b);
       }
-      for (uint64_t b = e0; b < e1; b++)
-        if (level[b] + 1 >= p->max_level) deep.push_back((uint32_t)b);
     }
   } else {
     parallel_for(nb, T, [&](uint64_t b) { parse_block(pc, b, false, seqs[b]); });

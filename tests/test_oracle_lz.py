@@ -180,6 +180,36 @@ def test_level_cap_bounds_depth(orc, cap):
             assert np.all((M == 0) | (O >= b * 4096))
 
 
+@pytest.mark.parametrize("cap", [2, 4, 16])
+def test_level_budget_respected(orc, cap):
+    # the capped parse policy, checked from the tokens: a block of epoch e
+    # (64 blocks each, E in all) references only blocks of earlier epochs
+    # whose level is below min(cap - 1, floor(log2(e + 1)),
+    # max(1, floor(log2(E + 1)) - 1)); levels then come out geometric
+    import gen
+    B = 1024
+    x = gen.fastq(1 << 20, 9)
+    a = orc.encode(x, block_size=B, interleave=8, min_match=16, hash_len=16, max_level=cap)
+    level, _, _ = orc.block_facts(a)
+    nb = len(level)
+    E = (nb + 63) // 64
+    lg = lambda v: v.bit_length() - 1
+    n_refs = 0
+    for b in range(nb):
+        e = b // 64
+        lam = min(cap - 1, lg(e + 1), max(1, lg(E + 1) - 1))
+        _, L, M, O = orc.block_tokens(a, b)
+        for m, o in zip(M.tolist(), O.tolist()):
+            if m == 0 or o >= b * B:
+                continue
+            for d in range(o // B, (min(o + m, b * B) - 1) // B + 1):
+                assert d < 64 * e and level[d] < lam, (b, d)
+                n_refs += 1
+    assert n_refs > 1000  # the rule was exercised
+    assert level.max() < cap
+    assert orc.decode(a) == x
+
+
 def test_dependencies_recomputed_from_tokens(orc):
     import gen
     x = gen.genome(1 << 18, 11)
