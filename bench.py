@@ -28,6 +28,36 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "decode_fastq256_hbm_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_24531_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per step moved by `kernel`'s launches, from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (already scaled by the copy-kernel
+    calibration there), or None when that summary was taken on another
+    workload or on a kernel source other than the one built now."""
+    try:
+        lines = open(COUNTERS).read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("@ ") and ":" in ln:
+            k, v = ln[2:].split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_sha256() or kv.get("workload") != workload:
+        return None
+    v = kv.get("hbm_bytes_per_step " + kernel)
+    return int(v) if v is not None else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,7 +71,9 @@ def main():
     ap.add_argument("--min-match", type=int, default=20)
     ap.add_argument("--max-level", type=int, default=16)
     ap.add_argument("--mode", type=int, default=1,
-                    help="1: entropy decode of all blocks, then one expansion launch per level")
+                    help="1: entropy decode of all blocks, then one expansion launch per level, "
+                         "one stream; 3: entropy decode per level on a second stream beside the "
+                         "per-level expansion")
     ap.add_argument("--seek-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seek", action="store_true")
@@ -129,7 +161,8 @@ def main():
     ms_ent, ms_mat = float(np.mean(t_ent)), float(np.mean(t_mat))
     tok = facts["token_bytes"]
     phase = {
-        "entropy": {"kernel": "k_rans", "launches_per_step": 1, "ms": round(ms_ent, 4),
+        "entropy": {"kernel": "k_rans", "launches_per_step": arc.depth if args.mode == 3 else 1,
+                    "ms": round(ms_ent, 4),
                     "alg_bytes": len(a) + tok},
         "match": {"kernel": "k_expand", "launches_per_step": arc.depth, "ms": round(ms_mat, 4),
                   "alg_bytes": tok + ext + len(x)},
@@ -144,6 +177,8 @@ def main():
         torch.cuda.synchronize()
         _log("calibration copy of %d MiB done" % args.calib_copy)
 
+    workload = "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
+        args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level)
     result = {
         "metric": "2-layer decode GB/s (full archive)",
         "value": round(gbs, 2),
@@ -158,19 +193,20 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {
-            "workload": "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
-                args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level),
+            "workload": workload,
             "n_total": len(x), "archive_bytes": len(a), "ratio": round(len(x) / len(a), 4),
             "block_size": args.block, "interleave": args.interleave,
             "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
-            "mode": "per-level launches",
+            "mode": {1: "per-level launches, one stream",
+                     3: "per-level launches, entropy overlapped on a second stream"}[args.mode],
         },
         "roofline": {
             "bound": "hbm", "kernel": phase[dom]["kernel"],
             "achieved": round(phase[dom]["alg_bytes"] / (phase[dom]["ms"] * 1e-3) / 1e9, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(phase[dom]["alg_bytes"] / (phase[dom]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(phase[dom]["kernel"], workload),
+            "traffic_unit": "HBM bytes per step (all launches of the kernel)",
             "alg_bytes_per_launch_sequence": phase[dom]["alg_bytes"],
             "phases": phase,
             "path": {"alg_bytes_per_step": alg_bytes, "achieved": round(achieved, 2),

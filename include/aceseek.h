@@ -64,15 +64,28 @@ typedef struct {
   uint64_t lo, hi;
 } ace_range;
 
-/* Launch shape.  Zero fields take the library defaults.
- *  waves_per_block  wavefronts cooperating on one block's match expansion
- *  blocks_per_wg    reserved (1)
- *  lut_variant      0 = 4096 x u32 slot table in LDS
+/* Launch shape.  Zero fields take the library defaults; a value this build
+ * does not offer is ACE_E_ARG.
+ *  waves_per_block  wavefronts cooperating on one block's match expansion:
+ *                   2, 4 or 8 (0 = 4); each takes two sequences per lane
+ *                   per tile
+ *  blocks_per_wg    blocks whose streams one entropy wavefront decodes side
+ *                   by side: 1, or 2 when the interleave is at most 32
+ *                   (0 = 2 when possible)
+ *  lut_variant      entropy table layout in LDS: 0 = 4096-byte slot->symbol
+ *                   map plus one (f-1, cum) word per symbol (the only one)
  *  grid_wgs         workgroups of the persistent decoder (0 = fill the GPU)
- *  mode             0 and 1: entropy decode of every planned block in one
- *                   launch, then one match-expansion launch per dependency
- *                   level; 2: the persistent dependency-ordered kernel, which
- *                   is disabled in this build (ACE_E_ARG) */
+ *  mode             0 and 1: one entropy launch for every planned block,
+ *                   then one match-expansion launch per dependency level,
+ *                   all on the caller's stream; 2: the persistent
+ *                   dependency-ordered kernel, which is disabled in this
+ *                   build (ACE_E_ARG); 3: one entropy launch per level on a
+ *                   second stream of the calling thread (created on first
+ *                   use, one per device), each level's expansion on the
+ *                   caller's stream waiting for that level's entropy decode,
+ *                   so later levels' entropy decode runs beside earlier
+ *                   levels' expansion; the caller's stream is joined with
+ *                   the second stream before the call's last launch */
 typedef struct {
   uint32_t waves_per_block, blocks_per_wg, lut_variant, grid_wgs, mode;
 } ace_tuning;

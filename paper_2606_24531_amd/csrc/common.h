@@ -75,8 +75,10 @@ struct BatchArgs {
 };
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
-hipError_t launch_rans(const DecodeArgs& a, hipStream_t s);
-hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi,
+// per_wave: streams one wavefront decodes (0 = 2 when W <= 32, else 1);
+// waves: wavefronts per block in the expansion (2, 4 or 8; 0 = 4)
+hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s);
+hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi, uint32_t waves,
                                hipStream_t s);
 hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,
@@ -87,8 +89,12 @@ hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s);
 hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStream_t s);
-hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t grid, hipStream_t s);
-hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width,
+hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave, hipStream_t s);
+// entropy decode of one level whose plan range is read from lvl_dev; width =
+// the most entries the level can hold
+hipError_t launch_rans_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t per_wave,
+                                 hipStream_t s);
+hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
                                    hipStream_t s);
 
 }  // namespace ace

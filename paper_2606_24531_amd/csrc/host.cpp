@@ -216,17 +216,71 @@ extern "C" int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_
 // ---------------------------------------------------------------------------
 namespace {
 
-// Optional phase timing (per thread): events around the entropy launch and
-// around the expansion launches of the last decode on this thread.
+// Optional phase timing (per thread): a pair of events around every entropy
+// launch and every expansion launch of the last decode on this thread, each
+// pair recorded on the stream the launch goes to.
 struct PhaseTimer {
   bool on = false;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> ent, mat;  // begin/end pairs
+  size_t n_ent = 0, n_mat = 0;
   bool recorded = false;
 };
 thread_local PhaseTimer g_timer;
 
-constexpr uint64_t kWsHeader = 256;  // error word, work counter
-constexpr uint32_t kModePersistent = 2;
+hipError_t timer_pair(std::vector<hipEvent_t>& v, size_t k) {
+  while (v.size() < 2 * (k + 1)) {
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    v.push_back(e);
+  }
+  return hipSuccess;
+}
+
+// The calling thread's second stream and level events on the current device:
+// the entropy launches of later levels run on it beside the expansion of
+// earlier levels on the caller's stream.
+struct Overlap {
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;  // [0] fork, [1 + l] entropy of level l done
+};
+thread_local std::vector<Overlap> g_overlap;  // by device ordinal
+
+hipError_t overlap_for(size_t n_levels, Overlap*& o) {
+  int dev = 0;
+  hipError_t r = hipGetDevice(&dev);
+  if (r != hipSuccess) return r;
+  if (g_overlap.size() <= (size_t)dev) g_overlap.resize(dev + 1);
+  o = &g_overlap[dev];
+  if (!o->s2) {
+    r = hipStreamCreateWithFlags(&o->s2, hipStreamNonBlocking);
+    if (r != hipSuccess) return r;
+  }
+  while (o->ev.size() < n_levels + 1) {
+    hipEvent_t e = nullptr;
+    r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    o->ev.push_back(e);
+  }
+  return hipSuccess;
+}
+
+// Launch-shape fields of a tuning record that this build offers.
+int check_tuning(const ace_archive* A, const ace_tuning* t) {
+  if (!t) return ACE_OK;
+  const uint32_t w = t->waves_per_block, p = t->blocks_per_wg;
+  if (w != 0 && w != 2 && w != 4 && w != 8)
+    return fail(ACE_E_ARG, "waves_per_block %u: 2, 4 or 8 (0 = 4)", w);
+  if (p > 2 || (p == 2 && A->W > 32))
+    return fail(ACE_E_ARG, "blocks_per_wg %u: 1, or 2 when the interleave is at most 32", p);
+  if (t->lut_variant != 0) return fail(ACE_E_ARG, "lut_variant %u: only 0 is built", t->lut_variant);
+  return ACE_OK;
+}
+
+// workspace header: error word (0), work counter (4), 16 counters of match
+// bytes read from earlier blocks (16..144, one per block id mod 16)
+constexpr uint64_t kWsHeader = 256, kWsCounters = 16;
+constexpr uint32_t kModePersistent = 2, kModeOverlap = 3;  // 0 and 1: per level, one stream
 
 struct Layout {
   uint64_t plan, loc, done, lit, lens, offs, slots, items, total;
@@ -306,7 +360,10 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   if (mode == kModePersistent)
     return fail(ACE_E_ARG, "the persistent dependency-ordered kernel is disabled in this build: "
                            "it did not complete on the GPU and its cause is not yet found");
-  if (mode > 1) return fail(ACE_E_ARG, "unknown mode %u", mode);
+  if (mode > 1 && mode != kModeOverlap) return fail(ACE_E_ARG, "unknown mode %u", mode);
+  int rc = check_tuning(A, t);
+  if (rc) return rc;
+  const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
   DecodeArgs a{};
   a.arch = A->d_arch;
   a.plan = reinterpret_cast<const PlanEntry*>(ws + L.plan);
@@ -322,7 +379,7 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.lens = ws + L.lens;
   a.offs = ws + L.offs;
   a.err = reinterpret_cast<uint32_t*>(ws);
-  a.ext_bytes = reinterpret_cast<unsigned long long*>(ws + 8);
+  a.ext_bytes = reinterpret_cast<unsigned long long*>(ws + kWsCounters);
   a.queue = reinterpret_cast<uint32_t*>(ws + 4);
   a.done = reinterpret_cast<uint32_t*>(ws + L.done);
   a.epoch = 1;
@@ -332,16 +389,54 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,
                                       hipMemcpyHostToDevice, s));
   if (n_plan) {
-    const bool timed = g_timer.on;
-    if (timed) HIP_TRY(hipEventRecord(g_timer.ev[0], s));
-    HIP_TRY(launch_rans(a, s));
-    if (timed) HIP_TRY(hipEventRecord(g_timer.ev[1], s));
-    for (size_t l = 0; l + 1 < lstart.size(); l++)
-      HIP_TRY(launch_expand_level(a, lstart[l], lstart[l + 1], s));
-    if (timed) {
-      HIP_TRY(hipEventRecord(g_timer.ev[2], s));
-      g_timer.recorded = true;
+    PhaseTimer& T = g_timer;
+    const bool timed = T.on;
+    T.n_ent = T.n_mat = 0;
+    T.recorded = false;
+    const size_t nl = lstart.size() - 1;
+    auto expand = [&](size_t l) -> hipError_t {
+      if (lstart[l + 1] <= lstart[l]) return hipSuccess;
+      if (timed) {
+        hipError_t r = timer_pair(T.mat, T.n_mat);
+        if (r == hipSuccess) r = hipEventRecord(T.mat[2 * T.n_mat], s);
+        if (r != hipSuccess) return r;
+      }
+      hipError_t r = launch_expand_level(a, lstart[l], lstart[l + 1], waves, s);
+      if (r == hipSuccess && timed) r = hipEventRecord(T.mat[2 * T.n_mat++ + 1], s);
+      return r;
+    };
+    auto entropy = [&](uint32_t lo, uint32_t hi, hipStream_t st) -> hipError_t {
+      if (hi <= lo) return hipSuccess;
+      if (timed) {
+        hipError_t r = timer_pair(T.ent, T.n_ent);
+        if (r == hipSuccess) r = hipEventRecord(T.ent[2 * T.n_ent], st);
+        if (r != hipSuccess) return r;
+      }
+      hipError_t r = launch_rans(a, lo, hi, per_wave, st);
+      if (r == hipSuccess && timed) r = hipEventRecord(T.ent[2 * T.n_ent++ + 1], st);
+      return r;
+    };
+    if (mode == kModeOverlap && nl > 1) {
+      // fork: entropy of level l on the second stream, level by level; the
+      // caller's stream expands level l once that level's entropy is done
+      // (and, by stream order, every earlier level is expanded), then joins
+      Overlap* o = nullptr;
+      HIP_TRY(overlap_for(nl, o));
+      HIP_TRY(hipEventRecord(o->ev[0], s));
+      HIP_TRY(hipStreamWaitEvent(o->s2, o->ev[0], 0));
+      for (size_t l = 0; l < nl; l++) {
+        HIP_TRY(entropy(lstart[l], lstart[l + 1], o->s2));
+        HIP_TRY(hipEventRecord(o->ev[1 + l], o->s2));
+      }
+      for (size_t l = 0; l < nl; l++) {
+        HIP_TRY(hipStreamWaitEvent(s, o->ev[1 + l], 0));
+        HIP_TRY(expand(l));
+      }
+    } else {
+      HIP_TRY(entropy(0, (uint32_t)n_plan, s));
+      for (size_t l = 0; l < nl; l++) HIP_TRY(expand(l));
     }
+    T.recorded = timed;
   }
   if (n_items)
     HIP_TRY(launch_copy(a, reinterpret_cast<const CopyItem*>(ws + L.items), (uint32_t)n_items, s));
@@ -508,10 +603,12 @@ extern "C" int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_byt
   if (!d_ws || !ext_src_bytes) return fail(ACE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(s));
-  uint64_t v = 0, zero = 0;
-  HIP_TRY(hipMemcpy(&v, static_cast<uint8_t*>(d_ws) + 8, 8, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d_ws) + 8, &zero, 8, hipMemcpyHostToDevice));
-  *ext_src_bytes = v;
+  uint64_t v[16] = {0}, zero[16] = {0};
+  HIP_TRY(hipMemcpy(v, static_cast<uint8_t*>(d_ws) + kWsCounters, sizeof(v), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d_ws) + kWsCounters, zero, sizeof(zero), hipMemcpyHostToDevice));
+  uint64_t sum = 0;
+  for (uint64_t c : v) sum += c;
+  *ext_src_bytes = sum;
   return ACE_OK;
 }
 
@@ -529,6 +626,8 @@ struct ace_batch {
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
   bool pending = false;
+  hipStream_t s2 = nullptr;     // the entropy branch of the captured graph
+  std::vector<hipEvent_t> ev;   // fork + one per level (capture edges only)
 };
 
 namespace {
@@ -576,6 +675,8 @@ extern "C" void ace_batch_destroy(ace_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->done) (void)hipEventDestroy(b->done);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->s2) (void)hipStreamDestroy(b->s2);
   if (b->staging) (void)hipHostFree(b->staging);
   delete b;
 }
@@ -645,7 +746,7 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.lens = b->ws + L.lens;
     a.offs = b->ws + L.offs;
     a.err = reinterpret_cast<uint32_t*>(b->ws);
-    a.ext_bytes = reinterpret_cast<unsigned long long*>(b->ws + 8);
+    a.ext_bytes = reinterpret_cast<unsigned long long*>(b->ws + kWsCounters);
     a.queue = reinterpret_cast<uint32_t*>(b->ws + 4);
     a.done = reinterpret_cast<uint32_t*>(b->ws + L.done);
     a.epoch = 1;
@@ -653,9 +754,30 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.n_plan_dev = ba.n_plan_dev;
     a.lvl_dev = ba.lvl_dev;
     const uint32_t mode = t ? t->mode : 0;
-    if (mode == kModePersistent || mode > 1) {
-      rc = fail(ACE_E_ARG, "mode %u is not available (the persistent kernel is disabled)", mode);
+    if (mode == kModePersistent) {
+      rc = fail(ACE_E_ARG, "mode 2 is not available (the persistent kernel is disabled)");
       break;
+    }
+    if (mode > 1 && mode != kModeOverlap) {
+      rc = fail(ACE_E_ARG, "unknown mode %u", mode);
+      break;
+    }
+    if ((rc = check_tuning(A, t)) != ACE_OK) break;
+    const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
+    // the entropy decode of level l on a branch of the graph, beside the
+    // expansion of earlier levels (mode 3, up to 64 levels)
+    const bool overlap = mode == kModeOverlap && A->depth > 1 && A->depth <= 64;
+    if (overlap) {
+      bool ok = hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking) == hipSuccess;
+      for (uint32_t l = 0; ok && l <= A->depth; l++) {
+        hipEvent_t ev = nullptr;
+        ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) b->ev.push_back(ev);
+      }
+      if (!ok) {
+        rc = fail(ACE_E_HIP, "stream or event creation failed");
+        break;
+      }
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       rc = fail(ACE_E_HIP, "graph capture could not start");
@@ -668,10 +790,22 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     for (uint32_t l = A->depth; e == hipSuccess && l-- > 1;)
       e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
     if (e == hipSuccess) e = launch_batch_compact(ba, s);
-    if (e == hipSuccess) {
-      e = launch_rans_dev(a, A->nb, s);
+    if (e == hipSuccess && overlap) {
+      e = hipEventRecord(b->ev[0], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->s2, b->ev[0], 0);
+      for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++) {
+        e = launch_rans_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], per_wave, b->s2);
+        if (e == hipSuccess) e = hipEventRecord(b->ev[1 + l], b->s2);
+      }
+      for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++) {
+        e = hipStreamWaitEvent(s, b->ev[1 + l], 0);
+        if (e == hipSuccess)
+          e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], waves, s);
+      }
+    } else if (e == hipSuccess) {
+      e = launch_rans_dev(a, A->nb, per_wave, s);
       for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++)
-        e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], s);
+        e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], waves, s);
     }
     if (e == hipSuccess) e = launch_batch_gather(ba, a, s);
     hipError_t e2 = hipStreamEndCapture(s, &b->graph);
@@ -718,8 +852,6 @@ extern "C" int ace_batch_run(ace_batch* b, const ace_range* r, uint32_t n, uint8
 }
 
 extern "C" int ace_set_timing(int on) {
-  if (on && !g_timer.ev[0])
-    for (auto& e : g_timer.ev) HIP_TRY(hipEventCreate(&e));
   g_timer.on = on != 0;
   g_timer.recorded = false;
   return ACE_OK;
@@ -727,9 +859,22 @@ extern "C" int ace_set_timing(int on) {
 
 extern "C" int ace_last_timings(float* ms_entropy, float* ms_match) {
   if (!ms_entropy || !ms_match) return fail(ACE_E_ARG, "null argument");
-  if (!g_timer.recorded) return fail(ACE_E_ARG, "no timed decode on this thread");
-  HIP_TRY(hipEventSynchronize(g_timer.ev[2]));
-  HIP_TRY(hipEventElapsedTime(ms_entropy, g_timer.ev[0], g_timer.ev[1]));
-  HIP_TRY(hipEventElapsedTime(ms_match, g_timer.ev[1], g_timer.ev[2]));
+  const PhaseTimer& T = g_timer;
+  if (!T.recorded) return fail(ACE_E_ARG, "no timed decode on this thread");
+  float e = 0, m = 0;
+  for (size_t k = 0; k < T.n_ent; k++) {
+    float t = 0;
+    HIP_TRY(hipEventSynchronize(T.ent[2 * k + 1]));
+    HIP_TRY(hipEventElapsedTime(&t, T.ent[2 * k], T.ent[2 * k + 1]));
+    e += t;
+  }
+  for (size_t k = 0; k < T.n_mat; k++) {
+    float t = 0;
+    HIP_TRY(hipEventSynchronize(T.mat[2 * k + 1]));
+    HIP_TRY(hipEventElapsedTime(&t, T.mat[2 * k], T.mat[2 * k + 1]));
+    m += t;
+  }
+  *ms_entropy = e;
+  *ms_match = m;
   return ACE_OK;
 }

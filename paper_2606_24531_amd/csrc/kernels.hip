@@ -48,189 +48,334 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 __device__ __forceinline__ void flag(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
 
 // ---------------------------------------------------------------------------
-// Entropy layer: one wavefront decodes one rANS stream.
+// Entropy layer: a group of G lanes (G = 64, or 32 when W <= 32, so that one
+// wavefront decodes two streams side by side) decodes one rANS stream.
 //
-// LDS holds the stream's 12-bit table as a 4096-byte slot -> symbol map plus
-// one packed word per symbol ((f-1) << 16 | cum), and a 4 KiB ring of
-// renormalisation words refilled 1 KiB at a time from a register prefetch,
-// so the decode loop never waits on HBM latency.  Lane j owns state j; each
-// step decodes symbols t*W .. t*W+W-1, and the lanes that renormalise take
-// consecutive words in lane order: word = running position +
-// mbcnt(ballot(need)).  The loop body is branch-free apart from the
-// wave-uniform ring refill.
+// LDS holds each stream's 12-bit table as a 4096-byte slot -> symbol map plus
+// one packed word per symbol ((f-1) << 16 | cum), and a ring of two chunks of
+// renormalisation words (16 G bytes each), refilled from a register
+// prefetch so the decode loop never waits on HBM latency.  The table build's
+// scratch lives in the ring before the ring is filled.  Lane j of a group
+// owns state j; each step decodes symbols t*W .. t*W+W-1, and the lanes that
+// renormalise take consecutive words in lane order: word = running position
+// + (count of renormalising lanes below in the group).  The loop body is
+// branch-free apart from the ring refill.
 // ---------------------------------------------------------------------------
-struct RansSmem {
-  uint8_t sym[4096];              // slot -> symbol
-  uint4 ring[256];                // 4 chunks x 64 lanes x 16 B
-  uint32_t fc[256];               // symbol -> (f-1) << 16 | cum
-  uint8_t by_rank[256];           // k-th present symbol
-  unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
+template <uint32_t G>
+struct RansGroup {
+  uint8_t sym[4096];  // slot -> symbol
+  uint32_t fc[256];   // symbol -> (f-1) << 16 | cum
+  uint8_t stage[16 * G + 16];  // decoded symbols not yet written out; the last 16 bytes
+                               // take the writes of idle lanes
+  union {
+    uint4 ring[2 * G];  // 2 chunks x G lanes x 16 B
+    struct {
+      unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
+      uint8_t by_rank[256];           // k-th present symbol
+    } b;
+  } u;
 };
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Returns false (wave-uniform) when the stream breaks a format rule.
-__device__ __forceinline__ bool rans_decode_wave(const uint8_t* src, uint32_t clen, uint32_t n, uint32_t W,
-                                 uint8_t* dst, RansSmem& sm, uint32_t lane) {
-  // ---- frequency table: 32-byte presence bitmap, then f-1 per present symbol
-  if (clen < 32) return false;
-  const uint32_t nib = ((uint32_t)src[lane >> 1] >> ((lane & 1) * 4)) & 0xFu;
-  const uint32_t cnt = __popc(nib);
-  const uint32_t before = wave_incl_sum(cnt, lane) - cnt;
-  const uint32_t present = uniform(wave_total(cnt));
-  const uint32_t tsz = (32 + 2 * present + 3) & ~3u;
-  if (present == 0 || tsz + 4 * W > clen || ((clen - tsz - 4 * W) & 1)) return false;
-  uint32_t f[4], mysum = 0, k = before;
+// Inclusive prefix sum and total over aligned groups of G lanes.
+template <uint32_t G>
+__device__ __forceinline__ uint32_t grp_incl_sum(uint32_t v, uint32_t g) {
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    f[j] = ((nib >> j) & 1) ? ld16(src + 32 + 2 * (k++)) + 1 : 0;
+  for (uint32_t d = 1; d < G; d <<= 1) {
+    uint32_t y = __shfl_up(v, d, G);
+    if (g >= d) v += y;
+  }
+  return v;
+}
+template <uint32_t G>
+__device__ __forceinline__ uint32_t grp_total(uint32_t v) {
+#pragma unroll
+  for (uint32_t d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, G);
+  return v;
+}
+
+// Whether any lane of group h has v set.
+template <uint32_t G>
+__device__ __forceinline__ bool grp_any(bool v, uint32_t h) {
+  const uint64_t m = __ballot(v);
+  return G == 64 ? m != 0 : ((m >> (32 * h)) & 0xFFFFFFFFull) != 0;
+}
+
+// Decodes one stream per group; `on` (group-uniform) says whether the group
+// has a stream.  Every lane of the wave must call it.  Returns true (for the
+// group's lanes) when the group's stream breaks a format rule.
+template <uint32_t G>
+__device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t clen, uint32_t n, uint32_t W,
+                                                  uint8_t* dst, RansGroup<G>& sm, uint32_t g, uint32_t h,
+                                                  bool on) {
+  constexpr uint32_t kSpl = 256 / G;      // symbols per lane in the table build
+  constexpr uint32_t kChunkW = 8 * G;     // words per ring chunk
+  // ---- frequency table: 32-byte presence bitmap, then f-1 per present symbol
+  bool bad = on && clen < 32;
+  on = on && !bad;
+  const uint32_t bits = !on ? 0u
+                        : G == 64 ? ((uint32_t)src[g >> 1] >> ((g & 1) * 4)) & 0xFu
+                                  : (uint32_t)src[g];
+  const uint32_t cnt = __popc(bits);
+  const uint32_t before = grp_incl_sum<G>(cnt, g) - cnt;
+  const uint32_t present = grp_total<G>(cnt);
+  const uint32_t tsz = (32 + 2 * present + 3) & ~3u;
+  if (on && (present == 0 || tsz + 4 * W > clen || ((clen - tsz - 4 * W) & 1))) bad = true;
+  on = on && !bad;
+  uint32_t f[kSpl], mysum = 0, k = before;
+#pragma unroll
+  for (uint32_t j = 0; j < kSpl; j++) {
+    f[j] = (on && ((bits >> j) & 1)) ? ld16(src + 32 + 2 * (k++)) + 1 : 0;
     mysum += f[j];
   }
-  uint32_t cum = wave_incl_sum(mysum, lane) - mysum;
-  if (uniform(wave_total(mysum)) != kM) return false;
-  sm.starts[lane] = 0ull;
+  uint32_t cum = grp_incl_sum<G>(mysum, g) - mysum;
+  const uint32_t total = grp_total<G>(mysum);
+  if (on && total != kM) bad = true;
+  on = on && !bad;
+  for (uint32_t j = g; j < 64; j += G) sm.u.b.starts[j] = 0ull;
   wave_sync();
   k = before;
+  if (on) {
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const uint32_t s = 4 * lane + j;
-    sm.fc[s] = f[j] ? ((f[j] - 1) << 16) | cum : 0u;
-    if (f[j]) {
-      sm.by_rank[k++] = (uint8_t)s;
-      atomicOr(&sm.starts[cum >> 6], 1ull << (cum & 63));
+    for (uint32_t j = 0; j < kSpl; j++) {
+      const uint32_t s = kSpl * g + j;
+      sm.fc[s] = f[j] ? ((f[j] - 1) << 16) | cum : 0u;
+      if (f[j]) {
+        sm.u.b.by_rank[k++] = (uint8_t)s;
+        atomicOr(&sm.u.b.starts[cum >> 6], 1ull << (cum & 63));
+      }
+      cum += f[j];
     }
-    cum += f[j];
   }
   wave_sync();
-  // ---- slot -> symbol: lane l fills slots 64l .. 64l+63 in order, the rank
-  // of the covering symbol advancing at every interval start
+  // ---- slot -> symbol: lane g fills slots 4096/G * g onwards in order, the
+  // rank of the covering symbol advancing at every interval start
   {
-    const unsigned long long w = sm.starts[lane];
-    const uint32_t pc = __popcll(w);
-    int rank = (int)(wave_incl_sum(pc, lane) - pc) - 1;
-    uint32_t* out32 = reinterpret_cast<uint32_t*>(sm.sym) + 16 * lane;
-    uint32_t cur = rank >= 0 ? sm.by_rank[rank] : 0u;
-    for (uint32_t q = 0; q < 16; q++) {
-      uint32_t word = 0;
+    constexpr uint32_t kWpl = 64 / G;  // 64-bit start words per lane
+    uint32_t pc = 0;
 #pragma unroll
-      for (uint32_t b = 0; b < 4; b++) {
-        if ((w >> (4 * q + b)) & 1) cur = sm.by_rank[++rank];
-        word |= cur << (8 * b);
+    for (uint32_t q = 0; q < kWpl; q++) pc += __popcll(sm.u.b.starts[kWpl * g + q]);
+    int rank = (int)(grp_incl_sum<G>(pc, g) - pc) - 1;
+    uint32_t cur = (on && rank >= 0) ? sm.u.b.by_rank[rank] : 0u;
+    uint32_t* out32 = reinterpret_cast<uint32_t*>(sm.sym) + 16 * kWpl * g;
+    if (on) {
+#pragma unroll
+      for (uint32_t q = 0; q < kWpl; q++) {
+        const unsigned long long w = sm.u.b.starts[kWpl * g + q];
+        for (uint32_t r = 0; r < 16; r++) {
+          uint32_t word = 0;
+#pragma unroll
+          for (uint32_t b = 0; b < 4; b++) {
+            if ((w >> (4 * r + b)) & 1) cur = sm.u.b.by_rank[++rank];
+            word |= cur << (8 * b);
+          }
+          out32[16 * q + r] = word;
+        }
       }
-      out32[q] = word;
     }
   }
+  wave_sync();  // the build scratch is dead from here: the ring reuses it
   // ---- states and word ring
   const uint8_t* wsrc = src + tsz + 4 * W;
-  const uint32_t nwords = (clen - tsz - 4 * W) >> 1;
-  uint32_t x = lane < W ? ld32(src + tsz + 4 * lane) : kL;
-  if (__ballot(lane < W && x < kL)) return false;
+  const uint32_t nwords = on ? (clen - tsz - 4 * W) >> 1 : 0;
+  uint32_t x = (on && g < W) ? ld32(src + tsz + 4 * g) : kL;
+  if (on && g < W && x < kL) bad = true;
+  bad = grp_any<G>(bad, h);
+  on = on && !bad;
   const uintptr_t a0 = (uintptr_t)wsrc & ~(uintptr_t)15;
-  const uint32_t hw = uniform((uint32_t)((uintptr_t)wsrc - a0) >> 1);  // word 0 in chunk 0
-  const uint32_t nchunks = uniform((2 * (hw + nwords) + 1023) >> 10);
+  const uint32_t hw = (uint32_t)((uintptr_t)wsrc - a0) >> 1;  // word 0 in chunk 0
+  const uint32_t nchunks = on ? (2 * (hw + nwords) + 16 * G - 1) / (16 * G) : 0;
   const uint4* gch = reinterpret_cast<const uint4*>(a0);
   uint32_t committed = 0;
-  for (; committed < 3 && committed < nchunks; committed++)
-    sm.ring[(committed & 3) * 64 + lane] = gch[committed * 64 + lane];
+  for (; committed < 2 && committed < nchunks; committed++)
+    sm.u.ring[(committed & 1) * G + g] = gch[committed * G + g];
   uint4 pf = make_uint4(0, 0, 0, 0);
-  if (committed < nchunks) pf = gch[committed * 64 + lane];
+  if (committed < nchunks) pf = gch[committed * G + g];
   wave_sync();
-  const uint16_t* ring16 = reinterpret_cast<const uint16_t*>(sm.ring);
+  const uint16_t* ring16 = reinterpret_cast<const uint16_t*>(sm.u.ring);
   uint32_t rp = hw;  // ring position (in words) of the next unread word
-  const bool lane_on = lane < W;
-  const uint32_t nsteps = uniform((n + W - 1) / W);
-  uint32_t i = lane;
-  for (uint32_t t = 0; t < nsteps; t++) {
-    if (rp + 64 > committed * 512 && committed < nchunks) {  // wave-uniform
-      sm.ring[(committed & 3) * 64 + lane] = pf;
-      committed++;
-      if (committed < nchunks) pf = gch[committed * 64 + lane];
+  const bool lane_on = on && g < W;
+  const uint32_t my_steps = on ? (n + W - 1) / W : 0;
+  const uint32_t nsteps = uniform(G == 64 ? my_steps : max(my_steps, (uint32_t)__shfl_xor(my_steps, 32, 64)));
+  // Decoded symbols go to the LDS stage and are written out right after a
+  // ring refill (or when the stage is full): the refill waits for its
+  // prefetch, and a wait issued there then finds the earlier stores done.
+  constexpr uint32_t kU = 4;  // steps per ring/stage check in the main loop
+  const uint32_t stage_steps = (16 * G / W) & ~(kU - 1);
+  uint32_t t0 = 0;  // first step held in the stage
+  auto flush = [&](uint32_t t) {
+    const uint32_t f0 = min(t0 * W, n), f1 = min(t * W, n), cnt = f1 - f0;
+    uint8_t* o = dst + f0;
+    uint32_t k = 0;
+    if ((((uintptr_t)o) & 3) == 0) {
+      for (k = 4 * g; k + 4 <= cnt; k += 4 * G)
+        *reinterpret_cast<uint32_t*>(o + k) = *reinterpret_cast<const uint32_t*>(sm.stage + k);
+      k = (cnt & ~3u) + g;
+    } else {
+      k = g;
+    }
+    for (; k < cnt; k += G) o[k] = sm.stage[k];
+    t0 = t;
+  };
+  // Makes room for `steps` more steps: ring words and stage space.
+  auto prepare = [&](uint32_t t, uint32_t steps) {
+    const bool refill = rp + steps * W > committed * kChunkW && committed < nchunks;  // group-uniform
+    if (__ballot(refill)) {
+      if (refill) {
+        sm.u.ring[(committed & 1) * G + g] = pf;
+        committed++;
+        if (committed < nchunks) pf = gch[committed * G + g];
+      }
       wave_sync();
     }
-    const bool act = lane_on && i < n;
+    const bool out = on && (refill || t - t0 + steps > stage_steps) && t > t0;  // group-uniform
+    if (__ballot(out)) {
+      if (out) flush(t);
+      wave_sync();
+    }
+  };
+  auto step = [&](uint32_t t, bool act) {
     const uint32_t slot = x & (kM - 1);
     const uint32_t s = sm.sym[slot];
     const uint32_t e = sm.fc[s];
     const uint32_t xs = x >> kProbBits;
     const uint32_t xn = __umul24(e >> 16, xs) + xs + slot - (e & 0xFFFu);
     const bool need = act && xn < kL;
-    const uint64_t m = __ballot(need);
-    const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, rp));
-    uint32_t wd = ring16[pos & 2047];
+    const uint64_t m = __builtin_amdgcn_ballot_w64(need);
+    const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(G == 64 || h == 0 ? mlo : 0u, rp));
+    uint32_t wd = ring16[(pos & (2 * kChunkW - 1))];
     __asm__ volatile("" : "+v"(wd));  // read for every lane: keeps the update branch-free
     const uint32_t xa = act ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
-    rp += (uint32_t)__popcll(m);
-    if (act) dst[i] = (uint8_t)s;
-    i += W;
+    rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
+    sm.stage[act ? (t - t0) * W + g : 16 * G] = (uint8_t)s;  // idle lanes: a spare byte
+  };
+  // main loop: steps where every state of both groups has a symbol, kU at a
+  // time with one check; then the ragged tail one step at a time
+  const uint32_t my_full = on ? n / W : 0;
+  const uint32_t t_full =
+      uniform(G == 64 ? my_full : min(my_full, (uint32_t)__shfl_xor(my_full, 32, 64))) & ~(kU - 1);
+  uint32_t t = 0;
+  if (W == G) {  // every lane holds a state: no per-lane activity in the main loop
+    for (; t < t_full; t += kU) {
+      prepare(t, kU);
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) step(t + u, true);
+    }
+  } else {
+    for (; t < t_full; t += kU) {
+      prepare(t, kU);
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) step(t + u, lane_on);
+    }
   }
-  const bool bad = rp - hw != nwords || (lane_on && x != kL);
-  return __ballot(bad) == 0;
+  for (; t < nsteps; t++) {
+    prepare(t, 1);
+    step(t, lane_on && g + t * W < n);
+  }
+  wave_sync();
+  if (on) flush(nsteps);
+  if (on && (rp - hw != nwords || (g < W && x != kL))) bad = true;
+  return grp_any<G>(bad, h);
 }
 
-// Kernel (a): grid (n_plan, 3), one wavefront per (block, stream).  Decodes
-// LIT into lit + plan_index * B, LEN into lens + 4 * seq_base and OFF into
-// offs + ow * seq_base, and records where the block's bytes will live.
-__global__ __launch_bounds__(64) void k_rans(DecodeArgs a) {
-  __shared__ RansSmem sm;
-  const uint32_t i = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
-  if (a.n_plan_dev && i >= *a.n_plan_dev) return;
-  const PlanEntry pe = a.plan[i];
+// Kernel (a): grid (ceil(n_plan / (64/G)), 3); each wavefront decodes stream
+// t of 64/G consecutive plan entries.  LIT goes to lit + plan_index * B, LEN
+// to lens + 4 * seq_base and OFF to offs + ow * seq_base; raw streams are
+// left in place (the expansion reads them there).  Also records where each
+// block's bytes will live.
+template <uint32_t G>
+__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int level) {
+  __shared__ RansGroup<G> sm[64 / G];
+  const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
+  if (level >= 0) {  // the level's plan range, from device memory
+    plan_lo = a.lvl_dev[level];
+    plan_hi = a.lvl_dev[level + 1];
+  } else if (a.n_plan_dev) {
+    plan_hi = *a.n_plan_dev;
+  }
+  const uint32_t i = plan_lo + blockIdx.x * (64 / G) + h;
+  bool on = i < plan_hi;
+  if (!__ballot(on)) return;
+  const PlanEntry pe = on ? a.plan[i] : PlanEntry{0, 0, 0};
   const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
-  const uint64_t pay = ld64(be);
-  if (t == 0 && lane == 0) a.loc[pe.block] = a.dst_base + pe.dst;
+  const uint64_t pay = on ? ld64(be) : 0;
+  if (on && t == 0 && g == 0) a.loc[pe.block] = a.dst_base + pe.dst;
   const uint8_t* d = a.arch + pay + kSDesc * t;
-  const uint32_t mode = d[0], n = ld32(d + 4), clen = ld32(d + 8), off = ld32(d + 12);
+  uint32_t mode = 0, n = 0, clen = 0, off = 0;
+  if (on) {
+    mode = d[0];
+    n = ld32(d + 4);
+    clen = ld32(d + 8);
+    off = ld32(d + 12);
+  }
+  on = on && mode != 0;
+  if (!__ballot(on)) return;  // raw streams are read in place by the expansion
   uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
                : t == 1 ? a.lens + 4ull * pe.seq_base
                         : a.offs + (uint64_t)a.ow * pe.seq_base;
   const uint8_t* src = a.arch + pay + off;
-  if (mode == 0) return;  // raw streams are read in place by the expansion
-  if (!rans_decode_wave(src, clen, n, a.W, dst, sm, lane) && lane == 0) flag(a.err, kErrCorrupt);
+  if (rans_decode_group<G>(src, clen, n, a.W, dst, sm[h], g, h, on) && g == 0) flag(a.err, kErrCorrupt);
 }
 
 // ---------------------------------------------------------------------------
-// Match layer: expansion of one block by a workgroup of kTile threads.
+// Match layer: expansion of one block by a workgroup of kThreads threads.
 //
-// Sequences are taken kTile at a time (one per thread).  A workgroup scan of
-// L_k + M_k and L_k gives every sequence its block-relative start and its
-// first literal, and each thread classifies its sequence's source once: a
-// match byte i of sequence k reads absolute position O_k + (i mod d_k), with
-// d_k = (match start) - O_k, so overlapping matches repeat with that period
-// and every source lies before the match.  When all of a match's source
-// bytes sit in one earlier block (found through the location table) or in an
-// earlier tile of this block, a single base address serves every byte.
-// Then every thread produces 16 contiguous output bytes at a time: one binary
-// search for the first byte's sequence, then a forward walk; literal and
-// match bytes each cost one address and one byte load, and a whole aligned
-// chunk is written as one 16-byte store.  Sources that span blocks, or lie
-// inside the tile being produced, take the slow path: follow the source back
-// (to a literal, an earlier tile or an earlier block) -- each step moves
-// strictly backwards, so the walk ends.
+// Sequences are taken 2*kThreads at a time (two per thread, so a 16 KiB
+// block is usually one tile).  A workgroup scan of L_k + M_k and L_k gives
+// every sequence its block-relative start and its first literal.  Match byte
+// i of sequence k reads absolute position O_k + (i mod d_k), d_k = (match
+// start) - O_k, so all of a match's bytes come from its source span
+// [O_k, O_k + min(M_k, d_k)), which lies before the match.  Each span is
+// resolved to one address in memory whenever it can be:
+//   * inside one earlier block: that block's location (the block's
+//     dependency list and locations are cached in LDS once per block);
+//   * inside an earlier tile of this block: the output itself;
+//   * inside this tile: pointer jumping over sequences.  A span inside a
+//     literal run resolves to the literal stream; a span inside one period
+//     of another match's bytes points at that match's span, and pointers are
+//     doubled (a pointer to a pointer becomes one) until each reaches a
+//     resolved span, so a chain of n such matches takes log2(n) rounds.
+// Output is then produced in 16-byte chunks: a chunk of one literal run or
+// of one resolved, non-wrapping match is a copy of five aligned dwords; the
+// others are assembled byte by byte, every byte's address first and then the
+// loads together.  Spans that straddle sequences or blocks take the slow
+// path: follow the source back until it reaches a literal, a resolved span,
+// an earlier tile or an earlier block; each step moves strictly backwards.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kPoison = 1u, kSlow = 2u;
+constexpr uint32_t kPoison = 1u, kSlow = 2u, kPend = 4u, kExt = 8u;
+constexpr uint32_t kUnres = kPoison | kSlow | kPend;  // flags of a span without an address
+constexpr uint32_t kDepCache = 256;  // dependency locations cached in LDS per block
+constexpr uint32_t kMaxJumps = 12;   // pointer-doubling rounds (chains up to 4096)
 
-template <uint32_t kTile>
+template <uint32_t kThreads>
 struct ExpandSmem {
-  static constexpr uint32_t kRound = 4 * kTile;  // chunks sorted per round
-  uint32_t list[kRound]; // chunk << 8 | sequence: copy chunks first, per-byte chunks from the back
-  uint32_t nvec, nbyte;
-  uint32_t dst[kTile];   // block-relative start of the sequence
-  uint32_t lm[kTile];    // L | M << 16
-  uint32_t dist[kTile];  // match start - O
-  uint32_t flags[kTile]; // kPoison, kSlow
-  uint64_t O[kTile];
-  uint64_t lit[kTile];   // address of the sequence's first literal
-  uint64_t mbase[kTile]; // address of absolute position 0 for this match's source
-  uint32_t scan[8];
+  static constexpr uint32_t kSeq = 2 * kThreads;    // sequences per tile (two per thread)
+  static constexpr uint32_t kRound = 4 * kThreads;  // 16-byte chunks sorted per round
+  static constexpr uint32_t kSeqBits = kThreads <= 64 ? 7 : kThreads <= 128 ? 8 : kThreads <= 256 ? 9 : 10;
+  uint32_t list[kRound];  // chunk << kSeqBits | sequence: copy chunks first, per-byte chunks from the back
+  uint32_t cseq[kRound];  // sequence holding each chunk's first byte
+  uint32_t nvec, nbyte, carry;
+  uint32_t dst[kSeq];     // block-relative start of the sequence
+  uint32_t lm[kSeq];      // L | M << 16
+  uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
+  uint32_t dfl[kSeq];     // min(d, 2^24 - 1) | flags << 24
+  uint32_t win[kSeq];     // readable bytes around src0: back (0..3) | forward << 2
+  uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
+  uint64_t O[kSeq];
+  uint64_t src0[kSeq];    // address of the first byte of a resolved span
+  uint32_t deps[kDepCache];
+  uint64_t dloc[kDepCache];  // location of each cached dependency's first byte
+  uint32_t scan[16];
 };
 
-// Inclusive scans of a and b over the workgroup (kTile threads) and totals.
-template <uint32_t kTile>
+// Inclusive scans of a and b over the workgroup (kThreads threads) and totals.
+template <uint32_t kThreads>
 __device__ __forceinline__ void wg_scan2(uint32_t a, uint32_t b, uint32_t& ia, uint32_t& ib,
                                          uint32_t& ta, uint32_t& tb, uint32_t* sh) {
-  constexpr uint32_t kW = kTile / 64;
+  constexpr uint32_t kW = kThreads / 64;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   a = wave_incl_sum(a, lane);
   b = wave_incl_sum(b, lane);
@@ -244,21 +389,52 @@ __device__ __forceinline__ void wg_scan2(uint32_t a, uint32_t b, uint32_t& ia, u
   __syncthreads();
   if (lane == 63) {
     sh[w] = a;
-    sh[4 + w] = b;
+    sh[8 + w] = b;
   }
   __syncthreads();
   uint32_t oa = 0, ob = 0;
-  for (uint32_t j = 0; j < w; j++) {
-    oa += sh[j];
-    ob += sh[4 + j];
-  }
   ta = tb = 0;
   for (uint32_t j = 0; j < kW; j++) {
+    if (j < w) {
+      oa += sh[j];
+      ob += sh[8 + j];
+    }
     ta += sh[j];
-    tb += sh[4 + j];
+    tb += sh[8 + j];
   }
   ia = a + oa;
   ib = b + ob;
+}
+
+// In place: v[j] = max(carry, every value up to and including this one) over
+// kThreads threads x 4 consecutive values; returns the overall maximum.
+template <uint32_t kThreads>
+__device__ __forceinline__ uint32_t wg_max_scan4(uint32_t (&v)[4], uint32_t carry, uint32_t* sh) {
+  constexpr uint32_t kW = kThreads / 64;
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v[1] = max(v[1], v[0]);
+  v[2] = max(v[2], v[1]);
+  v[3] = max(v[3], v[2]);
+  uint32_t t = v[3];
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(t, d, 64);
+    if (lane >= d) t = max(t, y);
+  }
+  uint32_t before = __shfl_up(t, 1, 64);
+  if (lane == 0) before = 0;
+  __syncthreads();
+  if (lane == 63) sh[w] = t;
+  __syncthreads();
+  uint32_t pw = carry, all = carry;
+  for (uint32_t j = 0; j < kW; j++) {
+    if (j < w) pw = max(pw, sh[j]);
+    all = max(all, sh[j]);
+  }
+  before = max(before, pw);
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) v[j] = max(v[j], before);
+  return all;
 }
 
 __device__ __forceinline__ uint32_t find_seq(const uint32_t* sdst, uint32_t cnt, uint32_t p) {
@@ -270,53 +446,81 @@ __device__ __forceinline__ uint32_t find_seq(const uint32_t* sdst, uint32_t cnt,
   return lo;
 }
 
-__device__ __forceinline__ bool dep_listed(const uint32_t* deps, uint32_t cnt, uint32_t c) {
+// Index of c in the ascending list, or -1.
+__device__ __forceinline__ int dep_index(const uint32_t* deps, uint32_t cnt, uint32_t c) {
   uint32_t lo = 0, hi = cnt;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
     uint32_t v = deps[mid];
-    if (v == c) return true;
+    if (v == c) return (int)mid;
     if (v < c) lo = mid + 1; else hi = mid;
   }
-  return false;
+  return -1;
 }
 
 struct BlockCtx {
   uint64_t bs;       // absolute start of the block
-  uint32_t blen, n_lit, d0, cnt;
+  uint32_t blen, n_lit, d0, cnt, dep_cnt;
   uint8_t* out;      // the block's first byte
+  const uint8_t* lit;  // the block's literal stream
   bool ext_ok;
 };
 
-// Slow path: the byte at block-relative p, following sources back.
-template <uint32_t kTile>
-__device__ uint8_t resolve_slow(const DecodeArgs& a, const ExpandSmem<kTile>& sm, const BlockCtx& c,
-                                uint32_t p, uint32_t& n_ext) {
+// Location of the first byte of earlier block blk (a listed dependency, so
+// usually in the LDS cache).
+template <uint32_t kThreads>
+__device__ __forceinline__ uint64_t dep_loc(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
+                                            uint32_t dep_cnt, uint64_t blk) {
+  const int di = dep_cnt <= kDepCache ? dep_index(sm.deps, dep_cnt, (uint32_t)blk) : -1;
+  return di >= 0 ? sm.dloc[di] : a.loc[blk];
+}
+
+// Slow path: the address of the byte at block-relative p, following sources
+// back to a literal, a resolved span, an earlier tile of this block or an
+// earlier block; null when the byte is to be written as zero (a failed
+// format rule, or an earlier block that was never published).  Reads only
+// LDS (and the location table for a dependency beyond the cache).
+template <uint32_t kThreads>
+__device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
+                                       const BlockCtx& c, uint32_t p, uint32_t& n_ext) {
   for (;;) {
     const uint32_t s = find_seq(sm.dst, c.cnt, p);
-    if (sm.flags[s] & kPoison) return 0;
+    const uint32_t fl = sm.dfl[s] >> 24;
+    if (fl & kPoison) return nullptr;
     const uint32_t r = p - sm.dst[s];
     const uint32_t Ls = sm.lm[s] & 0xFFFFu;
-    if (r < Ls) return *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
-    const uint32_t ii = r - Ls, d = sm.dist[s];
-    const uint64_t src = sm.O[s] + (ii < d ? ii : ii % d);
+    if (r < Ls) return c.lit + sm.lit[s] + r;
+    const uint32_t ii = r - Ls, d = sm.dfl[s] & 0xFFFFFFu;
+    const uint32_t im = ii < d ? ii : ii % d;
+    if (!(fl & kUnres)) {
+      if (fl & kExt) n_ext++;
+      return reinterpret_cast<const uint8_t*>(sm.src0[s] + im);
+    }
+    const uint64_t src = sm.O[s] + im;
     if (src < c.bs) {
-      if (!c.ext_ok) return 0;  // a dependency never published: read nothing
-      const uint64_t blk = src / a.B;
+      if (!c.ext_ok) return nullptr;
       n_ext++;
-      return reinterpret_cast<const uint8_t*>(a.loc[blk])[src - blk * a.B];
+      const uint64_t blk = src / a.B;
+      return reinterpret_cast<const uint8_t*>(dep_loc<kThreads>(a, sm, c.dep_cnt, blk)) + (src - blk * a.B);
     }
     const uint32_t q = (uint32_t)(src - c.bs);
-    if (q < c.d0) return c.out[q];
+    if (q < c.d0) return c.out + q;
     p = q;
   }
 }
 
-// Expands plan entry i.  Sources in earlier blocks must be complete and
-// visible (unless ext_ok is false, after a timed-out wait).
-template <uint32_t kTile>
-__device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kTile>& sm,
+__device__ __forceinline__ uint32_t win_pack(uint64_t back, uint64_t fwd) {
+  return (uint32_t)(back < 3 ? back : 3) | ((uint32_t)fwd << 2);
+}
+
+// Expands plan entry i with kThreads threads.  Sources in earlier blocks must
+// be complete and visible (unless ext_ok is false, after a timed-out wait).
+template <uint32_t kThreads>
+__device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kThreads>& sm,
                                              bool ext_ok = true) {
+  constexpr uint32_t kSeq = ExpandSmem<kThreads>::kSeq, kRound = ExpandSmem<kThreads>::kRound;
+  constexpr uint32_t kSB = ExpandSmem<kThreads>::kSeqBits, kSM = (1u << kSB) - 1;
+  static_assert(kSeq <= (1u << kSB), "sequence index must fit its field");
   const uint32_t tid = threadIdx.x;
   const PlanEntry pe = a.plan[i];
   const uint32_t b = pe.block;
@@ -324,178 +528,375 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const uint64_t pay = ld64(be);
   const uint32_t n_seq = ld32(be + 12), dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
   const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
+  // each stream is read in place when stored raw, else from its decoded copy
+  const uint8_t* pl = a.arch + pay;
   BlockCtx c;
-  c.n_lit = ld32(a.arch + pay + 4);
+  c.n_lit = ld32(pl + 4);
   c.bs = (uint64_t)b * a.B;
   c.blen = (uint32_t)((a.n_total - c.bs) < a.B ? (a.n_total - c.bs) : a.B);
   c.out = reinterpret_cast<uint8_t*>(a.dst_base + pe.dst);
   c.ext_ok = ext_ok;
-  // each stream is read in place when stored raw, else from its decoded copy
-  const uint8_t* pl = a.arch + pay;
-  const uint8_t* lit = pl[0] == 0 ? pl + ld32(pl + 12) : a.lit + (uint64_t)i * a.B;
+  c.dep_cnt = dep_cnt;
+  c.lit = pl[0] == 0 ? pl + ld32(pl + 12) : a.lit + (uint64_t)i * a.B;
   const uint8_t* lens = pl[16] == 0 ? pl + ld32(pl + 28) : a.lens + 4ull * pe.seq_base;
   const uint8_t* offs = pl[32] == 0 ? pl + ld32(pl + 44) : a.offs + (uint64_t)a.ow * pe.seq_base;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
-  constexpr uint32_t kRound = ExpandSmem<kTile>::kRound;
+  // the block's dependencies and their locations, once, in LDS
+  const bool cached = dep_cnt <= kDepCache;
+  for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) {
+    const uint32_t d = deps[j];
+    sm.deps[j] = d;
+    sm.dloc[j] = ext_ok ? a.loc[d] : 0;
+  }
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
-  for (uint32_t t0 = 0; t0 < n_seq; t0 += kTile) {
-    const uint32_t k = t0 + tid;
-    const bool valid = k < n_seq;
-    uint32_t L = 0, M = 0;
-    uint64_t O = 0;
-    if (valid) {
-      const uint32_t lm = ld32(lens + 4ull * k);
-      L = lm & 0xFFFFu;
-      M = lm >> 16;
-      O = a.ow == 4 ? (uint64_t)ld32(offs + 4ull * k) : ld64(offs + 8ull * k);
+  for (uint32_t t0 = 0; t0 < n_seq; t0 += kSeq) {
+    // ---- two sequences per thread: tokens, scans, first classification
+    uint32_t L[2] = {0, 0}, M[2] = {0, 0};
+    uint64_t O[2] = {0, 0};
+#pragma unroll
+    for (uint32_t h = 0; h < 2; h++) {
+      const uint32_t k = t0 + 2 * tid + h;
+      if (k < n_seq) {
+        const uint32_t lm = ld32(lens + 4ull * k);
+        L[h] = lm & 0xFFFFu;
+        M[h] = lm >> 16;
+        O[h] = a.ow == 4 ? (uint64_t)ld32(offs + 4ull * k) : ld64(offs + 8ull * k);
+      }
     }
     uint32_t ip, il, tp, tl;
-    wg_scan2<kTile>(L + M, L, ip, il, tp, tl, sm.scan);
-    const uint32_t dst = carry_pos + ip - (L + M);
-    const uint32_t litk = carry_lit + il - L;
+    wg_scan2<kThreads>(L[0] + M[0] + L[1] + M[1], L[0] + L[1], ip, il, tp, tl, sm.scan);
     const uint32_t d0 = carry_pos;
-    uint32_t fl = 0, dist = 0;
-    uint64_t mbase = 0;
-    if (valid) {
-      const uint64_t mabs = c.bs + dst + L;
-      if ((uint64_t)dst + L + M > c.blen || (uint64_t)litk + L > c.n_lit) fl = kPoison;
-      if (M && !fl) {
-        if (O >= mabs) {
-          fl = kPoison;
-        } else {
-          dist = (uint32_t)((mabs - O) < 0xFFFFFFFFull ? (mabs - O) : 0xFFFFFFFFull);
-          const uint64_t src_hi = O + (M < dist ? M : dist);  // bytes actually read
-          if (O < c.bs) {
-            // every earlier block the source touches must be a listed dependency
-            const uint64_t end = src_hi < c.bs ? src_hi : c.bs;
-            for (uint64_t blk = O / a.B; blk * a.B < end; blk++)
-              if (!dep_listed(deps, dep_cnt, (uint32_t)blk)) {
-                fl = kPoison;
-                break;
+    c.d0 = d0;
+    c.cnt = (n_seq - t0) < kSeq ? (n_seq - t0) : kSeq;
+    uint32_t pos = carry_pos + ip - (L[0] + M[0] + L[1] + M[1]);
+    uint32_t litk = carry_lit + il - (L[0] + L[1]);
+    uint32_t fl_h[2] = {0, 0};
+#pragma unroll
+    for (uint32_t h = 0; h < 2; h++) {
+      const uint32_t k = t0 + 2 * tid + h, slot = 2 * tid + h;
+      uint32_t fl = 0, dist = 0, win = 0;
+      uint64_t src0 = 0;
+      if (k < n_seq) {
+        const uint64_t mabs = c.bs + pos + L[h];
+        if ((uint64_t)pos + L[h] + M[h] > c.blen || (uint64_t)litk + L[h] > c.n_lit) fl = kPoison;
+        if (M[h] && !fl) {
+          if (O[h] >= mabs) {
+            fl = kPoison;
+          } else {
+            const uint64_t dd = mabs - O[h];
+            dist = (uint32_t)(dd < 0xFFFFFFull ? dd : 0xFFFFFFull);
+            const uint64_t span_end = O[h] + (M[h] < dd ? M[h] : dd);  // bytes actually read
+            // every earlier block the span touches must be a listed
+            // dependency; blocks that lie back to back in memory (always so
+            // in a whole-archive decode) make one contiguous source
+            bool contiguous = ext_ok;
+            uint64_t loc0 = 0;
+            if (O[h] < c.bs) {
+              const uint64_t end = span_end < c.bs ? span_end : c.bs;
+              const uint64_t b0 = O[h] / a.B;
+              for (uint64_t blk = b0; blk * a.B < end; blk++) {
+                const int di = cached ? dep_index(sm.deps, dep_cnt, (uint32_t)blk)
+                                      : dep_index(deps, dep_cnt, (uint32_t)blk);
+                if (di < 0) {
+                  fl = kPoison;
+                  break;
+                }
+                if (contiguous) {
+                  const uint64_t lb = cached ? sm.dloc[di] : a.loc[blk];
+                  if (blk == b0) loc0 = lb;
+                  else contiguous = lb == loc0 + (blk - b0) * a.B;
+                }
               }
-          }
-          if (!fl) {
-            const uint64_t b0 = O / a.B, b1 = (src_hi - 1) / a.B;
-            if (src_hi <= c.bs && b0 == b1 && ext_ok) {
-              mbase = a.loc[b0] - b0 * a.B;  // one earlier block
-              n_ext += M;
-            } else if (O >= c.bs && src_hi - c.bs <= d0) {
-              mbase = (uint64_t)(uintptr_t)c.out - c.bs;  // an earlier tile of this block
-            } else {
-              fl = kSlow;
+            }
+            if (!fl) {
+              const uint64_t b0 = O[h] / a.B;
+              if (span_end <= c.bs && contiguous) {
+                const uint64_t off = O[h] - b0 * a.B;  // earlier blocks, one run of memory
+                const uint64_t nblk = (span_end - 1) / a.B - b0 + 1;
+                src0 = loc0 + off;
+                win = win_pack(off, nblk * a.B - off);
+                fl = kExt;
+                n_ext += M[h];
+              } else if (O[h] >= c.bs && span_end - c.bs <= d0) {
+                const uint64_t q = O[h] - c.bs;  // an earlier tile of this block
+                src0 = (uint64_t)(uintptr_t)c.out + q;
+                win = win_pack(q, c.blen - q);
+              } else if (O[h] >= c.bs + d0) {
+                fl = kPend;  // inside this tile: resolved below
+              } else {
+                fl = kSlow;
+              }
             }
           }
+        } else if (!M[h] && O[h] != 0) {
+          bad = true;
         }
-      } else if (!M && O != 0) {
-        bad = true;
+        if (fl & kPoison) bad = true;
       }
-      if (fl & kPoison) bad = true;
+      fl_h[h] = fl;
+      sm.dst[slot] = pos;
+      sm.lm[slot] = L[h] | (M[h] << 16);
+      sm.lit[slot] = litk;
+      sm.dfl[slot] = dist | (fl << 24);
+      sm.win[slot] = win;
+      sm.O[slot] = O[h];
+      sm.src0[slot] = src0;
+      pos += L[h] + M[h];
+      litk += L[h];
     }
-    sm.dst[tid] = dst;
-    sm.lm[tid] = L | (M << 16);
-    sm.dist[tid] = dist;
-    sm.flags[tid] = fl;
-    sm.O[tid] = O;
-    sm.lit[tid] = (uint64_t)(uintptr_t)lit + litk;
-    sm.mbase[tid] = mbase;
     __syncthreads();
-    c.d0 = d0;
-    c.cnt = (n_seq - t0) < kTile ? (n_seq - t0) : kTile;
+    // ---- spans inside this tile: a literal run resolves at once; a span
+    // inside one period of another match points at that match's span
+#pragma unroll
+    for (uint32_t h = 0; h < 2; h++) {
+      if (!(fl_h[h] & kPend)) continue;
+      const uint32_t slot = 2 * tid + h;
+      const uint32_t q = (uint32_t)(O[h] - c.bs);
+      const uint32_t dist = sm.dfl[slot] & 0xFFFFFFu;
+      const uint32_t sl = M[h] < dist ? M[h] : dist;
+      const uint32_t j = find_seq(sm.dst, c.cnt, q);
+      const uint32_t r = q - sm.dst[j], Lj = sm.lm[j] & 0xFFFFu, Mj = sm.lm[j] >> 16;
+      uint32_t fl = kSlow, ptr = 0;
+      uint64_t src0 = 0;
+      uint32_t win = 0;
+      const bool j_ok = !((sm.dfl[j] >> 24) & kPoison);  // a poisoned run is written as zeros
+      if (j_ok && r + sl <= Lj) {
+        const uint32_t lp = sm.lit[j] + r;
+        src0 = (uint64_t)(uintptr_t)(c.lit + lp);
+        win = win_pack(lp, (uint64_t)(c.n_lit - lp) + 4);  // literal streams have readable slack
+        fl = 0;
+      } else if (j_ok && r >= Lj) {
+        const uint32_t off = r - Lj, dj = sm.dfl[j] & 0xFFFFFFu;
+        if (off + sl <= Mj && (Mj <= dj || off / dj == (off + sl - 1) / dj)) {
+          ptr = (j << 16) | (Mj <= dj ? off : off % dj);
+          fl = kPend;
+        }
+      }
+      sm.dfl[slot] = dist | (fl << 24);
+      sm.ptr[slot] = ptr;
+      sm.src0[slot] = src0;
+      sm.win[slot] = win;
+      fl_h[h] = fl;
+    }
+    // ---- pointer doubling
+    for (uint32_t round = 0;; round++) {
+      const bool pend = (fl_h[0] | fl_h[1]) & kPend;
+      if (!__syncthreads_or(pend)) break;
+      uint32_t nfl[2] = {fl_h[0], fl_h[1]}, nptr[2] = {0, 0}, nwin[2] = {0, 0};
+      uint64_t nsrc[2] = {0, 0};
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        if (!(fl_h[h] & kPend)) continue;
+        const uint32_t pt = sm.ptr[2 * tid + h], j = pt >> 16, off = pt & 0xFFFFu;
+        const uint32_t fj = sm.dfl[j] >> 24;
+        if (!(fj & kUnres)) {
+          const uint32_t wj = sm.win[j];
+          nsrc[h] = sm.src0[j] + off;
+          nwin[h] = win_pack((wj & 3u) + off, (wj >> 2) - off);
+          nfl[h] = fj & kExt;
+          if (fj & kExt) n_ext += M[h];
+        } else if ((fj & kPend) && round + 1 < kMaxJumps) {
+          const uint32_t pj = sm.ptr[j];
+          nptr[h] = (pj & 0xFFFF0000u) | ((pj & 0xFFFFu) + off);
+        } else {
+          nfl[h] = kSlow;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        if (!(fl_h[h] & kPend)) continue;
+        const uint32_t slot = 2 * tid + h;
+        const uint32_t dist = sm.dfl[slot] & 0xFFFFFFu;
+        sm.dfl[slot] = dist | (nfl[h] << 24);
+        if (nfl[h] & kPend) {
+          sm.ptr[slot] = nptr[h];
+        } else if (!(nfl[h] & kUnres)) {
+          sm.src0[slot] = nsrc[h];
+          sm.win[slot] = nwin[h];
+        }
+        fl_h[h] = nfl[h];
+      }
+    }
+    // slow sequences' match bytes, numbered: slot k's end in sm.ptr (the
+    // pointers are no longer needed)
+    uint32_t n_slow = 0;
+    {
+      const uint32_t c0 = (fl_h[0] & kSlow) ? M[0] : 0u, c1 = (fl_h[1] & kSlow) ? M[1] : 0u;
+      uint32_t is, iz, ts, tz;
+      wg_scan2<kThreads>(c0 + c1, 0u, is, iz, ts, tz, sm.scan);
+      sm.ptr[2 * tid] = is - c1;
+      sm.ptr[2 * tid + 1] = is;
+      n_slow = ts;
+      __syncthreads();
+    }
     const uint64_t d1w = (uint64_t)carry_pos + tp;
     const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
-    // Output is produced in 16-byte chunks, 4 per thread per round.  Each
-    // round first sorts its chunks: a chunk whose 16 bytes come from one
-    // contiguous source (all literals of one sequence, or one match with no
-    // period wrap) is copied with five aligned dword loads and one 16-byte
-    // store; the others go through the per-byte path.  Sorting keeps the two
-    // kinds of work in separate passes, so a wavefront does not pay for both.
+    // ---- output in 16-byte chunks, sorted per round: copy chunks (one
+    // literal run, or one resolved match with no period wrap, whose five
+    // aligned source dwords are readable) first, per-byte chunks after, so a
+    // wavefront does not pay for both kinds of work
     const uint32_t base = d0 & ~15u;
     const uint32_t nch = d1 > base ? (d1 - base + 15) / 16 : 0;
-    const bool pow2 = (a.B & (a.B - 1)) == 0;
     for (uint32_t k0 = 0; k0 < nch; k0 += kRound) {
       const uint32_t kn = nch - k0 < kRound ? nch - k0 : kRound;
+      // the sequence holding each chunk's first byte: every sequence marks
+      // the first chunk whose first byte is at or after its start, then a
+      // running maximum over the chunks fills the rest
+      for (uint32_t j = tid; j < kRound; j += kThreads) sm.cseq[j] = 0;
       if (tid == 0) {
         sm.nvec = 0;
         sm.nbyte = 0;
+        if (k0 == 0) sm.carry = 0;
       }
       __syncthreads();
-      for (uint32_t k = k0 + tid; k < k0 + kn; k += kTile) {
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        const uint32_t slot = 2 * tid + h;
+        if (slot < c.cnt) {
+          const uint32_t ds = sm.dst[slot];
+          const uint32_t cm = ds <= d0 ? 0u : (ds - base + 15) / 16;
+          if (cm >= k0 && cm < k0 + kn) atomicMax(&sm.cseq[cm - k0], slot);
+        }
+      }
+      __syncthreads();
+      {
+        uint32_t v[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++) v[j] = sm.cseq[4 * tid + j];
+        const uint32_t carry = sm.carry;
+        const uint32_t all = wg_max_scan4<kThreads>(v, carry, sm.scan);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++) sm.cseq[4 * tid + j] = v[j];
+        __syncthreads();
+        if (tid == 0) sm.carry = all;
+      }
+      __syncthreads();
+      for (uint32_t k = k0 + tid; k < k0 + kn; k += kThreads) {
         const uint32_t cb = base + 16 * k;
         const uint32_t p0 = cb < d0 ? d0 : cb;
         const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-        const uint32_t sq = find_seq(sm.dst, c.cnt, p0);
-        bool vec = aligned && p0 == cb && pe1 == cb + 16 && !(sm.flags[sq] & kPoison);
+        const uint32_t sq = sm.cseq[k - k0];
+        const uint32_t fl = sm.dfl[sq] >> 24;
+        bool vec = aligned && p0 == cb && pe1 == cb + 16 && !(fl & kPoison);
         if (vec) {
           const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
           const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
           if (cb + 16 > end_s) {
             vec = false;
           } else if (r0 + 16 <= Ls) {
-            vec = true;  // all literals (the literal scratch has readable slack)
-          } else if (r0 >= Ls && sm.flags[sq] == 0 && pow2) {
-            // the five aligned dwords must stay inside the source block's bytes
-            const uint32_t ii0 = r0 - Ls;
-            const uint64_t src = sm.O[sq] + ii0;
-            const uint32_t off = (uint32_t)(src & (a.B - 1));
-            const uint32_t shp = (uint32_t)((sm.mbase[sq] + src) & 3);
-            const uint32_t limit = src >= c.bs ? c.blen : a.B;
-            vec = ii0 + 16 <= sm.dist[sq] && off >= shp && off - shp + 20 <= limit;
+            vec = true;  // all literals (stream data has readable slack)
+          } else if (r0 >= Ls && !(fl & kUnres)) {
+            const uint32_t ii0 = r0 - Ls, w = sm.win[sq];
+            const uint32_t shp = (uint32_t)((sm.src0[sq] + ii0) & 3);
+            vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (w & 3u) >= shp && ii0 + 20 <= (w >> 2) + shp;
           } else {
             vec = false;
           }
         }
-        const uint32_t e = (k << 8) | sq;
+        const uint32_t e = (k << kSB) | sq;
         if (vec) sm.list[atomicAdd(&sm.nvec, 1u)] = e;
         else sm.list[kRound - 1 - atomicAdd(&sm.nbyte, 1u)] = e;
       }
       __syncthreads();
       const uint32_t nv = sm.nvec, nby = sm.nbyte;
-      for (uint32_t ei = tid; ei < nv; ei += kTile) {
-        const uint32_t e = sm.list[ei], k = e >> 8, sq = e & 0xFFu;
-        const uint32_t cb = base + 16 * k;
-        const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
-        const uint8_t* src = r0 < Ls ? reinterpret_cast<const uint8_t*>(sm.lit[sq] + r0)
-                                     : reinterpret_cast<const uint8_t*>(sm.mbase[sq] + sm.O[sq] + (r0 - Ls));
-        const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(src - sh);
-        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
-        *reinterpret_cast<uint4*>(c.out + cb) =
-            make_uint4(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
-                       __builtin_amdgcn_alignbyte(w3, w2, sh), __builtin_amdgcn_alignbyte(w4, w3, sh));
+      // copy chunks: all loads of this thread's chunks first, then the stores
+      uint32_t w[4][5];
+      uint32_t shv[4];
+      uint32_t cbv[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t ei = tid + j * kThreads;
+        shv[j] = 0;
+        cbv[j] = 0xFFFFFFFFu;
+        if (ei < nv) {
+          const uint32_t e = sm.list[ei], k = e >> kSB, sq = e & kSM;
+          const uint32_t cb = base + 16 * k;
+          const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
+          const uint8_t* src = r0 < Ls ? c.lit + sm.lit[sq] + r0
+                                       : reinterpret_cast<const uint8_t*>(sm.src0[sq] + (r0 - Ls));
+          const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
+          const uint32_t* wp = reinterpret_cast<const uint32_t*>(src - sh);
+#pragma unroll
+          for (uint32_t q = 0; q < 5; q++) w[j][q] = wp[q];
+          shv[j] = sh;
+          cbv[j] = cb;
+        }
       }
-      for (uint32_t ei = tid; ei < nby; ei += kTile) {
-        const uint32_t e = sm.list[kRound - 1 - ei], k = e >> 8;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        if (cbv[j] != 0xFFFFFFFFu) {
+          const uint32_t sh = shv[j];
+          *reinterpret_cast<uint4*>(c.out + cbv[j]) =
+              make_uint4(__builtin_amdgcn_alignbyte(w[j][1], w[j][0], sh),
+                         __builtin_amdgcn_alignbyte(w[j][2], w[j][1], sh),
+                         __builtin_amdgcn_alignbyte(w[j][3], w[j][2], sh),
+                         __builtin_amdgcn_alignbyte(w[j][4], w[j][3], sh));
+        }
+      }
+      // per-byte chunks: every byte's source address first, then the 16
+      // loads back to back, so their latencies overlap.  The current
+      // sequence's fields stay in registers (LDS is read only when the walk
+      // enters the next sequence), and match bytes step their source offset
+      // by one, wrapping at the period.  Bytes of slow sequences get a
+      // placeholder here; the slow pass below writes them.
+      for (uint32_t ei = tid; ei < nby; ei += kThreads) {
+        const uint32_t e = sm.list[kRound - 1 - ei], k = e >> kSB;
         const uint32_t cb = base + 16 * k;
         const uint32_t p0 = cb < d0 ? d0 : cb;
         const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-        uint32_t s = e & 0xFFu;
-        uint32_t s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
-        uint32_t acc[4] = {0, 0, 0, 0};
+        uint32_t s = e & kSM;
+        uint32_t sd = 0, se = 0, sL = 0, sf = 0, sdist = 1, im = 0;
+        const uint8_t* litp = c.lit;
+        uint64_t src0 = 0;
+        bool started = false;
+        auto view = [&]() {
+          sd = sm.dst[s];
+          se = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+          sL = sm.lm[s] & 0xFFFFu;
+          sf = sm.dfl[s] >> 24;
+          sdist = sm.dfl[s] & 0xFFFFFFu;
+          litp = c.lit + sm.lit[s];
+          src0 = sm.src0[s];
+          started = false;
+        };
+        view();
+        const uint8_t* ad[16];
+        uint32_t zero = 0;
 #pragma unroll
         for (uint32_t j = 0; j < 16; j++) {
           const uint32_t p = cb + j;
-          uint32_t v = 0;
+          const uint8_t* q = nullptr;
           if (p >= p0 && p < pe1) {
-            while (p >= s_end) {
+            while (p >= se) {
               s++;
-              s_end = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
+              view();
             }
-            const uint32_t r = p - sm.dst[s];
-            const uint32_t Ls = sm.lm[s] & 0xFFFFu;
-            const uint32_t f = sm.flags[s];
-            if (f & kPoison) {
-              v = 0;  // a format rule failed: write zeros, read nothing
-            } else if (r < Ls) {
-              v = *reinterpret_cast<const uint8_t*>(sm.lit[s] + r);
-            } else if (f == 0) {
-              const uint32_t ii = r - Ls, d = sm.dist[s];
-              v = *reinterpret_cast<const uint8_t*>(sm.mbase[s] + sm.O[s] + (ii < d ? ii : ii % d));
-            } else {
-              v = resolve_slow<kTile>(a, sm, c, p, n_ext);
+            const uint32_t r = p - sd;
+            if (sf & kPoison) {
+              q = nullptr;  // a format rule failed: write zeros, read nothing
+            } else if (r < sL) {
+              q = litp + r;
+            } else if (!(sf & kUnres)) {
+              if (!started) {
+                const uint32_t ii = r - sL;
+                im = ii < sdist ? ii : ii % sdist;
+                started = true;
+              } else if (++im == sdist) {
+                im = 0;
+              }
+              q = reinterpret_cast<const uint8_t*>(src0 + im);
             }
           }
-          acc[j >> 2] |= v << (8 * (j & 3));
+          zero |= (q == nullptr ? 1u : 0u) << j;
+          ad[j] = q == nullptr ? c.lit : q;  // c.lit is always readable
+        }
+        uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t j = 0; j < 16; j++) {
+          const uint32_t v = *ad[j];
+          acc[j >> 2] |= ((zero >> j) & 1u ? 0u : v) << (8 * (j & 3));
         }
         if (aligned && p0 == cb && pe1 == cb + 16) {
           *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
@@ -507,9 +908,25 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       }
       __syncthreads();
     }
+    // ---- slow pass: the match bytes of slow sequences (spans that straddle
+    // sequences, tiles or non-adjacent blocks), one byte per thread, each
+    // followed back to its origin
+    if (n_slow) {
+      for (uint32_t u = tid; u < n_slow; u += kThreads) {
+        uint32_t lo = 0, hi = c.cnt;  // first slot whose slow-byte end exceeds u
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (sm.ptr[mid] > u) hi = mid; else lo = mid + 1;
+        }
+        const uint32_t Mk = sm.lm[lo] >> 16, Lk = sm.lm[lo] & 0xFFFFu;
+        const uint32_t p = sm.dst[lo] + Lk + (u - (sm.ptr[lo] - Mk));
+        const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
+        c.out[p] = q ? *q : (uint8_t)0;
+      }
+      __syncthreads();
+    }
     carry_pos = (uint32_t)(d1w > 0xFFFFFFFFull ? 0xFFFFFFFFu : d1w);
     carry_lit += tl;
-    __syncthreads();
     if ((uint64_t)carry_pos > c.blen) {
       bad = true;
       break;
@@ -517,20 +934,27 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   }
   if (tid == 0 && (carry_pos != c.blen || carry_lit > c.n_lit)) bad = true;
   if (bad) flag(a.err, kErrCorrupt);
+  // one counter update per block, spread over 16 counters
   n_ext = wave_total(n_ext);
-  if ((tid & 63) == 0 && n_ext) atomicAdd(a.ext_bytes, (unsigned long long)n_ext);
+  __syncthreads();
+  if ((tid & 63) == 0) sm.scan[tid >> 6] = n_ext;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t sum = 0;
+    for (uint32_t w = 0; w < kThreads / 64; w++) sum += sm.scan[w];
+    if (sum) atomicAdd(a.ext_bytes + (b & 15), (unsigned long long)sum);
+  }
 }
 
-// level < 0: plan entries plan_lo + blockIdx.x; else the level's plan range
-// is read from device memory.
-__global__ __launch_bounds__(256) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
-  __shared__ ExpandSmem<256> sm;
+template <uint32_t kThreads>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
+  __shared__ ExpandSmem<kThreads> sm;
   uint32_t i = plan_lo + blockIdx.x;
   if (level >= 0) {
     i = a.lvl_dev[level] + blockIdx.x;
     if (i >= a.lvl_dev[level + 1]) return;
   }
-  expand_block<256>(a, i, sm);
+  expand_block<kThreads>(a, i, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,7 +969,7 @@ __global__ __launch_bounds__(256) void k_expand(DecodeArgs a, uint32_t plan_lo, 
 // writes back this XCD's L2), the wait an acquire load at agent scope.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void decode_stream(const DecodeArgs& a, const PlanEntry& pe, uint32_t i,
-                                              uint32_t t, RansSmem& sm, uint32_t lane) {
+                                              uint32_t t, RansGroup<64>& sm, uint32_t lane) {
   const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
   const uint64_t pay = ld64(be);
   const uint8_t* d = a.arch + pay + kSDesc * t;
@@ -556,13 +980,13 @@ __device__ __forceinline__ void decode_stream(const DecodeArgs& a, const PlanEnt
   const uint8_t* src = a.arch + pay + off;
   if (mode == 0) {
     for (uint32_t j = lane; j < n; j += kWave) dst[j] = src[j];
-  } else if (!rans_decode_wave(src, clen, n, a.W, dst, sm, lane) && lane == 0) {
+  } else if (rans_decode_group<64>(src, clen, n, a.W, dst, sm, lane, 0, true) && lane == 0) {
     flag(a.err, kErrCorrupt);
   }
 }
 
 __global__ __launch_bounds__(64) void k_persist(DecodeArgs a) {
-  __shared__ RansSmem rs;
+  __shared__ RansGroup<64> rs;
   __shared__ ExpandSmem<64> es;
   const uint32_t lane = threadIdx.x;
   const uint32_t n_plan = a.n_plan_dev ? *a.n_plan_dev : a.n_plan;
@@ -742,29 +1166,57 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
 
 }  // namespace
 
-hipError_t launch_rans(const DecodeArgs& a, hipStream_t s) {
-  if (a.n_plan == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rans, dim3(a.n_plan, 3), dim3(64), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_expand_level(const DecodeArgs& a, uint32_t lo, uint32_t hi, hipStream_t s) {
+// Entropy launch over plan entries [lo, hi), or (level >= 0) over that
+// level's range read from device memory with hi - lo entries of capacity.
+static hipError_t launch_rans_any(const DecodeArgs& a, uint32_t lo, uint32_t hi, int level, uint32_t per_wave,
+                                  hipStream_t s) {
   if (hi <= lo) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3(hi - lo), dim3(256), 0, s, a, lo, -1);
+  const uint32_t n = hi - lo;
+  if (per_wave == 0) per_wave = a.W <= 32 ? 2 : 1;
+  if (per_wave == 2 && a.W <= 32)
+    hipLaunchKernelGGL(k_rans<32>, dim3((n + 1) / 2, 3), dim3(64), 0, s, a, lo, hi, level);
+  else
+    hipLaunchKernelGGL(k_rans<64>, dim3(n, 3), dim3(64), 0, s, a, lo, hi, level);
   return hipGetLastError();
 }
 
-hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t grid, hipStream_t s) {
+hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s) {
+  return launch_rans_any(a, lo, hi, -1, per_wave, s);
+}
+
+// One expansion launch: grid blocks from plan_lo, or (level >= 0) the plan
+// range of that level read from device memory; waves = wavefronts per block.
+static hipError_t launch_expand(const DecodeArgs& a, uint32_t grid, uint32_t plan_lo, int level,
+                                uint32_t waves, hipStream_t s) {
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rans, dim3(grid, 3), dim3(64), 0, s, a);
+  switch (waves) {
+    case 2: hipLaunchKernelGGL(k_expand<128>, dim3(grid), dim3(128), 0, s, a, plan_lo, level); break;
+    case 8: hipLaunchKernelGGL(k_expand<512>, dim3(grid), dim3(512), 0, s, a, plan_lo, level); break;
+    default: hipLaunchKernelGGL(k_expand<256>, dim3(grid), dim3(256), 0, s, a, plan_lo, level); break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width,
+hipError_t launch_expand_level(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t waves,
+                               hipStream_t s) {
+  if (hi <= lo) return hipSuccess;
+  return launch_expand(a, hi - lo, lo, -1, waves, s);
+}
+
+// cap: the largest plan length the launch must cover (the length itself is
+// read from device memory)
+hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave, hipStream_t s) {
+  return launch_rans_any(a, 0, cap, -1, per_wave, s);
+}
+
+hipError_t launch_rans_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t per_wave,
+                                 hipStream_t s) {
+  return launch_rans_any(a, 0, width, (int)level, per_wave, s);
+}
+
+hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
                                    hipStream_t s) {
-  if (width == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3(width), dim3(256), 0, s, a, 0u, (int)level);
-  return hipGetLastError();
+  return launch_expand(a, width, 0u, (int)level, waves, s);
 }
 
 hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s) {

@@ -15,16 +15,18 @@ PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not c
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("mode", [1, pytest.param(2, marks=PERSISTENT_SKIP)],
-                         ids=["levels", "persistent"])
-def test_graph_batch_replays(orc, mode):
+@pytest.mark.parametrize("tuning", [dict(mode=1), dict(mode=3),
+                                    dict(mode=3, waves_per_block=8, blocks_per_wg=1),
+                                    pytest.param(dict(mode=2), marks=PERSISTENT_SKIP)],
+                         ids=["levels", "overlap", "overlap-8waves-1stream", "persistent"])
+def test_graph_batch_replays(orc, tuning):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2606_24531_amd import Archive, encode
     x = gen.mixed(3 << 20, 12)
     a = encode(x, block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=8)
     arc = Archive(a, device="cuda:0")
-    bt = arc.batch(500, tuning=dict(mode=mode))
+    bt = arc.batch(500, tuning=tuning)
     for it, (count, max_len, seed) in enumerate([(500, 200_000, 1), (37, 1 << 20, 2),
                                                  (1, 5, 3), (0, 10, 4), (400, 30_000, 5)]):
         lo, hi = gen.seek_requests(len(x), max(count, 1), seed, max_len=max_len)

@@ -43,8 +43,8 @@ def _expect_corrupt(ace, a, mode):
     arc.check()  # the sticky word was cleared by the read
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1],
-                         ids=["persistent", "levels"])
+@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+                         ids=["persistent", "levels", "overlap"])
 def test_damaged_rans_state(ace, orc, mode):
     x = gen.genome(1 << 18, 6)
     a = orc.encode(x, block_size=4096, interleave=32, flags=1)
@@ -55,8 +55,8 @@ def test_damaged_rans_state(ace, orc, mode):
     _expect_corrupt(ace, bad, mode)
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1],
-                         ids=["persistent", "levels"])
+@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+                         ids=["persistent", "levels", "overlap"])
 def test_offset_not_before_destination(ace, orc, mode):
     x = gen.genome(1 << 18, 7)
     a = orc.encode(x, block_size=4096, interleave=32, min_match=20, hash_len=20, flags=2)
@@ -79,8 +79,8 @@ def test_offset_not_before_destination(ace, orc, mode):
         _expect_corrupt(ace, _patch(a, offs["data_at"] + 4 * k, "<I", free[0] * 4096), mode)
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1],
-                         ids=["persistent", "levels"])
+@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+                         ids=["persistent", "levels", "overlap"])
 def test_lengths_that_miss_the_block(ace, orc, mode):
     x = gen.text(1 << 18, 8)
     a = orc.encode(x, block_size=4096, interleave=32, min_match=16, hash_len=16, flags=2)

@@ -29,8 +29,8 @@ def big():
     return x, a, Archive(a, device="cuda:0")
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1],
-                         ids=["persistent", "levels"])
+@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+                         ids=["persistent", "levels", "overlap"])
 def test_full_decode_equals_original(big, mode):
     x, a, arc = big
     out = arc.decode_all(tuning=dict(mode=mode))

@@ -18,8 +18,8 @@ PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not c
 
 torch = pytest.importorskip("torch")
 
-MODES = [pytest.param(dict(mode=2), marks=PERSISTENT_SKIP), dict(mode=1)]
-MODE_IDS = ["persistent", "levels"]
+MODES = [pytest.param(dict(mode=2), marks=PERSISTENT_SKIP), dict(mode=1), dict(mode=3)]
+MODE_IDS = ["persistent", "levels", "overlap"]
 
 
 @pytest.fixture(scope="module")
@@ -88,6 +88,21 @@ def test_decode_all_matches_oracle(dev, ace, archives, case, tuning):
         bad = np.nonzero(np.frombuffer(got, np.uint8) != np.frombuffer(ref, np.uint8))[0]
         pytest.fail("first mismatch at %d (block %d), %d bytes differ" %
                     (bad[0], bad[0] // case[2], bad.size))
+
+
+SHAPES = [dict(mode=3, waves_per_block=2), dict(mode=1, waves_per_block=8, blocks_per_wg=1)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+@pytest.mark.parametrize("tuning", SHAPES, ids=["2waves", "8waves-1stream"])
+def test_decode_all_launch_shapes(dev, ace, archives, case, tuning):
+    """The other expansion workgroup sizes (128 and 512 threads, so other
+    tile sizes) and one entropy stream per wavefront give the same bytes."""
+    x, a, ref = archives[case]
+    arc = ace.Archive(a, device=dev)
+    out = arc.decode_all(tuning=tuning)
+    arc.check()
+    assert _host(out) == ref
 
 
 @pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)

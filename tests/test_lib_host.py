@@ -56,6 +56,21 @@ def test_encoder_edge_sizes(orc, lib):
         assert orc.decode(a) == x
 
 
+def test_two_streams_per_wave_needs_narrow_interleave(lib):
+    x = gen.text(50_000, 2)
+    a = lib.encode(x, block_size=4096, interleave=64, min_match=8, hash_len=8)
+    rc, h = _open(lib, a)
+    assert rc == 0
+    L = lib.lib()
+    dummy = C.c_void_p(0x1000)
+    ws = C.c_uint64()
+    assert L.ace_workspace_bytes(h, None, 0, C.byref(ws)) == 0
+    t = lib.Tuning(0, 2, 0, 0, 1)
+    assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(t), None) == lib.E_ARG
+    assert b"interleave" in L.ace_last_error()
+    L.ace_archive_close(h)
+
+
 def _open(lib, a: bytes):
     L = lib.lib()
     h = C.c_void_p()
@@ -115,6 +130,9 @@ def test_argument_errors_before_device_work(lib):
     t = lib.Tuning(0, 0, 0, 0, 2)
     assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(t), None) == lib.E_ARG
     assert b"disabled" in L.ace_last_error()
+    for bad_t in [lib.Tuning(3, 0, 0, 0, 1), lib.Tuning(0, 3, 0, 0, 1), lib.Tuning(0, 0, 1, 0, 1),
+                  lib.Tuning(0, 0, 0, 0, 4)]:
+        assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(bad_t), None) == lib.E_ARG
     r = np.array([0, 100_001], dtype=np.uint64)
     assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), 1, C.byref(ws)) == lib.E_RANGE
     L.ace_archive_close(h)
