@@ -1,8 +1,10 @@
 """Benchmark: two-layer (rANS + absolute-offset match) full-archive decode.
 
 Workload: 256 MiB of seeded synthetic FASTQ-like records, 16 KiB blocks,
-32-way interleaved rANS with 12-bit frequencies, encoded on the host by the
-library encoder; the archive is resident in HBM before timing starts.  One
+interleaved rANS with 12-bit frequencies (the interleave width W and the
+launch shape picked by the autotuner on a 32 MiB sample unless given),
+encoded on the host by the library encoder; the archive is resident in HBM
+before timing starts.  One
 step = one whole-archive decode through both layers (every step of the
 hot path).  Prints one JSON line.
 
@@ -67,13 +69,19 @@ def main():
     ap.add_argument("--size", type=int, default=256 << 20)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--block", type=int, default=16384)
-    ap.add_argument("--interleave", type=int, default=32)
+    ap.add_argument("--interleave", type=int, default=0,
+                    help="rANS interleave width W; 0 = pick W and the launch shape with the "
+                         "autotuner on a 32 MiB sample of the workload")
     ap.add_argument("--min-match", type=int, default=20)
     ap.add_argument("--max-level", type=int, default=16)
     ap.add_argument("--mode", type=int, default=1,
                     help="1: entropy decode of all blocks, then one expansion launch per level, "
                          "one stream; 3: entropy decode per level on a second stream beside the "
                          "per-level expansion")
+    ap.add_argument("--waves-per-block", type=int, default=0,
+                    help="wavefronts per block in the match expansion (2, 4, 8; 0 = library default)")
+    ap.add_argument("--per-wave", type=int, default=0,
+                    help="entropy streams per wavefront (1, or 2 when W <= 32; 0 = library default)")
     ap.add_argument("--seek-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seek", action="store_true")
@@ -106,6 +114,19 @@ def main():
     t0 = time.time()
     x = gen.by_name(args.profile, args.size, args.seed)
     _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
+    tuned = None
+    if args.interleave == 0:
+        from paper_2606_24531_amd.autotune import tune
+        t0 = time.time()
+        tuned = tune(x[:min(len(x), 32 << 20)], args.profile, block_size=args.block,
+                     min_match=args.min_match, max_level=args.max_level, log=_log)
+        args.interleave = tuned["interleave"]
+        if not args.waves_per_block:
+            args.waves_per_block = tuned["waves_per_block"]
+        if not args.per_wave:
+            args.per_wave = tuned["blocks_per_wg"]
+        _log("autotune (%.1fs): W=%d, %d waves per block, %d streams per wave" % (
+            time.time() - t0, args.interleave, args.waves_per_block, args.per_wave))
     t0 = time.time()
     a = encode(x, block_size=args.block, interleave=args.interleave, min_match=args.min_match,
                hash_len=args.min_match, max_chain=32, max_level=args.max_level)
@@ -114,7 +135,7 @@ def main():
     arc = Archive(a, device=dev)
     ws = arc.workspace(arc.workspace_bytes())
     out = torch.empty(arc.n_total, dtype=torch.uint8, device=dev)
-    tuning = dict(mode=args.mode)
+    tuning = dict(mode=args.mode, waves_per_block=args.waves_per_block, blocks_per_wg=args.per_wave)
     stream = torch.cuda.current_stream()
 
     # untimed: one decode checked against the original bytes, and its
@@ -197,6 +218,9 @@ def main():
             "n_total": len(x), "archive_bytes": len(a), "ratio": round(len(x) / len(a), 4),
             "block_size": args.block, "interleave": args.interleave,
             "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
+            "waves_per_block": args.waves_per_block or 4,
+            "streams_per_wave": args.per_wave or (2 if args.interleave <= 32 else 1),
+            "autotuned": tuned is not None,
             "mode": {1: "per-level launches, one stream",
                      3: "per-level launches, entropy overlapped on a second stream"}[args.mode],
         },

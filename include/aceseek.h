@@ -79,13 +79,15 @@ typedef struct {
  *                   then one match-expansion launch per dependency level,
  *                   all on the caller's stream; 2: the persistent
  *                   dependency-ordered kernel, which is disabled in this
- *                   build (ACE_E_ARG); 3: one entropy launch per level on a
- *                   second stream of the calling thread (created on first
- *                   use, one per device), each level's expansion on the
- *                   caller's stream waiting for that level's entropy decode,
- *                   so later levels' entropy decode runs beside earlier
- *                   levels' expansion; the caller's stream is joined with
- *                   the second stream before the call's last launch */
+ *                   build (ACE_E_ARG); 3: the levels split in an early
+ *                   group (at most a quarter of the planned blocks, at
+ *                   least level 0) and a late group; the late group's
+ *                   entropy decode runs as one launch on a second stream of
+ *                   the calling thread (created on first use, one per
+ *                   device) while the caller's stream decodes and expands
+ *                   the early group, then waits for it and expands the late
+ *                   levels (so the caller's stream is joined with the
+ *                   second stream before the call's last launch) */
 typedef struct {
   uint32_t waves_per_block, blocks_per_wg, lut_variant, grid_wgs, mode;
 } ace_tuning;

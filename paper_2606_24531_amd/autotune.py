@@ -1,10 +1,11 @@
 """Autotuner for the decode launch shape.
 
 Searches, on a sample of the workload, the interleave width W (32 or 64;
-the sample is re-encoded, since W is an archive parameter) over the decode
-launch shapes the library offers.  Each
-candidate is timed as whole-archive decodes of the sample with HIP events;
-the fastest is cached as JSON keyed by (GPU architecture, block size, profile).
+the sample is re-encoded, since W is an archive parameter), the wavefronts
+per block of the match expansion and the entropy streams per wavefront.
+Each candidate is timed as whole-archive decodes of the sample with HIP
+events; the fastest is cached as JSON keyed by (GPU architecture, block
+size, profile).
 """
 from __future__ import annotations
 
@@ -38,9 +39,10 @@ def _time_decode(arc, tuning, reps: int, torch) -> float:
 
 
 def tune(sample: bytes, profile: str, block_size: int = 16384, min_match: int = 20,
-         max_level: int = 16, widths=(32, 64), grids=(0.5, 1.0, 2.0), reps: int = 5,
+         max_level: int = 16, widths=(32, 64), waves=(2, 4), reps: int = 5,
          cache_path: str = DEFAULT_CACHE, log=None) -> dict:
-    """Returns the best {"interleave", "mode", "grid_wgs"} and caches it."""
+    """Returns the best {"interleave", "waves_per_block", "blocks_per_wg",
+    "mode"} (with its time) and caches it."""
     import torch
 
     from .aceseek import Archive, encode
@@ -52,13 +54,15 @@ def tune(sample: bytes, profile: str, block_size: int = 16384, min_match: int = 
         a = encode(sample, block_size=block_size, interleave=W, min_match=min_match,
                    hash_len=min_match, max_chain=32, max_level=max_level)
         arc = Archive(a)
-        cands = [dict(mode=1, grid_wgs=0)]
+        per_wave = (1, 2) if W <= 32 else (1,)
+        cands = [dict(mode=1, waves_per_block=w, blocks_per_wg=p) for w in waves for p in per_wave]
         for c in cands:
             ms = _time_decode(arc, c, reps, torch)
-            results.append(dict(interleave=W, mode=c["mode"], grid_wgs=c["grid_wgs"], ms=ms,
-                                gbs=len(sample) / ms / 1e6))
+            results.append(dict(interleave=W, ms=ms, gbs=len(sample) / ms / 1e6,
+                                ratio=len(sample) / len(a), **c))
             if log:
-                log("tune W=%d mode=%d grid=%d: %.3f ms" % (W, c["mode"], c["grid_wgs"], ms))
+                log("tune W=%d waves/block=%d streams/wave=%d: %.3f ms" % (
+                    W, c["waves_per_block"], c["blocks_per_wg"], ms))
         arc.close()
     best = min(results, key=lambda r: r["ms"])
     entry = {"best": best, "all": results, "time": time.time(), "sample_bytes": len(sample)}

@@ -41,6 +41,8 @@ struct DecodeArgs {
   uint64_t n_total;
   uint64_t dst_base;
   uint64_t* loc;   // block id -> device address of its decoded bytes
+  uint32_t loc_linear;  // 1: block b lives at dst_base + b * B (whole-archive decode)
+  uint32_t b_shift;     // log2(B) when B is a power of two, else 64
   uint8_t* lit;    // token scratch: n_plan * B literal bytes
   uint8_t* lens;   // 4 bytes per sequence
   uint8_t* offs;   // ow bytes per sequence
@@ -90,10 +92,10 @@ hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width
 hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStream_t s);
 hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave, hipStream_t s);
-// entropy decode of one level whose plan range is read from lvl_dev; width =
-// the most entries the level can hold
-hipError_t launch_rans_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t per_wave,
-                                 hipStream_t s);
+// entropy decode of levels [lv_lo, lv_hi), whose plan range is read from
+// lvl_dev; width = the most entries those levels can hold
+hipError_t launch_rans_levels_dev(const DecodeArgs& a, uint32_t lv_lo, uint32_t lv_hi, uint32_t width,
+                                  uint32_t per_wave, hipStream_t s);
 hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
                                    hipStream_t s);
 

@@ -280,6 +280,26 @@ int check_tuning(const ace_archive* A, const ace_tuning* t) {
 // workspace header: error word (0), work counter (4), 16 counters of match
 // bytes read from earlier blocks (16..144, one per block id mod 16)
 constexpr uint64_t kWsHeader = 256, kWsCounters = 16;
+
+uint32_t shift_of(uint32_t B) {
+  if (B & (B - 1)) return 64;
+  uint32_t k = 0;
+  while ((1u << k) < B) k++;
+  return k;
+}
+
+// Overlapped decode: levels [0, split) form the early group, whose entropy
+// decode is one launch on the caller's stream; levels [split, n) are one
+// launch on the second stream, running beside the early group's entropy
+// decode and expansion.  The early group holds at most a quarter of the
+// planned blocks (and at least level 0).
+size_t level_split(const std::vector<uint32_t>& lstart) {
+  const size_t nl = lstart.size() - 1;
+  const uint64_t total = lstart[nl] - lstart[0];
+  size_t split = 1;
+  while (split + 1 < nl && 4ull * (lstart[split + 1] - lstart[0]) <= total) split++;
+  return split;
+}
 constexpr uint32_t kModePersistent = 2, kModeOverlap = 3;  // 0 and 1: per level, one stream
 
 struct Layout {
@@ -354,7 +374,7 @@ void close_range(const ace_archive* A, uint32_t t0, uint32_t t1, std::vector<uin
 static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
-               hipStream_t s, bool entries_pinned) {
+               hipStream_t s, bool entries_pinned, bool loc_linear = false) {
   (void)entries_pinned;
   const uint32_t mode = t ? t->mode : 0;
   if (mode == kModePersistent)
@@ -369,12 +389,14 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.plan = reinterpret_cast<const PlanEntry*>(ws + L.plan);
   a.n_plan = (uint32_t)n_plan;
   a.B = A->B;
+  a.b_shift = shift_of(A->B);
   a.W = A->W;
   a.ow = A->ow;
   a.n_blocks = A->nb;
   a.n_total = A->n;
   a.dst_base = dst_base;
   a.loc = reinterpret_cast<uint64_t*>(ws + L.loc);
+  a.loc_linear = loc_linear ? 1u : 0u;
   a.lit = ws + L.lit;
   a.lens = ws + L.lens;
   a.offs = ws + L.offs;
@@ -417,21 +439,20 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
       return r;
     };
     if (mode == kModeOverlap && nl > 1) {
-      // fork: entropy of level l on the second stream, level by level; the
-      // caller's stream expands level l once that level's entropy is done
-      // (and, by stream order, every earlier level is expanded), then joins
+      // fork: the late levels' entropy decode on the second stream; the
+      // caller's stream decodes and expands the early levels meanwhile,
+      // then waits for the late entropy decode and expands the rest
+      const size_t split = level_split(lstart);
       Overlap* o = nullptr;
-      HIP_TRY(overlap_for(nl, o));
+      HIP_TRY(overlap_for(1, o));
       HIP_TRY(hipEventRecord(o->ev[0], s));
       HIP_TRY(hipStreamWaitEvent(o->s2, o->ev[0], 0));
-      for (size_t l = 0; l < nl; l++) {
-        HIP_TRY(entropy(lstart[l], lstart[l + 1], o->s2));
-        HIP_TRY(hipEventRecord(o->ev[1 + l], o->s2));
-      }
-      for (size_t l = 0; l < nl; l++) {
-        HIP_TRY(hipStreamWaitEvent(s, o->ev[1 + l], 0));
-        HIP_TRY(expand(l));
-      }
+      HIP_TRY(entropy(lstart[split], lstart[nl], o->s2));
+      HIP_TRY(hipEventRecord(o->ev[1], o->s2));
+      HIP_TRY(entropy(lstart[0], lstart[split], s));
+      for (size_t l = 0; l < split; l++) HIP_TRY(expand(l));
+      HIP_TRY(hipStreamWaitEvent(s, o->ev[1], 0));
+      for (size_t l = split; l < nl; l++) HIP_TRY(expand(l));
     } else {
       HIP_TRY(entropy(0, (uint32_t)n_plan, s));
       for (size_t l = 0; l < nl; l++) HIP_TRY(expand(l));
@@ -495,7 +516,7 @@ extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out
     if (M->all_plan_pinned) entries = M->all_plan_pinned;
   }
   return run(A, entries, A->nb, A->all_levels, nullptr, 0, L, static_cast<uint8_t*>(d_ws),
-             (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), true);
+             (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), true, true);
 }
 
 extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
@@ -736,6 +757,7 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.plan = ba.plan;
     a.n_plan = A->nb;  // capacity: the real count is read on the device
     a.B = A->B;
+    a.b_shift = shift_of(A->B);
     a.W = A->W;
     a.ow = A->ow;
     a.n_blocks = A->nb;
@@ -764,12 +786,12 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     }
     if ((rc = check_tuning(A, t)) != ACE_OK) break;
     const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
-    // the entropy decode of level l on a branch of the graph, beside the
-    // expansion of earlier levels (mode 3, up to 64 levels)
-    const bool overlap = mode == kModeOverlap && A->depth > 1 && A->depth <= 64;
+    // the late levels' entropy decode on a branch of the graph, beside the
+    // early levels' decode (mode 3)
+    const bool overlap = mode == kModeOverlap && A->depth > 1;
     if (overlap) {
       bool ok = hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking) == hipSuccess;
-      for (uint32_t l = 0; ok && l <= A->depth; l++) {
+      for (uint32_t l = 0; ok && l < 2; l++) {
         hipEvent_t ev = nullptr;
         ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         if (ok) b->ev.push_back(ev);
@@ -791,14 +813,18 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
       e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
     if (e == hipSuccess) e = launch_batch_compact(ba, s);
     if (e == hipSuccess && overlap) {
+      const size_t split = level_split(A->all_levels);
+      const uint32_t nl = A->depth;
       e = hipEventRecord(b->ev[0], s);
       if (e == hipSuccess) e = hipStreamWaitEvent(b->s2, b->ev[0], 0);
-      for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++) {
-        e = launch_rans_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], per_wave, b->s2);
-        if (e == hipSuccess) e = hipEventRecord(b->ev[1 + l], b->s2);
-      }
-      for (uint32_t l = 0; e == hipSuccess && l < A->depth; l++) {
-        e = hipStreamWaitEvent(s, b->ev[1 + l], 0);
+      if (e == hipSuccess)
+        e = launch_rans_levels_dev(a, (uint32_t)split, nl, A->all_levels[nl] - A->all_levels[split], per_wave,
+                                   b->s2);
+      if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->s2);
+      if (e == hipSuccess)
+        e = launch_rans_levels_dev(a, 0, (uint32_t)split, A->all_levels[split] - A->all_levels[0], per_wave, s);
+      for (uint32_t l = 0; e == hipSuccess && l < nl; l++) {
+        if (l == split) e = hipStreamWaitEvent(s, b->ev[1], 0);
         if (e == hipSuccess)
           e = launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], waves, s);
       }

@@ -47,6 +47,11 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 
 __device__ __forceinline__ void flag(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
 
+// Block index of absolute position x (a shift for power-of-two block sizes).
+__device__ __forceinline__ uint64_t blk_of(const DecodeArgs& a, uint64_t x) {
+  return a.b_shift < 64 ? x >> a.b_shift : x / a.B;
+}
+
 // ---------------------------------------------------------------------------
 // Entropy layer: a group of G lanes (G = 64, or 32 when W <= 32, so that one
 // wavefront decodes two streams side by side) decodes one rANS stream.
@@ -287,12 +292,13 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
 // left in place (the expansion reads them there).  Also records where each
 // block's bytes will live.
 template <uint32_t G>
-__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int level) {
+__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
+                                             int lv_hi) {
   __shared__ RansGroup<G> sm[64 / G];
   const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
-  if (level >= 0) {  // the level's plan range, from device memory
-    plan_lo = a.lvl_dev[level];
-    plan_hi = a.lvl_dev[level + 1];
+  if (lv_lo >= 0) {  // the plan range of levels [lv_lo, lv_hi), from device memory
+    plan_lo = a.lvl_dev[lv_lo];
+    plan_hi = a.lvl_dev[lv_hi];
   } else if (a.n_plan_dev) {
     plan_hi = *a.n_plan_dev;
   }
@@ -500,7 +506,7 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
     if (src < c.bs) {
       if (!c.ext_ok) return nullptr;
       n_ext++;
-      const uint64_t blk = src / a.B;
+      const uint64_t blk = blk_of(a, src);
       return reinterpret_cast<const uint8_t*>(dep_loc<kThreads>(a, sm, c.dep_cnt, blk)) + (src - blk * a.B);
     }
     const uint32_t q = (uint32_t)(src - c.bs);
@@ -541,13 +547,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const uint8_t* lens = pl[16] == 0 ? pl + ld32(pl + 28) : a.lens + 4ull * pe.seq_base;
   const uint8_t* offs = pl[32] == 0 ? pl + ld32(pl + 44) : a.offs + (uint64_t)a.ow * pe.seq_base;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
-  // the block's dependencies and their locations, once, in LDS
   const bool cached = dep_cnt <= kDepCache;
-  for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) {
-    const uint32_t d = deps[j];
-    sm.deps[j] = d;
-    sm.dloc[j] = ext_ok ? a.loc[d] : 0;
-  }
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kSeq) {
@@ -562,6 +562,15 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         L[h] = lm & 0xFFFFu;
         M[h] = lm >> 16;
         O[h] = a.ow == 4 ? (uint64_t)ld32(offs + 4ull * k) : ld64(offs + 8ull * k);
+      }
+    }
+    if (t0 == 0) {
+      // the block's dependencies and their locations, once, in LDS (issued
+      // after the first tile's token loads, so the latencies overlap)
+      for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) {
+        const uint32_t d = deps[j];
+        sm.deps[j] = d;
+        sm.dloc[j] = !ext_ok ? 0 : a.loc_linear ? a.dst_base + (uint64_t)d * a.B : a.loc[d];
       }
     }
     uint32_t ip, il, tp, tl;
@@ -594,7 +603,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
             uint64_t loc0 = 0;
             if (O[h] < c.bs) {
               const uint64_t end = span_end < c.bs ? span_end : c.bs;
-              const uint64_t b0 = O[h] / a.B;
+              const uint64_t b0 = blk_of(a, O[h]);
               for (uint64_t blk = b0; blk * a.B < end; blk++) {
                 const int di = cached ? dep_index(sm.deps, dep_cnt, (uint32_t)blk)
                                       : dep_index(deps, dep_cnt, (uint32_t)blk);
@@ -610,10 +619,10 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               }
             }
             if (!fl) {
-              const uint64_t b0 = O[h] / a.B;
+              const uint64_t b0 = blk_of(a, O[h]);
               if (span_end <= c.bs && contiguous) {
                 const uint64_t off = O[h] - b0 * a.B;  // earlier blocks, one run of memory
-                const uint64_t nblk = (span_end - 1) / a.B - b0 + 1;
+                const uint64_t nblk = blk_of(a, span_end - 1) - b0 + 1;
                 src0 = loc0 + off;
                 win = win_pack(off, nblk * a.B - off);
                 fl = kExt;
@@ -795,9 +804,21 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
             vec = false;
           }
         }
+        // one LDS atomic per wavefront and list: lanes take slots in lane order
         const uint32_t e = (k << kSB) | sq;
-        if (vec) sm.list[atomicAdd(&sm.nvec, 1u)] = e;
-        else sm.list[kRound - 1 - atomicAdd(&sm.nbyte, 1u)] = e;
+        const uint64_t mv = __builtin_amdgcn_ballot_w64(vec), mb = __builtin_amdgcn_ballot_w64(!vec);
+        const uint32_t lane = tid & 63;
+        const uint32_t leader_v = mv ? (uint32_t)__builtin_ctzll(mv) : 64u;
+        const uint32_t leader_b = mb ? (uint32_t)__builtin_ctzll(mb) : 64u;
+        uint32_t bv = 0, bb = 0;
+        if (lane == leader_v) bv = atomicAdd(&sm.nvec, (uint32_t)__popcll(mv));
+        if (lane == leader_b) bb = atomicAdd(&sm.nbyte, (uint32_t)__popcll(mb));
+        bv = __shfl(bv, leader_v & 63, 64);
+        bb = __shfl(bb, leader_b & 63, 64);
+        const uint32_t below_v = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
+        const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+        if (vec) sm.list[bv + below_v] = e;
+        else sm.list[kRound - 1 - (bb + below_b)] = e;
       }
       __syncthreads();
       const uint32_t nv = sm.nvec, nby = sm.nbyte;
@@ -1041,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_copy(DecodeArgs a, const CopyItem* item
   uint8_t* dst = reinterpret_cast<uint8_t*>(it.dst);
   for (uint32_t j0 = threadIdx.x * 16; j0 < it.len; j0 += 256 * 16) {
     uint64_t pos = it.src_abs + j0;
-    uint64_t c = pos / a.B;
+    uint64_t c = blk_of(a, pos);
     uint64_t cend = (c + 1) * a.B;
     const uint8_t* base = reinterpret_cast<const uint8_t*>(a.loc[c]) - c * a.B;
     uint32_t jn = j0 + 16 < it.len ? j0 + 16 : it.len;
@@ -1143,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_bgather(BatchArgs b, DecodeArgs a) {
   const uint64_t len = hi - lo;
   for (uint64_t j0 = threadIdx.x * 16ull; j0 < len; j0 += 256 * 16) {
     uint64_t pos = lo + j0;
-    uint64_t c = pos / a.B;
+    uint64_t c = blk_of(a, pos);
     uint64_t cend = (c + 1) * a.B;
     const uint8_t* base = reinterpret_cast<const uint8_t*>(b.loc[c]) - c * a.B;
     const uint64_t jn = j0 + 16 < len ? j0 + 16 : len;
@@ -1166,22 +1187,23 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
 
 }  // namespace
 
-// Entropy launch over plan entries [lo, hi), or (level >= 0) over that
-// level's range read from device memory with hi - lo entries of capacity.
-static hipError_t launch_rans_any(const DecodeArgs& a, uint32_t lo, uint32_t hi, int level, uint32_t per_wave,
-                                  hipStream_t s) {
+// Entropy launch over plan entries [lo, hi), or (lv_lo >= 0) over the plan
+// range of levels [lv_lo, lv_hi) read from device memory, with hi - lo
+// entries of capacity.
+static hipError_t launch_rans_any(const DecodeArgs& a, uint32_t lo, uint32_t hi, int lv_lo, int lv_hi,
+                                  uint32_t per_wave, hipStream_t s) {
   if (hi <= lo) return hipSuccess;
   const uint32_t n = hi - lo;
   if (per_wave == 0) per_wave = a.W <= 32 ? 2 : 1;
   if (per_wave == 2 && a.W <= 32)
-    hipLaunchKernelGGL(k_rans<32>, dim3((n + 1) / 2, 3), dim3(64), 0, s, a, lo, hi, level);
+    hipLaunchKernelGGL(k_rans<32>, dim3((n + 1) / 2, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
   else
-    hipLaunchKernelGGL(k_rans<64>, dim3(n, 3), dim3(64), 0, s, a, lo, hi, level);
+    hipLaunchKernelGGL(k_rans<64>, dim3(n, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
   return hipGetLastError();
 }
 
 hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s) {
-  return launch_rans_any(a, lo, hi, -1, per_wave, s);
+  return launch_rans_any(a, lo, hi, -1, -1, per_wave, s);
 }
 
 // One expansion launch: grid blocks from plan_lo, or (level >= 0) the plan
@@ -1206,12 +1228,12 @@ hipError_t launch_expand_level(const DecodeArgs& a, uint32_t lo, uint32_t hi, ui
 // cap: the largest plan length the launch must cover (the length itself is
 // read from device memory)
 hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave, hipStream_t s) {
-  return launch_rans_any(a, 0, cap, -1, per_wave, s);
+  return launch_rans_any(a, 0, cap, -1, -1, per_wave, s);
 }
 
-hipError_t launch_rans_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t per_wave,
-                                 hipStream_t s) {
-  return launch_rans_any(a, 0, width, (int)level, per_wave, s);
+hipError_t launch_rans_levels_dev(const DecodeArgs& a, uint32_t lv_lo, uint32_t lv_hi, uint32_t width,
+                                  uint32_t per_wave, hipStream_t s) {
+  return launch_rans_any(a, 0, width, (int)lv_lo, (int)lv_hi, per_wave, s);
 }
 
 hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
