@@ -149,17 +149,23 @@ def stream_table(data) -> dict:
     raw = np.zeros(3, np.int64)
     stored = np.zeros(3, np.int64)
     rans = np.zeros(3, np.int64)
+    rans_raw = np.zeros(3, np.int64)
+    rans_stored = np.zeros(3, np.int64)
     for b in range(nb):
         pay = int(arr[64 + 32 * b:64 + 32 * b + 8].view("<u8")[0])
         d = arr[pay:pay + 48].view("<u4").reshape(3, 4)
         for t in range(3):
             raw[t] += int(d[t, 1])
             stored[t] += int(d[t, 2])
-            rans[t] += int(d[t, 0] & 0xFF) == 1
+            if int(d[t, 0] & 0xFF) == 1:
+                rans[t] += 1
+                rans_raw[t] += int(d[t, 1])
+                rans_stored[t] += int(d[t, 2])
     for t, nm in enumerate(names):
         out[nm] = {"raw": int(raw[t]), "stored": int(stored[t]),
                    "ratio": round(float(raw[t]) / max(1, int(stored[t])), 4),
-                   "rans_share": round(float(rans[t]) / max(1, nb), 4)}
+                   "rans_share": round(float(rans[t]) / max(1, nb), 4),
+                   "rans_raw": int(rans_raw[t]), "rans_stored": int(rans_stored[t])}
     return out
 
 
