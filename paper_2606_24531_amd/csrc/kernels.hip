@@ -361,9 +361,9 @@ struct ExpandSmem {
   static constexpr uint32_t kSeq = 2 * kThreads;    // sequences per tile (two per thread)
   static constexpr uint32_t kRound = 4 * kThreads;  // 16-byte chunks sorted per round
   static constexpr uint32_t kSeqBits = kThreads <= 64 ? 7 : kThreads <= 128 ? 8 : kThreads <= 256 ? 9 : 10;
-  uint32_t list[kRound];  // chunk << kSeqBits | sequence: copy chunks first, per-byte chunks from the back
+  uint32_t list[kRound];  // per-byte chunks: chunk << kSeqBits | sequence
   uint32_t cseq[kRound];  // sequence holding each chunk's first byte
-  uint32_t nvec, nbyte, carry;
+  uint32_t nbyte, carry;
   uint32_t dst[kSeq];     // block-relative start of the sequence
   uint32_t lm[kSeq];      // L | M << 16
   uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
@@ -374,42 +374,39 @@ struct ExpandSmem {
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
   uint32_t deps[kDepCache];
   uint64_t dloc[kDepCache];  // location of each cached dependency's first byte
-  uint32_t scan[16];
+  uint32_t scan[32];
 };
 
-// Inclusive scans of a and b over the workgroup (kThreads threads) and totals.
+// Inclusive scans of four values over the workgroup (kThreads threads):
+// v[j] becomes the sum of v[j] over threads 0..tid, t[j] the total.
 template <uint32_t kThreads>
-__device__ __forceinline__ void wg_scan2(uint32_t a, uint32_t b, uint32_t& ia, uint32_t& ib,
-                                         uint32_t& ta, uint32_t& tb, uint32_t* sh) {
+__device__ __forceinline__ void wg_scan4(uint32_t (&v)[4], uint32_t (&t)[4], uint32_t* sh) {
   constexpr uint32_t kW = kThreads / 64;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  a = wave_incl_sum(a, lane);
-  b = wave_incl_sum(b, lane);
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) v[j] = wave_incl_sum(v[j], lane);
   if (kW == 1) {
-    ta = __shfl(a, 63, 64);
-    tb = __shfl(b, 63, 64);
-    ia = a;
-    ib = b;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) t[j] = __shfl(v[j], 63, 64);
     return;
   }
   __syncthreads();
   if (lane == 63) {
-    sh[w] = a;
-    sh[8 + w] = b;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) sh[4 * w + j] = v[j];
   }
   __syncthreads();
-  uint32_t oa = 0, ob = 0;
-  ta = tb = 0;
-  for (uint32_t j = 0; j < kW; j++) {
-    if (j < w) {
-      oa += sh[j];
-      ob += sh[8 + j];
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) {
+    uint32_t o = 0, tot = 0;
+    for (uint32_t q = 0; q < kW; q++) {
+      const uint32_t x = sh[4 * q + j];
+      if (q < w) o += x;
+      tot += x;
     }
-    ta += sh[j];
-    tb += sh[8 + j];
+    v[j] += o;
+    t[j] = tot;
   }
-  ia = a + oa;
-  ib = b + ob;
 }
 
 // In place: v[j] = max(carry, every value up to and including this one) over
@@ -556,7 +553,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     uint64_t O[2] = {0, 0};
 #pragma unroll
     for (uint32_t h = 0; h < 2; h++) {
-      const uint32_t k = t0 + 2 * tid + h;
+      const uint32_t k = t0 + tid + h * kThreads;  // slot tid + h * kThreads
       if (k < n_seq) {
         const uint32_t lm = ld32(lens + 4ull * k);
         L[h] = lm & 0xFFFFu;
@@ -573,17 +570,20 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         sm.dloc[j] = !ext_ok ? 0 : a.loc_linear ? a.dst_base + (uint64_t)d * a.B : a.loc[d];
       }
     }
-    uint32_t ip, il, tp, tl;
-    wg_scan2<kThreads>(L[0] + M[0] + L[1] + M[1], L[0] + L[1], ip, il, tp, tl, sm.scan);
+    // positions in sequence order: slots 0..kThreads-1 first, then the rest
+    uint32_t sv[4] = {L[0] + M[0], L[0], L[1] + M[1], L[1]}, st[4];
+    wg_scan4<kThreads>(sv, st, sm.scan);
+    const uint32_t tp = st[0] + st[2], tl = st[1] + st[3];
     const uint32_t d0 = carry_pos;
     c.d0 = d0;
     c.cnt = (n_seq - t0) < kSeq ? (n_seq - t0) : kSeq;
-    uint32_t pos = carry_pos + ip - (L[0] + M[0] + L[1] + M[1]);
-    uint32_t litk = carry_lit + il - (L[0] + L[1]);
+    const uint32_t pos_h[2] = {carry_pos + sv[0] - (L[0] + M[0]), carry_pos + st[0] + sv[2] - (L[1] + M[1])};
+    const uint32_t lit_h[2] = {carry_lit + sv[1] - L[0], carry_lit + st[1] + sv[3] - L[1]};
     uint32_t fl_h[2] = {0, 0};
 #pragma unroll
     for (uint32_t h = 0; h < 2; h++) {
-      const uint32_t k = t0 + 2 * tid + h, slot = 2 * tid + h;
+      const uint32_t k = t0 + tid + h * kThreads, slot = tid + h * kThreads;
+      const uint32_t pos = pos_h[h], litk = lit_h[h];
       uint32_t fl = 0, dist = 0, win = 0;
       uint64_t src0 = 0;
       if (k < n_seq) {
@@ -651,8 +651,6 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       sm.win[slot] = win;
       sm.O[slot] = O[h];
       sm.src0[slot] = src0;
-      pos += L[h] + M[h];
-      litk += L[h];
     }
     __syncthreads();
     // ---- spans inside this tile: a literal run resolves at once; a span
@@ -660,7 +658,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 #pragma unroll
     for (uint32_t h = 0; h < 2; h++) {
       if (!(fl_h[h] & kPend)) continue;
-      const uint32_t slot = 2 * tid + h;
+      const uint32_t slot = tid + h * kThreads;
       const uint32_t q = (uint32_t)(O[h] - c.bs);
       const uint32_t dist = sm.dfl[slot] & 0xFFFFFFu;
       const uint32_t sl = M[h] < dist ? M[h] : dist;
@@ -697,7 +695,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
         if (!(fl_h[h] & kPend)) continue;
-        const uint32_t pt = sm.ptr[2 * tid + h], j = pt >> 16, off = pt & 0xFFFFu;
+        const uint32_t pt = sm.ptr[tid + h * kThreads], j = pt >> 16, off = pt & 0xFFFFu;
         const uint32_t fj = sm.dfl[j] >> 24;
         if (!(fj & kUnres)) {
           const uint32_t wj = sm.win[j];
@@ -716,7 +714,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
         if (!(fl_h[h] & kPend)) continue;
-        const uint32_t slot = 2 * tid + h;
+        const uint32_t slot = tid + h * kThreads;
         const uint32_t dist = sm.dfl[slot] & 0xFFFFFFu;
         sm.dfl[slot] = dist | (nfl[h] << 24);
         if (nfl[h] & kPend) {
@@ -732,20 +730,20 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     // pointers are no longer needed)
     uint32_t n_slow = 0;
     {
-      const uint32_t c0 = (fl_h[0] & kSlow) ? M[0] : 0u, c1 = (fl_h[1] & kSlow) ? M[1] : 0u;
-      uint32_t is, iz, ts, tz;
-      wg_scan2<kThreads>(c0 + c1, 0u, is, iz, ts, tz, sm.scan);
-      sm.ptr[2 * tid] = is - c1;
-      sm.ptr[2 * tid + 1] = is;
-      n_slow = ts;
+      uint32_t cv[4] = {(fl_h[0] & kSlow) ? M[0] : 0u, 0u, (fl_h[1] & kSlow) ? M[1] : 0u, 0u}, ct[4];
+      wg_scan4<kThreads>(cv, ct, sm.scan);
+      sm.ptr[tid] = cv[0];
+      sm.ptr[tid + kThreads] = ct[0] + cv[2];
+      n_slow = ct[0] + ct[2];
       __syncthreads();
     }
     const uint64_t d1w = (uint64_t)carry_pos + tp;
     const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
-    // ---- output in 16-byte chunks, sorted per round: copy chunks (one
-    // literal run, or one resolved match with no period wrap, whose five
-    // aligned source dwords are readable) first, per-byte chunks after, so a
-    // wavefront does not pay for both kinds of work
+    // ---- output in 16-byte chunks, four per thread per round: copy chunks
+    // (one literal run, or one resolved match with no period wrap, whose
+    // five aligned source dwords are readable) are copied where they are
+    // classified; per-byte chunks are gathered in a list and spread over
+    // the threads, so a wavefront does not pay for both kinds of work
     const uint32_t base = d0 & ~15u;
     const uint32_t nch = d1 > base ? (d1 - base + 15) / 16 : 0;
     for (uint32_t k0 = 0; k0 < nch; k0 += kRound) {
@@ -755,14 +753,13 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // running maximum over the chunks fills the rest
       for (uint32_t j = tid; j < kRound; j += kThreads) sm.cseq[j] = 0;
       if (tid == 0) {
-        sm.nvec = 0;
         sm.nbyte = 0;
         if (k0 == 0) sm.carry = 0;
       }
       __syncthreads();
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
-        const uint32_t slot = 2 * tid + h;
+        const uint32_t slot = tid + h * kThreads;
         if (slot < c.cnt) {
           const uint32_t ds = sm.dst[slot];
           const uint32_t cm = ds <= d0 ? 0u : (ds - base + 15) / 16;
@@ -782,68 +779,61 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         if (tid == 0) sm.carry = all;
       }
       __syncthreads();
-      for (uint32_t k = k0 + tid; k < k0 + kn; k += kThreads) {
-        const uint32_t cb = base + 16 * k;
-        const uint32_t p0 = cb < d0 ? d0 : cb;
-        const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-        const uint32_t sq = sm.cseq[k - k0];
-        const uint32_t fl = sm.dfl[sq] >> 24;
-        bool vec = aligned && p0 == cb && pe1 == cb + 16 && !(fl & kPoison);
-        if (vec) {
-          const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
-          const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
-          if (cb + 16 > end_s) {
-            vec = false;
-          } else if (r0 + 16 <= Ls) {
-            vec = true;  // all literals (stream data has readable slack)
-          } else if (r0 >= Ls && !(fl & kUnres)) {
-            const uint32_t ii0 = r0 - Ls, w = sm.win[sq];
-            const uint32_t shp = (uint32_t)((sm.src0[sq] + ii0) & 3);
-            vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (w & 3u) >= shp && ii0 + 20 <= (w >> 2) + shp;
-          } else {
-            vec = false;
-          }
-        }
-        // one LDS atomic per wavefront and list: lanes take slots in lane order
-        const uint32_t e = (k << kSB) | sq;
-        const uint64_t mv = __builtin_amdgcn_ballot_w64(vec), mb = __builtin_amdgcn_ballot_w64(!vec);
-        const uint32_t lane = tid & 63;
-        const uint32_t leader_v = mv ? (uint32_t)__builtin_ctzll(mv) : 64u;
-        const uint32_t leader_b = mb ? (uint32_t)__builtin_ctzll(mb) : 64u;
-        uint32_t bv = 0, bb = 0;
-        if (lane == leader_v) bv = atomicAdd(&sm.nvec, (uint32_t)__popcll(mv));
-        if (lane == leader_b) bb = atomicAdd(&sm.nbyte, (uint32_t)__popcll(mb));
-        bv = __shfl(bv, leader_v & 63, 64);
-        bb = __shfl(bb, leader_b & 63, 64);
-        const uint32_t below_v = __builtin_amdgcn_mbcnt_hi((uint32_t)(mv >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mv, 0u));
-        const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-        if (vec) sm.list[bv + below_v] = e;
-        else sm.list[kRound - 1 - (bb + below_b)] = e;
-      }
-      __syncthreads();
-      const uint32_t nv = sm.nvec, nby = sm.nbyte;
-      // copy chunks: all loads of this thread's chunks first, then the stores
+      // classify this thread's four chunks; a copy chunk's five source dwords
+      // are loaded at once (stored after all four are classified), per-byte
+      // chunks are appended to a list (one LDS atomic per wavefront)
       uint32_t w[4][5];
       uint32_t shv[4];
       uint32_t cbv[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
-        const uint32_t ei = tid + j * kThreads;
-        shv[j] = 0;
+        const uint32_t k = k0 + tid + j * kThreads;
         cbv[j] = 0xFFFFFFFFu;
-        if (ei < nv) {
-          const uint32_t e = sm.list[ei], k = e >> kSB, sq = e & kSM;
-          const uint32_t cb = base + 16 * k;
-          const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
-          const uint8_t* src = r0 < Ls ? c.lit + sm.lit[sq] + r0
-                                       : reinterpret_cast<const uint8_t*>(sm.src0[sq] + (r0 - Ls));
-          const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
-          const uint32_t* wp = reinterpret_cast<const uint32_t*>(src - sh);
+        shv[j] = 0;
+        const bool here = k < k0 + kn;
+        const uint32_t cb = base + 16 * k;
+        bool vec = false;
+        uint32_t sq = 0;
+        if (here) {
+          const uint32_t p0 = cb < d0 ? d0 : cb;
+          const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
+          sq = sm.cseq[k - k0];
+          const uint32_t fl = sm.dfl[sq] >> 24;
+          if (aligned && p0 == cb && pe1 == cb + 16 && !(fl & kPoison)) {
+            const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
+            const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
+            const uint8_t* src = nullptr;
+            if (cb + 16 > end_s) {
+              vec = false;
+            } else if (r0 + 16 <= Ls) {
+              vec = true;  // all literals (stream data has readable slack)
+              src = c.lit + sm.lit[sq] + r0;
+            } else if (r0 >= Ls && !(fl & kUnres)) {
+              const uint32_t ii0 = r0 - Ls, wn = sm.win[sq];
+              const uint64_t sa = sm.src0[sq] + ii0;
+              const uint32_t shp = (uint32_t)(sa & 3);
+              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (wn & 3u) >= shp && ii0 + 20 <= (wn >> 2) + shp;
+              src = reinterpret_cast<const uint8_t*>(sa);
+            }
+            if (vec) {
+              const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
+              const uint32_t* wp = reinterpret_cast<const uint32_t*>(src - sh);
 #pragma unroll
-          for (uint32_t q = 0; q < 5; q++) w[j][q] = wp[q];
-          shv[j] = sh;
-          cbv[j] = cb;
+              for (uint32_t q = 0; q < 5; q++) w[j][q] = wp[q];
+              shv[j] = sh;
+              cbv[j] = cb;
+            }
+          }
         }
+        const bool byte = here && !vec;
+        const uint64_t mb = __builtin_amdgcn_ballot_w64(byte);
+        const uint32_t lane = tid & 63;
+        const uint32_t leader_b = mb ? (uint32_t)__builtin_ctzll(mb) : 64u;
+        uint32_t bb = 0;
+        if (lane == leader_b) bb = atomicAdd(&sm.nbyte, (uint32_t)__popcll(mb));
+        bb = __shfl(bb, leader_b & 63, 64);
+        const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+        if (byte) sm.list[bb + below_b] = (k << kSB) | sq;
       }
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
@@ -856,6 +846,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
                          __builtin_amdgcn_alignbyte(w[j][4], w[j][3], sh));
         }
       }
+      __syncthreads();
+      const uint32_t nby = sm.nbyte;
       // per-byte chunks: every byte's source address first, then the 16
       // loads back to back, so their latencies overlap.  The current
       // sequence's fields stay in registers (LDS is read only when the walk
@@ -863,7 +855,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // by one, wrapping at the period.  Bytes of slow sequences get a
       // placeholder here; the slow pass below writes them.
       for (uint32_t ei = tid; ei < nby; ei += kThreads) {
-        const uint32_t e = sm.list[kRound - 1 - ei], k = e >> kSB;
+        const uint32_t e = sm.list[ei], k = e >> kSB;
         const uint32_t cb = base + 16 * k;
         const uint32_t p0 = cb < d0 ? d0 : cb;
         const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
