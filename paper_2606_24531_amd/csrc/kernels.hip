@@ -368,7 +368,7 @@ struct ExpandSmem {
   uint32_t lm[kSeq];      // L | M << 16
   uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
   uint32_t dfl[kSeq];     // min(d, 2^24 - 1) | flags << 24
-  uint32_t win[kSeq];     // readable bytes around src0: back (0..3) | forward << 2
+  uint32_t win[kSeq];     // readable bytes around src0: back (0..31) | forward << 5
   uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
   uint64_t O[kSeq];
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
@@ -512,8 +512,110 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
   }
 }
 
+// Readable bytes around a resolved span's address: back (capped at 31) and
+// forward (capped at 2^26).
 __device__ __forceinline__ uint32_t win_pack(uint64_t back, uint64_t fwd) {
-  return (uint32_t)(back < 3 ? back : 3) | ((uint32_t)fwd << 2);
+  return (uint32_t)(back < 31 ? back : 31) | ((uint32_t)(fwd < (1ull << 26) ? fwd : (1ull << 26)) << 5);
+}
+
+// Byte mask (as bit mask of dword j's four bytes) of chunk bytes [lo, hi).
+__device__ __forceinline__ uint32_t dword_mask(uint32_t j, uint32_t lo, uint32_t hi) {
+  uint32_t m = 0;
+#pragma unroll
+  for (uint32_t b = 0; b < 4; b++) {
+    const uint32_t x = 4 * j + b;
+    m |= (x >= lo && x < hi) ? (0xFFu << (8 * b)) : 0u;
+  }
+  return m;
+}
+
+// Segment path for a 16-byte output chunk [cb, cb+16) inside the tile: the
+// chunk is cut at literal/match and sequence boundaries into at most four
+// segments over at most two sequences, each copied from one contiguous
+// source with five aligned dword loads (all issued before any is used) and
+// merged by byte mask.  Bytes of slow spans are left as placeholders (the
+// slow pass writes them), bytes of poisoned sequences as zeros.  Returns
+// false (the caller takes the per-byte path) for a period wrap inside a
+// segment, a third sequence, or a source window that is not known readable.
+template <uint32_t kThreads>
+__device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const BlockCtx& c, uint32_t cb,
+                                          uint32_t s, uint32_t d1, uint32_t (&out)[4]) {
+  constexpr uint32_t kC = 4;  // candidate segments: (literal, match) x 2 sequences
+  uint64_t V[kC];
+  uint32_t lo[kC], hi[kC];
+  bool load[kC];
+  uint32_t x = cb;
+  bool ok = true;
+#pragma unroll
+  for (uint32_t q = 0; q < 2; q++) {
+    load[2 * q] = load[2 * q + 1] = false;
+    lo[2 * q] = hi[2 * q] = lo[2 * q + 1] = hi[2 * q + 1] = 0;
+    V[2 * q] = V[2 * q + 1] = 0;
+    const uint32_t sq = s + q;
+    if (x < cb + 16 && sq < c.cnt) {
+      const uint32_t sd = sm.dst[sq];
+      const uint32_t se = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
+      const uint32_t L = sm.lm[sq] & 0xFFFFu;
+      const uint32_t dfl = sm.dfl[sq], f = dfl >> 24, d = dfl & 0xFFFFFFu;
+      const uint32_t end = se < cb + 16 ? se : cb + 16;
+      if (f & kPoison) {
+        lo[2 * q] = x - cb;  // zeros: a segment with no load
+        hi[2 * q] = end - cb;
+        x = end;
+      } else {
+        if (x < sd + L) {  // literal run
+          const uint32_t h = sd + L < end ? sd + L : end;
+          const uint8_t* A = c.lit + sm.lit[sq] + (x - sd);
+          V[2 * q] = (uint64_t)(uintptr_t)A - (x - cb);
+          lo[2 * q] = x - cb;
+          hi[2 * q] = h - cb;
+          load[2 * q] = true;  // literal streams are readable 31 bytes before and 20 after
+          x = h;
+        }
+        if (x < end) {  // match part
+          const uint32_t ii0 = x - (sd + L);
+          lo[2 * q + 1] = x - cb;
+          hi[2 * q + 1] = end - cb;
+          if (!(f & kUnres)) {
+            const uint64_t A = sm.src0[sq] + ii0;
+            const uint64_t v = A - (x - cb);
+            const uint32_t wn = sm.win[sq], back = (wn & 31u) + ii0, fwd = (wn >> 5) - ii0;
+            const uint32_t need_back = (x - cb) + (uint32_t)(v & 3);
+            ok = ok && ii0 + (end - x) <= d && need_back <= back && 20 - need_back <= fwd;
+            V[2 * q + 1] = v;
+            load[2 * q + 1] = true;
+          }
+          x = end;
+        }
+      }
+    }
+  }
+  if (!ok || x < cb + 16) return false;
+  uint32_t wv[kC][5];
+#pragma unroll
+  for (uint32_t k = 0; k < kC; k++) {
+    if (load[k]) {
+      const uint32_t* wp = reinterpret_cast<const uint32_t*>(V[k] & ~3ull);
+#pragma unroll
+      for (uint32_t q = 0; q < 5; q++) wv[k][q] = wp[q];
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 5; q++) wv[k][q] = 0;
+    }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) out[j] = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kC; k++) {
+    const uint32_t sh = (uint32_t)(V[k] & 3);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) {
+      const uint32_t m = dword_mask(j, lo[k], hi[k]);
+      const uint32_t v = __builtin_amdgcn_alignbyte(wv[k][j + 1], wv[k][j], sh);
+      out[j] = (out[j] & ~m) | (v & m);
+    }
+  }
+  return true;
 }
 
 // Expands plan entry i with kThreads threads.  Sources in earlier blocks must
@@ -700,7 +802,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         if (!(fj & kUnres)) {
           const uint32_t wj = sm.win[j];
           nsrc[h] = sm.src0[j] + off;
-          nwin[h] = win_pack((wj & 3u) + off, (wj >> 2) - off);
+          nwin[h] = win_pack((wj & 31u) + off, (wj >> 5) - off);
           nfl[h] = fj & kExt;
           if (fj & kExt) n_ext += M[h];
         } else if ((fj & kPend) && round + 1 < kMaxJumps) {
@@ -812,7 +914,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               const uint32_t ii0 = r0 - Ls, wn = sm.win[sq];
               const uint64_t sa = sm.src0[sq] + ii0;
               const uint32_t shp = (uint32_t)(sa & 3);
-              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (wn & 3u) >= shp && ii0 + 20 <= (wn >> 2) + shp;
+              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (wn & 31u) >= shp && ii0 + 20 <= (wn >> 5) + shp;
               src = reinterpret_cast<const uint8_t*>(sa);
             }
             if (vec) {
@@ -860,6 +962,13 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         const uint32_t p0 = cb < d0 ? d0 : cb;
         const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
         uint32_t s = e & kSM;
+        if (aligned && p0 == cb && pe1 == cb + 16) {
+          uint32_t o4[4];
+          if (seg_chunk<kThreads>(sm, c, cb, s, d1, o4)) {
+            *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+            continue;
+          }
+        }
         uint32_t sd = 0, se = 0, sL = 0, sf = 0, sdist = 1, im = 0;
         const uint8_t* litp = c.lit;
         uint64_t src0 = 0;
