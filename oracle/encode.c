@@ -15,13 +15,14 @@
  *     the common prefix of X[q..] and X[p..], capped at the block end and at
  *     65535 (overlap with p is allowed: the copy is byte-sequential);
  *   - with max_level > 0 blocks are grouped in epochs of 64 (E epochs in
- *     all); a block of epoch e may take sources only from itself and from
- *     blocks of earlier epochs whose level is below
- *         lambda(e) = min(max_level - 1, floor(log2(e + 1)),
- *                         max(1, floor(log2(E + 1)) - 1))
+ *     all), and epochs in units of c = max(1, floor(E / 64)); a block of
+ *     epoch e may take sources only from itself and from blocks of earlier
+ *     epochs whose level is below
+ *         lambda(e) = min(max_level - 1, floor(log2(floor(e / c) + 1)),
+ *                         max(1, floor(log2(floor(E / c) + 1)) - 1))
  *     ("visible" blocks), so every level stays below max_level and the
- *     levels grow geometrically in size (the last level holds at least half
- *     of the epochs).  Chain candidates in invisible blocks are passed over
+ *     levels grow geometrically in size from c epochs (the last level holds
+ *     at least half of the epochs).  Chain candidates in invisible blocks are passed over
  *     without being counted (at most 8 * max_chain chain steps in all), and a
  *     counted candidate is cut where its source first enters an invisible
  *     block;
@@ -380,8 +381,9 @@ static uint32_t ilog2(uint64_t v) {
 /* Level budget of epoch e of E under cap max_level: blocks of the epoch see
  * only earlier-epoch blocks whose level is below this value. */
 static uint32_t level_budget(uint64_t e, uint64_t E, uint32_t max_level) {
-  uint32_t lam = ilog2(e + 1);
-  uint32_t top = ilog2(E + 1);
+  uint64_t c = E / 64 > 1 ? E / 64 : 1;
+  uint32_t lam = ilog2(e / c + 1);
+  uint32_t top = ilog2(E / c + 1);
   top = top >= 2 ? top - 1 : 1;
   if (lam > top) lam = top;
   if (lam > max_level - 1) lam = max_level - 1;

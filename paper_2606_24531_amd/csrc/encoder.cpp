@@ -11,10 +11,11 @@
 //   prefix with p (overlap allowed) capped at the block end and 65535.
 //   Longest wins, ties to the first found; taken if it reaches
 //   min_match.  With a level cap, blocks are grouped in epochs of 64 (E in
-//   all): a block of epoch e takes sources only from itself and from blocks
-//   of earlier epochs whose level is below min(cap - 1, floor(log2(e + 1)),
-//   max(1, floor(log2(E + 1)) - 1)), so levels stay below the cap and grow
-//   geometrically in size; chain candidates elsewhere are passed over without
+//   all), counted in units of c = max(1, floor(E / 64)) epochs: a block of
+//   epoch e takes sources only from itself and from blocks of earlier epochs
+//   whose level is below min(cap - 1, floor(log2(floor(e / c) + 1)),
+//   max(1, floor(log2(floor(E / c) + 1)) - 1)), so levels stay below the cap
+//   and grow geometrically in size; chain candidates elsewhere are passed over without
 //   being counted (at most 8 * max_chain chain steps), and a counted
 //   candidate is cut where its source first enters such a block.
 //   Frequencies are normalised to 4096 with f = max(1,
@@ -153,8 +154,9 @@ uint32_t level_budget(uint64_t e, uint64_t n_ep, uint32_t cap) {
     while (v >>= 1) r++;
     return r;
   };
-  const uint32_t top = std::max<uint32_t>(1, lg(n_ep + 1) >= 1 ? lg(n_ep + 1) - 1 : 0);
-  return std::min({lg(e + 1), top, cap - 1});
+  const uint64_t c = std::max<uint64_t>(1, n_ep / 64);
+  const uint32_t top = std::max<uint32_t>(1, lg(n_ep / c + 1) >= 1 ? lg(n_ep / c + 1) - 1 : 0);
+  return std::min({lg(e / c + 1), top, cap - 1});
 }
 
 void push_seq(std::vector<Seq>& out, uint64_t lits, uint32_t M, uint64_t O) {

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace ace {
@@ -57,7 +59,7 @@ __device__ __forceinline__ uint64_t blk_of(const DecodeArgs& a, uint64_t x) {
 // wavefront decodes two streams side by side) decodes one rANS stream.
 //
 // LDS holds each stream's 12-bit table as a 4096-byte slot -> symbol map plus
-// one packed word per symbol ((f-1) << 16 | cum), and a ring of two chunks of
+// one packed word per symbol (f << 16 | cum), and a ring of two chunks of
 // renormalisation words (16 G bytes each), refilled from a register
 // prefetch so the decode loop never waits on HBM latency.  The table build's
 // scratch lives in the ring before the ring is filled.  Lane j of a group
@@ -69,7 +71,7 @@ __device__ __forceinline__ uint64_t blk_of(const DecodeArgs& a, uint64_t x) {
 template <uint32_t G>
 struct RansGroup {
   uint8_t sym[4096];  // slot -> symbol
-  uint32_t fc[256];   // symbol -> (f-1) << 16 | cum
+  uint32_t fc[256];   // symbol -> f << 16 | cum
   uint8_t stage[16 * G + 16];  // decoded symbols not yet written out; the last 16 bytes
                                // take the writes of idle lanes
   union {
@@ -145,7 +147,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
 #pragma unroll
     for (uint32_t j = 0; j < kSpl; j++) {
       const uint32_t s = kSpl * g + j;
-      sm.fc[s] = f[j] ? ((f[j] - 1) << 16) | cum : 0u;
+      sm.fc[s] = f[j] ? (f[j] << 16) | cum : 0u;
       if (f[j]) {
         sm.u.b.by_rank[k++] = (uint8_t)s;
         atomicOr(&sm.u.b.starts[cum >> 6], 1ull << (cum & 63));
@@ -209,6 +211,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   constexpr uint32_t kU = 4;  // steps per ring/stage check in the main loop
   const uint32_t stage_steps = (16 * G / W) & ~(kU - 1);
   uint32_t t0 = 0;  // first step held in the stage
+  uint32_t so = g;  // this lane's stage offset for the next step
   auto flush = [&](uint32_t t) {
     const uint32_t f0 = min(t0 * W, n), f1 = min(t * W, n), cnt = f1 - f0;
     uint8_t* o = dst + f0;
@@ -222,6 +225,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     }
     for (; k < cnt; k += G) o[k] = sm.stage[k];
     t0 = t;
+    so = g;
   };
   // Makes room for `steps` more steps: ring words and stage space.
   auto prepare = [&](uint32_t t, uint32_t steps) {
@@ -240,22 +244,26 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
       wave_sync();
     }
   };
-  auto step = [&](uint32_t t, bool act) {
+  // One step.  kAll: every lane of the wave holds a state with a symbol in
+  // this step, so the renormalisation ballot is the comparison itself.
+  auto step = [&](auto all, bool act) {
+    constexpr bool kAll = decltype(all)::value;
     const uint32_t slot = x & (kM - 1);
     const uint32_t s = sm.sym[slot];
     const uint32_t e = sm.fc[s];
-    const uint32_t xs = x >> kProbBits;
-    const uint32_t xn = __umul24(e >> 16, xs) + xs + slot - (e & 0xFFFu);
-    const bool need = act && xn < kL;
+    const uint32_t xn = __umul24(e >> 16, x >> kProbBits) + slot - (e & 0xFFFu);
+    const bool lt = xn < kL;
+    const bool need = kAll ? lt : (act && lt);
     const uint64_t m = __builtin_amdgcn_ballot_w64(need);
     const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
     const uint32_t pos = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(G == 64 || h == 0 ? mlo : 0u, rp));
     uint32_t wd = ring16[(pos & (2 * kChunkW - 1))];
     __asm__ volatile("" : "+v"(wd));  // read for every lane: keeps the update branch-free
-    const uint32_t xa = act ? xn : x;
+    const uint32_t xa = (kAll || act) ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
     rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
-    sm.stage[act ? (t - t0) * W + g : 16 * G] = (uint8_t)s;  // idle lanes: a spare byte
+    sm.stage[(kAll || act) ? so : 16 * G] = (uint8_t)s;  // idle lanes: a spare byte
+    so += W;
   };
   // main loop: steps where every state of both groups has a symbol, kU at a
   // time with one check; then the ragged tail one step at a time
@@ -267,18 +275,18 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     for (; t < t_full; t += kU) {
       prepare(t, kU);
 #pragma unroll
-      for (uint32_t u = 0; u < kU; u++) step(t + u, true);
+      for (uint32_t u = 0; u < kU; u++) step(std::true_type{}, true);
     }
   } else {
     for (; t < t_full; t += kU) {
       prepare(t, kU);
 #pragma unroll
-      for (uint32_t u = 0; u < kU; u++) step(t + u, lane_on);
+      for (uint32_t u = 0; u < kU; u++) step(std::false_type{}, lane_on);
     }
   }
   for (; t < nsteps; t++) {
     prepare(t, 1);
-    step(t, lane_on && g + t * W < n);
+    step(std::false_type{}, lane_on && g + t * W < n);
   }
   wave_sync();
   if (on) flush(nsteps);

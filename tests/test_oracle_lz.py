@@ -180,15 +180,16 @@ def test_level_cap_bounds_depth(orc, cap):
             assert np.all((M == 0) | (O >= b * 4096))
 
 
-@pytest.mark.parametrize("cap", [2, 4, 16])
-def test_level_budget_respected(orc, cap):
+@pytest.mark.parametrize("cap,B,size", [(2, 1024, 1 << 20), (4, 1024, 1 << 20), (16, 1024, 1 << 20),
+                                        (16, 128, 1 << 20)])
+def test_level_budget_respected(orc, cap, B, size):
     # the capped parse policy, checked from the tokens: a block of epoch e
-    # (64 blocks each, E in all) references only blocks of earlier epochs
-    # whose level is below min(cap - 1, floor(log2(e + 1)),
-    # max(1, floor(log2(E + 1)) - 1)); levels then come out geometric
+    # (64 blocks each, E in all, counted in units of c = max(1, E // 64))
+    # references only blocks of earlier epochs whose level is below
+    # min(cap - 1, floor(log2(e // c + 1)), max(1, floor(log2(E // c + 1)) - 1));
+    # levels then come out geometric
     import gen
-    B = 1024
-    x = gen.fastq(1 << 20, 9)
+    x = gen.fastq(size, 9)
     a = orc.encode(x, block_size=B, interleave=8, min_match=16, hash_len=16, max_level=cap)
     level, _, _ = orc.block_facts(a)
     nb = len(level)
@@ -197,7 +198,8 @@ def test_level_budget_respected(orc, cap):
     n_refs = 0
     for b in range(nb):
         e = b // 64
-        lam = min(cap - 1, lg(e + 1), max(1, lg(E + 1) - 1))
+        cu = max(1, E // 64)
+        lam = min(cap - 1, lg(e // cu + 1), max(1, lg(E // cu + 1) - 1))
         _, L, M, O = orc.block_tokens(a, b)
         for m, o in zip(M.tolist(), O.tolist()):
             if m == 0 or o >= b * B:
@@ -207,6 +209,8 @@ def test_level_budget_respected(orc, cap):
                 n_refs += 1
     assert n_refs > 1000  # the rule was exercised
     assert level.max() < cap
+    if E >= 128:  # epochs counted in units of two or more: the first level is wider
+        assert max(1, E // 64) >= 2 and int(np.sum(level == 0)) >= 128
     assert orc.decode(a) == x
 
 
