@@ -92,6 +92,12 @@ def main():
                     help="archive sizes as a fraction of 4/2/1/1 GiB")
     ap.add_argument("--serve-rates", default="1000,5000,20000,100000")
     ap.add_argument("--serve-count", type=int, default=3000)
+    ap.add_argument("--suite", default="",
+                    help="instead of the headline decode, run the other workloads and print one "
+                         "JSON line each: cfg1 (1 MiB genome, decode + every block sought with the "
+                         "three-phase check), cfg3 (1 GiB mixed, 16 and 64 KiB blocks, DAG facts), "
+                         "cfg3u (the same archive uncapped: depth and ratio only), cfg4 (100k "
+                         "seeks on the cfg3 16 KiB archive: one graph replay vs one launch per seek)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -111,6 +117,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.serve:
         return serve_main(args)
+    if args.suite:
+        return suite_main(args)
     t0 = time.time()
     x = gen.by_name(args.profile, args.size, args.seed)
     _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
@@ -325,7 +333,7 @@ def serve_main(args):
         n = int(full * args.serve_scale)
         t0 = time.time()
         x = gen.by_name(name, n, seeds[name])
-        a = encode(x, block_size=args.block, interleave=args.interleave, min_match=mm[name],
+        a = encode(x, block_size=args.block, interleave=args.interleave or 64, min_match=mm[name],
                    hash_len=mm[name], max_chain=32, max_level=args.max_level)
         arcs[name] = Archive(a, device="cuda:0")
         n_total[name] = n
@@ -351,6 +359,193 @@ def serve_main(args):
                                "Poisson arrivals, 16 B..16 MiB log-uniform, 32 GiB budget, 4 slots"
                                % args.serve_scale},
         "runs": runs}), flush=True)
+
+
+def _dag_facts(a: bytes) -> dict:
+    """Depth, level sizes, dependency out-degree and single-block closure sizes
+    read from an archive's index."""
+    import struct
+
+    import numpy as np
+
+    import oracle
+    nb = struct.unpack_from("<I", a, 24)[0]
+    depth = struct.unpack_from("<I", a, 28)[0]
+    ent = np.frombuffer(a, dtype=np.uint32, count=8 * nb, offset=64).reshape(nb, 8)
+    level, dep_cnt = ent[:, 4], ent[:, 6]
+    oracle.build()
+    rng = np.random.default_rng(7)
+    B = struct.unpack_from("<I", a, 8)[0]
+    clos = [len(oracle.closure(a, int(b) * B, int(b) * B + 1)) for b in rng.integers(0, nb, 100)]
+    return {"depth": int(depth), "n_blocks": int(nb),
+            "level_sizes": np.bincount(level, minlength=depth).tolist()[:64],
+            "deps_per_block_mean": round(float(dep_cnt.mean()), 2), "deps_per_block_max": int(dep_cnt.max()),
+            "closure_single_block_p50": float(np.median(clos)), "closure_single_block_max": int(max(clos))}
+
+
+def _time_decode(arc, x_dev, tuning, steps):
+    import torch
+    out = torch.empty(arc.n_total, dtype=torch.uint8, device=arc.device)
+    ws = arc.workspace(arc.workspace_bytes())
+    arc.decode_all(out=out, ws=ws, tuning=tuning)
+    arc.check(ws)
+    ok = bool(torch.equal(out, x_dev))
+    for _ in range(3):
+        arc.decode_all(out=out, ws=ws, tuning=tuning)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        arc.decode_all(out=out, ws=ws, tuning=tuning)
+    e1.record()
+    torch.cuda.synchronize()
+    arc.check(ws)
+    return e0.elapsed_time(e1) / steps, ok
+
+
+def suite_main(args):
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2606_24531_amd import Archive, encode
+    from paper_2606_24531_amd.autotune import tune
+
+    dev = torch.device("cuda:0")
+    which = set(args.suite.split(","))
+    os.environ.setdefault("ACESEEK_ENCODE_PROGRESS", "1")  # 1 GiB encodes take a while
+
+    def emit(d):
+        d.update(n_gpus=1, data="synthetic", dtype="u8")
+        print(json.dumps(d), flush=True)
+
+    if "cfg1" in which:
+        x = gen.genome(1 << 20, 1)
+        a = encode(x, block_size=16384, interleave=32, min_match=20, hash_len=20, max_chain=32)
+        arc = Archive(a, device=dev)
+        xd = torch.frombuffer(bytearray(x), dtype=torch.uint8).to(dev)
+        ms, ok = _time_decode(arc, xd, dict(mode=1), 20)
+        lat, good = [], True
+        for b in range(arc.n_blocks):
+            lo, hi = b * 16384, min(len(x), (b + 1) * 16384)
+            # the paper's three-phase check on the device: a seeded sentinel
+            # everywhere, the region differs before, equals the original
+            # after, and nothing outside it moved (the seek alone is timed)
+            g = torch.Generator(device=dev)
+            g.manual_seed(1000 + b)
+            buf = torch.randint(0, 256, (len(x),), dtype=torch.uint8, device=dev, generator=g)
+            before = buf.clone()
+            phase1 = not torch.equal(buf[lo:hi], xd[lo:hi])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            arc.seek(lo, hi, out=buf[lo:], tuning=dict(mode=1))
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+            arc.check()
+            good = good and phase1 and torch.equal(buf[lo:hi], xd[lo:hi]) and \
+                torch.equal(buf[:lo], before[:lo]) and torch.equal(buf[hi:], before[hi:])
+        _log("cfg1: decode %.4f ms, %d block seeks, three-phase %s" % (ms, arc.n_blocks, good))
+        emit({"metric": "2-layer decode GB/s (full archive); single-block seek latency",
+              "config": {"workload": "genome 1 MiB, 16 KiB blocks, 32-way rANS, uncapped",
+                         "ratio": round(len(x) / len(a), 4), "depth": arc.depth},
+              "value": round(len(x) / ms / 1e6, 3), "unit": "GB/s", "ms_per_step": round(ms, 4),
+              "parity": ok, "seek_p50_ms": round(1e3 * float(np.median(lat)), 4),
+              "seek_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+              "three_phase_all_blocks": good})
+    arc16 = x3 = None
+    if which & {"cfg3", "cfg4", "cfg3u"}:
+        t0 = time.time()
+        x3 = gen.mixed(1 << 30, 3)
+        _log("cfg3: generated 1 GiB mixed in %.1fs" % (time.time() - t0))
+        x3d = torch.frombuffer(bytearray(x3), dtype=torch.uint8).to(dev)
+        for B in ((16384, 65536) if "cfg3" in which else (16384,)):
+            tuned = tune(x3[:32 << 20], "mixed", block_size=B, min_match=16, max_level=16)
+            t0 = time.time()
+            a = encode(x3, block_size=B, interleave=tuned["interleave"], min_match=16, hash_len=16,
+                       max_chain=32, max_level=16)
+            enc_s = time.time() - t0
+            arc = Archive(a, device=dev)
+            shape = dict(mode=1, waves_per_block=tuned["waves_per_block"], blocks_per_wg=tuned["blocks_per_wg"])
+            if "cfg3" in which:
+                ms, ok = _time_decode(arc, x3d, shape, 10)
+                facts = _dag_facts(a)
+                _log("cfg3 B=%d: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
+                    B, len(x3) / len(a), arc.depth, ms, len(x3) / ms / 1e6, ok))
+                emit({"metric": "2-layer decode GB/s (full archive)",
+                      "config": dict({"workload": "mixed 1 GiB, %d KiB blocks, %d-way rANS, level cap 16" % (
+                          B >> 10, tuned["interleave"]), "ratio": round(len(x3) / len(a), 4),
+                          "encode_s": round(enc_s, 1)}, **facts),
+                      "value": round(len(x3) / ms / 1e6, 2), "unit": "GB/s", "ms_per_step": round(ms, 4),
+                      "parity": ok, "tuning": shape})
+            if B == 16384:
+                arc16 = (arc, shape)
+            else:
+                arc.close()
+        if "cfg3u" in which:
+            t0 = time.time()
+            au = encode(x3, block_size=16384, interleave=64, min_match=16, hash_len=16, max_chain=32,
+                        max_level=0)
+            facts = _dag_facts(au)
+            emit({"metric": "DAG depth and ratio without a level cap",
+                  "config": dict({"workload": "mixed 1 GiB, 16 KiB blocks, 64-way rANS, uncapped",
+                                  "ratio": round(len(x3) / len(au), 4), "encode_s": round(time.time() - t0, 1)},
+                                 **facts)})
+            del au
+    if "cfg4" in which:
+        arc, shape = arc16
+        n = len(x3)
+        rng = np.random.default_rng(4)
+        n_req = 100_000
+        ln = np.floor(np.exp(rng.uniform(0, np.log(4 << 20), n_req))).astype(np.int64)
+        lo = (rng.random(n_req) * (n - ln + 1)).astype(np.int64)
+        hi = lo + ln
+        total = int(ln.sum())
+        out = torch.empty(total, dtype=torch.uint8, device=dev)
+        offs = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
+        res = {}
+        for sub in (1000, 10_000, n_req):
+            bt = arc.batch(sub, tuning=shape)
+            rr = (lo[:sub].astype(np.uint64), hi[:sub].astype(np.uint64))
+            bt.run(rr, out, offs[:sub])
+            torch.cuda.synchronize()
+            bt.check()
+            times = []
+            for _ in range(3):
+                t = time.perf_counter()
+                bt.run(rr, out, offs[:sub])
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            bt.check()
+            tb = float(np.median(times))
+            res[sub] = {"latency_ms": round(1e3 * tb, 3), "req_per_s": round(sub / tb, 1),
+                        "out_GB_per_s": round(float(ln[:sub].sum()) / tb / 1e9, 2)}
+            _log("cfg4 batch %d: %.3f ms, %.0f req/s" % (sub, 1e3 * tb, sub / tb))
+            bt.close()
+        # every output of the full batch checked against the original bytes on
+        # a sample of requests
+        sample = rng.choice(n_req, 300, replace=False)
+        good = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x3d[int(lo[i]):int(hi[i])]))
+                   for i in sample)
+        # plain: one seek call (its own launches) per request, waited on
+        ws = torch.zeros(arc.workspace_bytes([0, 1 << 30]), dtype=torch.uint8, device=dev)
+        lat = []
+        n_plain = 2000
+        for i in range(n_plain):
+            t = time.perf_counter()
+            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=shape)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+        arc.check(ws)
+        plain_rate = n_plain / sum(lat)
+        emit({"metric": "p50/p99 seek latency, batched vs plain",
+              "config": {"workload": "mixed 1 GiB resident, 16 KiB blocks; 100k seeks, length "
+                                     "log-uniform 1 B..4 MiB, uniform offsets (seed 4)",
+                         "requests": n_req, "output_bytes": total},
+              "batched": res, "sample_outputs_equal_original": good,
+              "plain": {"requests_timed": n_plain, "p50_ms": round(1e3 * float(np.median(lat)), 4),
+                        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+                        "req_per_s": round(plain_rate, 1)},
+              "batched_vs_plain_throughput": round(res[n_req]["req_per_s"] / plain_rate, 1)})
 
 
 if __name__ == "__main__":

@@ -8,7 +8,7 @@
  * chain over every position of the input:
  *   - hash of X[p .. p+hash_len): h = sum X[p+i] * 0x01000193^(hash_len-1-i)
  *     (mod 2^32), bucket = (h * 0x9E3779B1 mod 2^32) >> (32 - hbits), with
- *     hbits = clamp(ceil(log2 n), 12, 24); prev[p] = the previous position
+ *     hbits = clamp(ceil(log2 n), 12, 27); prev[p] = the previous position
  *     with the same bucket;
  *   - blocks are parsed in order; at p the chain from prev[p] is walked most
  *     recent first for at most max_chain candidates; a candidate q scores
@@ -77,7 +77,7 @@ static uint32_t hash_bits_for(uint64_t n) {
   uint32_t b = 0;
   while (b < 64 && (1ull << b) < n) b++;
   if (b < 12) b = 12;
-  if (b > 24) b = 24;
+  if (b > 27) b = 27;
   return b;
 }
 

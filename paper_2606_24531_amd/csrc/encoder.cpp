@@ -5,7 +5,7 @@
 // Policy (encoder-only; any legal parse decodes the same):
 //   hash of X[p .. p+k): h = sum X[p+i] * 0x01000193^(k-1-i) mod 2^32,
 //   bucket = (h * 0x9E3779B1 mod 2^32) >> (32 - hbits),
-//   hbits = clamp(ceil(log2 n), 12, 24); chains link each position to the
+//   hbits = clamp(ceil(log2 n), 12, 27); chains link each position to the
 //   previous one of its bucket.  At p the chain is walked most recent first
 //   for at most max_chain candidates; a candidate's length is its common
 //   prefix with p (overlap allowed) capped at the block end and 65535.
@@ -32,6 +32,7 @@
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -58,7 +59,7 @@ inline uint64_t rup(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 uint32_t hash_bits(uint64_t n) {
   uint32_t b = 0;
   while (b < 63 && (1ull << b) < n) b++;
-  return std::min<uint32_t>(24, std::max<uint32_t>(12, b));
+  return std::min<uint32_t>(27, std::max<uint32_t>(12, b));
 }
 
 unsigned thread_count(uint32_t want) {
@@ -361,7 +362,18 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
   const uint64_t B = p->block_size, nb = n ? (n + B - 1) / B : 0;
   const uint32_t W = p->interleave, policy = p->flags & 3, ow = 4;
   Chains C;
+  // optional progress lines on stderr (environment ACESEEK_ENCODE_PROGRESS=1),
+  // for callers that must show a long encode is alive
+  const char* pe = getenv("ACESEEK_ENCODE_PROGRESS");
+  const bool progress = pe && pe[0] == '1';
+  std::atomic<uint64_t> parsed{0};
+  auto report = [&](uint64_t done_blocks) {
+    if (progress && nb >= 16 && done_blocks % ((nb + 15) / 16) == 0)
+      fprintf(stderr, "[aceseek encode] parsed %llu of %llu blocks\n", (unsigned long long)done_blocks,
+              (unsigned long long)nb), fflush(stderr);
+  };
   build_chains(x, n, p->hash_len, T, C);
+  if (progress) fprintf(stderr, "[aceseek encode] hash chains built (%llu bytes)\n", (unsigned long long)n), fflush(stderr);
   std::vector<std::vector<Seq>> seqs(nb);
   std::vector<uint32_t> level(nb, 0);
   std::vector<std::vector<uint32_t>> deps(nb);
@@ -380,7 +392,10 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
         deep.erase(std::remove_if(deep.begin(), deep.end(), [&](uint32_t b) { return level[b] < lam; }),
                    deep.end());
       }
-      parallel_for(e1 - e0, T, [&](uint64_t i) { parse_block(pc, e0 + i, true, seqs[e0 + i]); });
+      parallel_for(e1 - e0, T, [&](uint64_t i) {
+        parse_block(pc, e0 + i, true, seqs[e0 + i]);
+        report(++parsed);
+      });
       for (uint64_t b = e0; b < e1; b++) {
         deps_of(seqs[b], b, B, deps[b]);
         uint32_t lv = 0;
@@ -390,7 +405,10 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
       }
     }
   } else {
-    parallel_for(nb, T, [&](uint64_t b) { parse_block(pc, b, false, seqs[b]); });
+    parallel_for(nb, T, [&](uint64_t b) {
+      parse_block(pc, b, false, seqs[b]);
+      report(++parsed);
+    });
     for (uint64_t b = 0; b < nb; b++) {
       deps_of(seqs[b], b, B, deps[b]);
       uint32_t lv = 0;
