@@ -115,6 +115,16 @@ void ace_archive_close(ace_archive* a);
 int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_t* block_size,
                      uint32_t* n_blocks, uint32_t* depth);
 
+/* Optional: the whole-archive decode plan (the blocks in dependency-level
+ * order with the index fields the kernels need, 64 bytes per block) kept
+ * resident on the device.  ace_plan_bytes gives its size; attach uploads it
+ * once into d_plan (caller-owned device memory of at least that many bytes,
+ * kept alive and unmodified while the handle is used; synchronous on
+ * `stream`), and later ace_decode_all calls read it there instead of copying
+ * it from the host on every call. */
+int ace_plan_bytes(const ace_archive* a, uint64_t* bytes);
+int ace_archive_attach_plan(ace_archive* a, void* d_plan, uint64_t bytes, void* stream);
+
 /* Workspace bytes needed to decode the given ranges (ranges == NULL and
  * n_ranges == 0: the whole archive). */
 int ace_workspace_bytes(const ace_archive* a, const ace_range* ranges, uint32_t n_ranges,

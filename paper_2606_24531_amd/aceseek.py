@@ -20,7 +20,7 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
            "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters",
            "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
-           "ace_set_timing", "ace_last_timings"]
+           "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan"]
 
 
 class AceError(RuntimeError):
@@ -80,6 +80,8 @@ def lib():
         L.ace_batch_destroy.restype = None
         L.ace_set_timing.argtypes = [C.c_int]
         L.ace_last_timings.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.ace_plan_bytes.argtypes = [vp, u64p]
+        L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
         _lib = L
     return _lib
 
@@ -190,7 +192,7 @@ def _stream_ptr(stream):
 class Archive:
     """A compressed archive resident in HBM, with a reusable workspace."""
 
-    def __init__(self, data, device="cuda"):
+    def __init__(self, data, device="cuda", resident_plan=True):
         import torch
         self._torch = torch
         host = np.frombuffer(data, dtype=np.uint8) if not isinstance(data, np.ndarray) else data
@@ -208,6 +210,15 @@ class Archive:
         _check(lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)))
         self.n_total, self.block_size, self.n_blocks, self.depth = n.value, B.value, nb.value, depth.value
         self._ws = None
+        # the whole-archive decode plan, resident next to the archive (else
+        # it is copied from the host on every whole-archive decode)
+        self.d_plan = None
+        if resident_plan:
+            pb = C.c_uint64(0)
+            _check(lib().ace_plan_bytes(h, C.byref(pb)))
+            self.d_plan = torch.empty(max(pb.value, 1), dtype=torch.uint8, device=self.device)
+            _check(lib().ace_archive_attach_plan(h, C.c_void_p(self.d_plan.data_ptr()), pb.value,
+                                                 _stream_ptr(torch.cuda.current_stream(self.device))))
 
     def close(self):
         if getattr(self, "_h", None):

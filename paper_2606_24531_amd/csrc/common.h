@@ -17,11 +17,18 @@ constexpr uint32_t kErrCorrupt = 1u, kErrTimeout = 2u;
 
 // One block to decode in a call.  dst is where the block's first byte goes,
 // relative to DecodeArgs::dst_base.
+// One planned block, with the index fields its kernels need, so that a
+// kernel reaches the block's tokens with one load of its plan entry.
 struct PlanEntry {
   uint32_t block;
   uint32_t seq_base;  // first token slot of this block in the token scratch
-  uint64_t dst;
+  uint64_t dst;       // where the block's bytes go (added to dst_base)
+  uint64_t pay;       // offset of the block payload in the archive
+  uint32_t n_seq, n_lit, dep_off, dep_cnt;
+  uint64_t raw[3];    // archive offset of the LIT, LEN, OFF data when stored raw, else kCoded
 };
+static_assert(sizeof(PlanEntry) == 64, "plan entries are 64 bytes");
+constexpr uint64_t kCoded = ~0ull;
 
 // One contiguous copy of decoded bytes: [src_abs, src_abs + len) of the
 // decompressed coordinate space into dst (device address).  Blocks are

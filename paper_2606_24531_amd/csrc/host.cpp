@@ -55,7 +55,9 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
 struct BlockInfo {
-  uint32_t n_seq, level, dep_off, dep_cnt;
+  uint32_t n_seq, level, dep_off, dep_cnt, n_lit;
+  uint64_t pay;
+  uint64_t raw[3];  // archive offset of each stream's data when stored raw, else kCoded
 };
 
 struct ace_archive {
@@ -69,11 +71,27 @@ struct ace_archive {
   std::vector<uint32_t> all_levels;
   uint64_t all_seq = 0;
   PlanEntry* all_plan_pinned = nullptr;
+  const PlanEntry* d_plan = nullptr;  // the whole-archive plan resident on the device, if attached
   std::mutex pin_mu;
   ~ace_archive() {
     if (all_plan_pinned) (void)hipHostFree(all_plan_pinned);
   }
 };
+
+static PlanEntry make_entry(const ace_archive* A, uint32_t b, uint64_t seq_base, uint64_t dst) {
+  const BlockInfo& bi = A->blk[b];
+  PlanEntry e{};
+  e.block = b;
+  e.seq_base = (uint32_t)seq_base;
+  e.dst = dst;
+  e.pay = bi.pay;
+  e.n_seq = bi.n_seq;
+  e.n_lit = bi.n_lit;
+  e.dep_off = bi.dep_off;
+  e.dep_cnt = bi.dep_cnt;
+  for (int t = 0; t < 3; t++) e.raw[t] = bi.raw[t];
+  return e;
+}
 
 extern "C" const char* ace_last_error(void) { return g_err.c_str(); }
 extern "C" void ace_internal_set_error(const char* msg) { g_err = msg; }
@@ -117,6 +135,7 @@ static int validate(const uint8_t* a, uint64_t len, ace_archive* A) {
     bi.level = h32(e + 16);
     bi.dep_off = h32(e + 20);
     bi.dep_cnt = h32(e + 24);
+    bi.pay = pay;
     if (h32(e + 28) != 0) return fail(ACE_E_CORRUPT, "block %u: reserved field is not zero", b);
     if (pay % 16 || pay < pay_at || pay + plen > len || plen < 3 * kSDesc)
       return fail(ACE_E_CORRUPT, "block %u: payload outside the archive", b);
@@ -148,6 +167,8 @@ static int validate(const uint8_t* a, uint64_t len, ace_archive* A) {
       if (mode == 0 && clen != nsym) return fail(ACE_E_CORRUPT, "block %u stream %d: raw size mismatch", b, t);
       if (mode == 1 && (nsym == 0 || clen < 36 + 4 * A->W))
         return fail(ACE_E_CORRUPT, "block %u stream %d: rANS stream too short", b, t);
+      bi.raw[t] = mode == 0 ? pay + off : kCoded;
+      if (t == 0) bi.n_lit = nsym;
     }
   }
   if (max_lv_plus1 != A->depth)
@@ -187,7 +208,7 @@ extern "C" int ace_archive_open(const uint8_t* h_arch, uint64_t len, const void*
   uint64_t seq = 0;
   for (uint32_t i = 0; i < A->nb; i++) {
     const uint32_t b = order[i];
-    A->all_plan[i] = PlanEntry{b, (uint32_t)seq, (uint64_t)b * A->B};
+    A->all_plan[i] = make_entry(A, b, seq, (uint64_t)b * A->B);
     seq += A->blk[b].n_seq;
   }
   if (seq > 0xFFFFFFFFull) {
@@ -374,7 +395,8 @@ void close_range(const ace_archive* A, uint32_t t0, uint32_t t1, std::vector<uin
 static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
-               hipStream_t s, bool entries_pinned, bool loc_linear = false) {
+               hipStream_t s, bool entries_pinned, bool loc_linear = false,
+               const PlanEntry* resident = nullptr) {
   (void)entries_pinned;
   const uint32_t mode = t ? t->mode : 0;
   if (mode == kModePersistent)
@@ -386,7 +408,7 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
   DecodeArgs a{};
   a.arch = A->d_arch;
-  a.plan = reinterpret_cast<const PlanEntry*>(ws + L.plan);
+  a.plan = resident ? resident : reinterpret_cast<const PlanEntry*>(ws + L.plan);
   a.n_plan = (uint32_t)n_plan;
   a.B = A->B;
   a.b_shift = shift_of(A->B);
@@ -406,7 +428,7 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.done = reinterpret_cast<uint32_t*>(ws + L.done);
   a.epoch = 1;
   a.wait_ticks = 10000000ull;  // 100 ms
-  if (n_plan) HIP_TRY(hipMemcpyAsync(ws + L.plan, entries, sizeof(PlanEntry) * n_plan,
+  if (n_plan && !resident) HIP_TRY(hipMemcpyAsync(ws + L.plan, entries, sizeof(PlanEntry) * n_plan,
                                      hipMemcpyHostToDevice, s));
   if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,
                                       hipMemcpyHostToDevice, s));
@@ -500,6 +522,9 @@ extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out
   Layout L = layout(A, A->nb, A->all_seq, 0, 0);
   if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
   if (A->nb == 0) return ACE_OK;
+  if (A->d_plan)
+    return run(A, A->all_plan.data(), A->nb, A->all_levels, nullptr, 0, L, static_cast<uint8_t*>(d_ws),
+               (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), false, true, A->d_plan);
   ace_archive* M = const_cast<ace_archive*>(A);
   const PlanEntry* entries = A->all_plan.data();
   {
@@ -517,6 +542,24 @@ extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out
   }
   return run(A, entries, A->nb, A->all_levels, nullptr, 0, L, static_cast<uint8_t*>(d_ws),
              (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), true, true);
+}
+
+extern "C" int ace_plan_bytes(const ace_archive* A, uint64_t* bytes) {
+  if (!A || !bytes) return fail(ACE_E_ARG, "null argument");
+  *bytes = sizeof(PlanEntry) * (uint64_t)A->nb;
+  return ACE_OK;
+}
+
+extern "C" int ace_archive_attach_plan(ace_archive* A, void* d_plan, uint64_t bytes, void* stream) {
+  if (!A || (!d_plan && A->nb)) return fail(ACE_E_ARG, "null argument");
+  const uint64_t need = sizeof(PlanEntry) * (uint64_t)A->nb;
+  if (bytes < need) return fail(ACE_E_NOSPACE, "the plan needs %llu bytes", (unsigned long long)need);
+  if (A->nb == 0) return ACE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(d_plan, A->all_plan.data(), need, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  A->d_plan = static_cast<const PlanEntry*>(d_plan);
+  return ACE_OK;
 }
 
 extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
@@ -542,8 +585,7 @@ extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t*
     const uint64_t bs = (uint64_t)b * A->B, be = std::min<uint64_t>(bs + A->B, A->n);
     direct[i] = b >= t0 && b <= t1 && bs >= lo && be <= hi;
     if (!direct[i]) n_slots++;
-    entries[i].block = b;
-    entries[i].seq_base = (uint32_t)seq;
+    entries[i] = make_entry(A, b, seq, 0);
     seq += A->blk[b].n_seq;
   }
   for (uint32_t b : {t0, t1}) {
@@ -601,7 +643,7 @@ extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t
   std::vector<PlanEntry> entries(order.size());
   uint64_t sq = 0;
   for (size_t i = 0; i < order.size(); i++) {
-    entries[i] = PlanEntry{order[i], (uint32_t)sq, (uint64_t)(uintptr_t)(ws + L.slots) + i * (uint64_t)A->B};
+    entries[i] = make_entry(A, order[i], sq, (uint64_t)(uintptr_t)(ws + L.slots) + i * (uint64_t)A->B);
     sq += A->blk[order[i]].n_seq;
   }
   return run(A, entries.data(), entries.size(), lstart, items.data(), items.size(), L, ws, 0, t,

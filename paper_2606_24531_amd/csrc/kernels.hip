@@ -313,20 +313,19 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
   const uint32_t i = plan_lo + blockIdx.x * (64 / G) + h;
   bool on = i < plan_hi;
   if (!__ballot(on)) return;
-  const PlanEntry pe = on ? a.plan[i] : PlanEntry{0, 0, 0};
-  const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
-  const uint64_t pay = on ? ld64(be) : 0;
+  PlanEntry pe{};
+  if (on) pe = a.plan[i];
   if (on && t == 0 && g == 0) a.loc[pe.block] = a.dst_base + pe.dst;
+  on = on && pe.raw[t] == kCoded;
+  if (!__ballot(on)) return;  // raw streams are read in place by the expansion
+  const uint64_t pay = pe.pay;
   const uint8_t* d = a.arch + pay + kSDesc * t;
-  uint32_t mode = 0, n = 0, clen = 0, off = 0;
+  uint32_t n = 0, clen = 0, off = 0;
   if (on) {
-    mode = d[0];
     n = ld32(d + 4);
     clen = ld32(d + 8);
     off = ld32(d + 12);
   }
-  on = on && mode != 0;
-  if (!__ballot(on)) return;  // raw streams are read in place by the expansion
   uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
                : t == 1 ? a.lens + 4ull * pe.seq_base
                         : a.offs + (uint64_t)a.ow * pe.seq_base;
@@ -637,22 +636,19 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const uint32_t tid = threadIdx.x;
   const PlanEntry pe = a.plan[i];
   const uint32_t b = pe.block;
-  const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * b;
-  const uint64_t pay = ld64(be);
-  const uint32_t n_seq = ld32(be + 12), dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
+  const uint32_t n_seq = pe.n_seq, dep_off = pe.dep_off, dep_cnt = pe.dep_cnt;
   const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
   // each stream is read in place when stored raw, else from its decoded copy
-  const uint8_t* pl = a.arch + pay;
   BlockCtx c;
-  c.n_lit = ld32(pl + 4);
+  c.n_lit = pe.n_lit;
   c.bs = (uint64_t)b * a.B;
   c.blen = (uint32_t)((a.n_total - c.bs) < a.B ? (a.n_total - c.bs) : a.B);
   c.out = reinterpret_cast<uint8_t*>(a.dst_base + pe.dst);
   c.ext_ok = ext_ok;
   c.dep_cnt = dep_cnt;
-  c.lit = pl[0] == 0 ? pl + ld32(pl + 12) : a.lit + (uint64_t)i * a.B;
-  const uint8_t* lens = pl[16] == 0 ? pl + ld32(pl + 28) : a.lens + 4ull * pe.seq_base;
-  const uint8_t* offs = pl[32] == 0 ? pl + ld32(pl + 44) : a.offs + (uint64_t)a.ow * pe.seq_base;
+  c.lit = pe.raw[0] != kCoded ? a.arch + pe.raw[0] : a.lit + (uint64_t)i * a.B;
+  const uint8_t* lens = pe.raw[1] != kCoded ? a.arch + pe.raw[1] : a.lens + 4ull * pe.seq_base;
+  const uint8_t* offs = pe.raw[2] != kCoded ? a.arch + pe.raw[2] : a.offs + (uint64_t)a.ow * pe.seq_base;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
   const bool cached = dep_cnt <= kDepCache;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
@@ -1100,10 +1096,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void decode_stream(const DecodeArgs& a, const PlanEntry& pe, uint32_t i,
                                               uint32_t t, RansGroup<64>& sm, uint32_t lane) {
-  const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
-  const uint64_t pay = ld64(be);
-  const uint8_t* d = a.arch + pay + kSDesc * t;
+  const uint8_t* d = a.arch + pe.pay + kSDesc * t;
   const uint32_t mode = d[0], n = ld32(d + 4), clen = ld32(d + 8), off = ld32(d + 12);
+  const uint64_t pay = pe.pay;
   uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
                : t == 1 ? a.lens + 4ull * pe.seq_base
                         : a.offs + (uint64_t)a.ow * pe.seq_base;
@@ -1131,8 +1126,7 @@ __global__ __launch_bounds__(64) void k_persist(DecodeArgs a) {
     decode_stream(a, pe, i, 2, rs, lane);
     decode_stream(a, pe, i, 0, rs, lane);
     // dependencies: every listed earlier block must have published
-    const uint8_t* be = a.arch + kHdr + (uint64_t)kBlk * pe.block;
-    const uint32_t dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
+    const uint32_t dep_off = pe.dep_off, dep_cnt = pe.dep_cnt;
     const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
     // Poll with relaxed loads (no cache invalidation per poll), then acquire
     // once.  The wait is bounded in time (the 100 MHz constant clock), and
@@ -1250,7 +1244,22 @@ __global__ __launch_bounds__(1024) void k_bcompact(BatchArgs b) {
     }
     const uint32_t pos = oc + ic - f, seq = os + is - ns;
     if (j < b.n_blocks) b.pre[j] = pos;
-    if (f) b.plan[pos] = PlanEntry{blk, seq, (uint64_t)pos * b.B};
+    if (f) {
+      const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
+      PlanEntry e{};
+      e.block = blk;
+      e.seq_base = seq;
+      e.dst = (uint64_t)pos * b.B;
+      e.pay = ld64(be);
+      e.n_seq = ns;
+      e.dep_off = ld32(be + 20);
+      e.dep_cnt = ld32(be + 24);
+      const uint8_t* d = b.arch + e.pay;
+      e.n_lit = ld32(d + 4);
+      for (uint32_t t = 0; t < 3; t++)
+        e.raw[t] = d[kSDesc * t] == 0 ? e.pay + ld32(d + kSDesc * t + 12) : kCoded;
+      b.plan[pos] = e;
+    }
     __syncthreads();
     if (tid == 0) {
       base_cnt += tc;

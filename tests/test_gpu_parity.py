@@ -90,6 +90,17 @@ def test_decode_all_matches_oracle(dev, ace, archives, case, tuning):
                     (bad[0], bad[0] // case[2], bad.size))
 
 
+@pytest.mark.parametrize("case", CASES[:6], ids=_case_id)
+def test_decode_all_plan_copied_per_call(dev, ace, archives, case):
+    """Without a device-resident plan the plan is copied from the host on each call."""
+    x, a, ref = archives[case]
+    arc = ace.Archive(a, device=dev, resident_plan=False)
+    for _ in range(2):
+        out = arc.decode_all(tuning=dict(mode=1))
+        arc.check()
+        assert _host(out) == ref
+
+
 SHAPES = [dict(mode=3, waves_per_block=2), dict(mode=1, waves_per_block=8, blocks_per_wg=1)]
 
 

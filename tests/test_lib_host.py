@@ -71,6 +71,20 @@ def test_two_streams_per_wave_needs_narrow_interleave(lib):
     L.ace_archive_close(h)
 
 
+def test_plan_bytes_and_attach_errors(lib):
+    x = gen.text(100_000, 2)
+    a = lib.encode(x, block_size=4096, interleave=8, min_match=8, hash_len=8)
+    rc, h = _open(lib, a)
+    assert rc == 0
+    L = lib.lib()
+    pb = C.c_uint64()
+    assert L.ace_plan_bytes(h, C.byref(pb)) == 0
+    assert pb.value == 64 * 25  # one 64-byte entry per block
+    assert L.ace_archive_attach_plan(h, C.c_void_p(0x1000), pb.value - 1, None) == lib.E_NOSPACE
+    assert L.ace_archive_attach_plan(h, None, pb.value, None) == lib.E_ARG
+    L.ace_archive_close(h)
+
+
 def _open(lib, a: bytes):
     L = lib.lib()
     h = C.c_void_p()
