@@ -519,6 +519,19 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
   }
 }
 
+// Block-relative position of slow byte u of the tile: slot k's slow bytes
+// end at sm.ptr[k] (its match bytes, numbered in sequence order).
+template <uint32_t kThreads>
+__device__ __forceinline__ uint32_t slow_pos(const ExpandSmem<kThreads>& sm, const BlockCtx& c, uint32_t u) {
+  uint32_t lo = 0, hi = c.cnt;  // first slot whose slow-byte end exceeds u
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sm.ptr[mid] > u) hi = mid; else lo = mid + 1;
+  }
+  const uint32_t Mk = sm.lm[lo] >> 16, Lk = sm.lm[lo] & 0xFFFFu;
+  return sm.dst[lo] + Lk + (u - (sm.ptr[lo] - Mk));
+}
+
 // Readable bytes around a resolved span's address: back (capped at 31) and
 // forward (capped at 2^26).
 __device__ __forceinline__ uint32_t win_pack(uint64_t back, uint64_t fwd) {
@@ -885,17 +898,18 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         if (tid == 0) sm.carry = all;
       }
       __syncthreads();
-      // classify this thread's four chunks; a copy chunk's five source dwords
-      // are loaded at once (stored after all four are classified), per-byte
-      // chunks are appended to a list (one LDS atomic per wavefront)
-      uint32_t w[4][5];
-      uint32_t shv[4];
+      // Phase A (LDS only): classify this thread's four chunks (a copy chunk
+      // records its source; the others are appended to a list, one LDS
+      // atomic per wavefront) and, when the tile is one round, follow this
+      // thread's slow byte back to its source.
+      const bool fold = nch <= kRound;  // slow bytes written in this round
+      const uint8_t* vsrc[4];
       uint32_t cbv[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         const uint32_t k = k0 + tid + j * kThreads;
         cbv[j] = 0xFFFFFFFFu;
-        shv[j] = 0;
+        vsrc[j] = c.lit;
         const bool here = k < k0 + kn;
         const uint32_t cb = base + 16 * k;
         bool vec = false;
@@ -922,11 +936,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               src = reinterpret_cast<const uint8_t*>(sa);
             }
             if (vec) {
-              const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
-              const uint32_t* wp = reinterpret_cast<const uint32_t*>(src - sh);
-#pragma unroll
-              for (uint32_t q = 0; q < 5; q++) w[j][q] = wp[q];
-              shv[j] = sh;
+              vsrc[j] = src;
               cbv[j] = cb;
             }
           }
@@ -941,10 +951,39 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
         if (byte) sm.list[bb + below_b] = (k << kSB) | sq;
       }
+      uint32_t slow_p = 0xFFFFFFFFu;
+      const uint8_t* slow_a = nullptr;
+      if (fold && tid < n_slow) {
+        slow_p = slow_pos<kThreads>(sm, c, tid);
+        slow_a = resolve_addr<kThreads>(a, sm, c, slow_p, n_ext);
+      }
+      __syncthreads();
+      const uint32_t nby = sm.nbyte;
+      // Phase B: every load of this thread is issued before any is used: the
+      // copy chunks' source dwords, its slow byte, and (through the segment
+      // path) its first listed chunk.
+      uint32_t w[4][5];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t* wp = reinterpret_cast<const uint32_t*>(vsrc[j] - ((uintptr_t)vsrc[j] & 3));
+#pragma unroll
+        for (uint32_t q = 0; q < 5; q++) w[j][q] = cbv[j] != 0xFFFFFFFFu ? wp[q] : 0u;
+      }
+      const uint32_t slow_v = slow_a ? (uint32_t)*slow_a : 0u;
+      bool seg_done = false;
+      uint32_t seg_cb = 0, o4[4] = {0, 0, 0, 0};
+      if (tid < nby) {
+        const uint32_t e = sm.list[tid], k = e >> kSB;
+        seg_cb = base + 16 * k;
+        const uint32_t p0 = seg_cb < d0 ? d0 : seg_cb;
+        const uint32_t pe1 = seg_cb + 16 < d1 ? seg_cb + 16 : d1;
+        if (aligned && p0 == seg_cb && pe1 == seg_cb + 16)
+          seg_done = seg_chunk<kThreads>(sm, c, seg_cb, e & kSM, d1, o4);
+      }
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         if (cbv[j] != 0xFFFFFFFFu) {
-          const uint32_t sh = shv[j];
+          const uint32_t sh = (uint32_t)((uintptr_t)vsrc[j] & 3);
           *reinterpret_cast<uint4*>(c.out + cbv[j]) =
               make_uint4(__builtin_amdgcn_alignbyte(w[j][1], w[j][0], sh),
                          __builtin_amdgcn_alignbyte(w[j][2], w[j][1], sh),
@@ -952,24 +991,25 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
                          __builtin_amdgcn_alignbyte(w[j][4], w[j][3], sh));
         }
       }
-      __syncthreads();
-      const uint32_t nby = sm.nbyte;
-      // per-byte chunks: every byte's source address first, then the 16
-      // loads back to back, so their latencies overlap.  The current
-      // sequence's fields stay in registers (LDS is read only when the walk
-      // enters the next sequence), and match bytes step their source offset
-      // by one, wrapping at the period.  Bytes of slow sequences get a
-      // placeholder here; the slow pass below writes them.
+      if (seg_done) *reinterpret_cast<uint4*>(c.out + seg_cb) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+      // per-byte path: listed chunks the segment path declined or that lie
+      // beyond the first kThreads entries.  Every byte's source address
+      // first, then the 16 loads back to back.  The current sequence's
+      // fields stay in registers (LDS is read only when the walk enters the
+      // next sequence), and match bytes step their source offset by one,
+      // wrapping at the period.  Bytes of slow sequences get a placeholder
+      // here; the slow bytes are written after the barrier below.
       for (uint32_t ei = tid; ei < nby; ei += kThreads) {
+        if (ei == tid && seg_done) continue;
         const uint32_t e = sm.list[ei], k = e >> kSB;
         const uint32_t cb = base + 16 * k;
         const uint32_t p0 = cb < d0 ? d0 : cb;
         const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
         uint32_t s = e & kSM;
-        if (aligned && p0 == cb && pe1 == cb + 16) {
-          uint32_t o4[4];
-          if (seg_chunk<kThreads>(sm, c, cb, s, d1, o4)) {
-            *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+        if (ei != tid && aligned && p0 == cb && pe1 == cb + 16) {
+          uint32_t q4[4];
+          if (seg_chunk<kThreads>(sm, c, cb, s, d1, q4)) {
+            *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(q4[0], q4[1], q4[2], q4[3]);
             continue;
           }
         }
@@ -1033,19 +1073,17 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         }
       }
       __syncthreads();
+      // the slow bytes loaded above, after every chunk store of the round
+      if (slow_p != 0xFFFFFFFFu) c.out[slow_p] = (uint8_t)slow_v;
+      __syncthreads();
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
     // sequences, tiles or non-adjacent blocks), one byte per thread, each
     // followed back to its origin
-    if (n_slow) {
-      for (uint32_t u = tid; u < n_slow; u += kThreads) {
-        uint32_t lo = 0, hi = c.cnt;  // first slot whose slow-byte end exceeds u
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (sm.ptr[mid] > u) hi = mid; else lo = mid + 1;
-        }
-        const uint32_t Mk = sm.lm[lo] >> 16, Lk = sm.lm[lo] & 0xFFFFu;
-        const uint32_t p = sm.dst[lo] + Lk + (u - (sm.ptr[lo] - Mk));
+    const uint32_t slow_from = nch <= kRound ? kThreads : 0u;  // the first ones went with the round
+    if (n_slow > slow_from) {
+      for (uint32_t u = slow_from + tid; u < n_slow; u += kThreads) {
+        const uint32_t p = slow_pos<kThreads>(sm, c, u);
         const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
         c.out[p] = q ? *q : (uint8_t)0;
       }
