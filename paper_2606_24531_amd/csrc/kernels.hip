@@ -313,12 +313,21 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
   const uint32_t i = plan_lo + blockIdx.x * (64 / G) + h;
   bool on = i < plan_hi;
   if (!__ballot(on)) return;
-  PlanEntry pe{};
-  if (on) pe = a.plan[i];
-  if (on && t == 0 && g == 0) a.loc[pe.block] = a.dst_base + pe.dst;
-  on = on && pe.raw[t] == kCoded;
+  // only the fields this kernel needs (no whole-entry copy: raw[t] is
+  // indexed by the grid's y coordinate)
+  const PlanEntry* pp = a.plan + (on ? i : 0);
+  uint32_t blk = 0, seq_base = 0;
+  uint64_t pdst = 0, pay = 0, raw_t = kCoded;
+  if (on) {
+    blk = pp->block;
+    seq_base = pp->seq_base;
+    pdst = pp->dst;
+    pay = pp->pay;
+    raw_t = pp->raw[t];
+  }
+  if (on && t == 0 && g == 0) a.loc[blk] = a.dst_base + pdst;
+  on = on && raw_t == kCoded;
   if (!__ballot(on)) return;  // raw streams are read in place by the expansion
-  const uint64_t pay = pe.pay;
   const uint8_t* d = a.arch + pay + kSDesc * t;
   uint32_t n = 0, clen = 0, off = 0;
   if (on) {
@@ -327,8 +336,8 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
     off = ld32(d + 12);
   }
   uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
-               : t == 1 ? a.lens + 4ull * pe.seq_base
-                        : a.offs + (uint64_t)a.ow * pe.seq_base;
+               : t == 1 ? a.lens + 4ull * seq_base
+                        : a.offs + (uint64_t)a.ow * seq_base;
   const uint8_t* src = a.arch + pay + off;
   if (rans_decode_group<G>(src, clen, n, a.W, dst, sm[h], g, h, on) && g == 0) flag(a.err, kErrCorrupt);
 }
