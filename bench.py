@@ -230,7 +230,7 @@ def main():
             "n_total": len(x), "archive_bytes": len(a), "ratio": round(len(x) / len(a), 4),
             "block_size": args.block, "interleave": args.interleave,
             "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
-            "waves_per_block": args.waves_per_block or 4,
+            "waves_per_block": args.waves_per_block or 2,
             "streams_per_wave": args.per_wave or (2 if args.interleave <= 32 else 1),
             "autotuned": tuned is not None,
             "mode": {1: "per-level launches, one stream",

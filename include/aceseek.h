@@ -67,7 +67,7 @@ typedef struct {
 /* Launch shape.  Zero fields take the library defaults; a value this build
  * does not offer is ACE_E_ARG.
  *  waves_per_block  wavefronts cooperating on one block's match expansion:
- *                   2, 4 or 8 (0 = 4); each takes two sequences per lane
+ *                   1, 2, 4 or 8 (0 = 2); each takes two sequences per lane
  *                   per tile
  *  blocks_per_wg    blocks whose streams one entropy wavefront decodes side
  *                   by side: 1, or 2 when the interleave is at most 32

@@ -39,7 +39,7 @@ def _time_decode(arc, tuning, reps: int, torch) -> float:
 
 
 def tune(sample: bytes, profile: str, block_size: int = 16384, min_match: int = 20,
-         max_level: int = 16, widths=(32, 64), waves=(2, 4), reps: int = 5,
+         max_level: int = 16, widths=(32, 64), waves=(1, 2, 4), reps: int = 5,
          cache_path: str = DEFAULT_CACHE, log=None) -> dict:
     """Returns the best {"interleave", "waves_per_block", "blocks_per_wg",
     "mode"} (with its time) and caches it."""

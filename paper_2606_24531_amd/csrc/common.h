@@ -85,7 +85,7 @@ struct BatchArgs {
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
 // per_wave: streams one wavefront decodes (0 = 2 when W <= 32, else 1);
-// waves: wavefronts per block in the expansion (2, 4 or 8; 0 = 4)
+// waves: wavefronts per block in the expansion (1, 2, 4 or 8; 0 = 2)
 hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s);
 hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi, uint32_t waves,
                                hipStream_t s);

@@ -290,8 +290,8 @@ hipError_t overlap_for(size_t n_levels, Overlap*& o) {
 int check_tuning(const ace_archive* A, const ace_tuning* t) {
   if (!t) return ACE_OK;
   const uint32_t w = t->waves_per_block, p = t->blocks_per_wg;
-  if (w != 0 && w != 2 && w != 4 && w != 8)
-    return fail(ACE_E_ARG, "waves_per_block %u: 2, 4 or 8 (0 = 4)", w);
+  if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8)
+    return fail(ACE_E_ARG, "waves_per_block %u: 1, 2, 4 or 8 (0 = 2)", w);
   if (p > 2 || (p == 2 && A->W > 32))
     return fail(ACE_E_ARG, "blocks_per_wg %u: 1, or 2 when the interleave is at most 32", p);
   if (t->lut_variant != 0) return fail(ACE_E_ARG, "lut_variant %u: only 0 is built", t->lut_variant);

@@ -1037,41 +1037,50 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           started = false;
         };
         view();
-        const uint8_t* ad[16];
-        uint32_t zero = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < 16; j++) {
-          const uint32_t p = cb + j;
-          const uint8_t* q = nullptr;
-          if (p >= p0 && p < pe1) {
-            while (p >= se) {
-              s++;
-              view();
-            }
-            const uint32_t r = p - sd;
-            if (sf & kPoison) {
-              q = nullptr;  // a format rule failed: write zeros, read nothing
-            } else if (r < sL) {
-              q = litp + r;
-            } else if (!(sf & kUnres)) {
-              if (!started) {
-                const uint32_t ii = r - sL;
-                im = ii < sdist ? ii : ii % sdist;
-                started = true;
-              } else if (++im == sdist) {
-                im = 0;
-              }
-              q = reinterpret_cast<const uint8_t*>(src0 + im);
-            }
-          }
-          zero |= (q == nullptr ? 1u : 0u) << j;
-          ad[j] = q == nullptr ? c.lit : q;  // c.lit is always readable
-        }
+        // two halves of eight bytes (this path is rare; halves keep its
+        // registers below those of the main path)
         uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll 1
+        for (uint32_t hf = 0; hf < 2; hf++) {
+          const uint8_t* ad[8];
+          uint32_t zero = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < 16; j++) {
-          const uint32_t v = *ad[j];
-          acc[j >> 2] |= ((zero >> j) & 1u ? 0u : v) << (8 * (j & 3));
+          for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t p = cb + 8 * hf + j;
+            const uint8_t* q = nullptr;
+            if (p >= p0 && p < pe1) {
+              while (p >= se) {
+                s++;
+                view();
+              }
+              const uint32_t r = p - sd;
+              if (sf & kPoison) {
+                q = nullptr;  // a format rule failed: write zeros, read nothing
+              } else if (r < sL) {
+                q = litp + r;
+              } else if (!(sf & kUnres)) {
+                if (!started) {
+                  const uint32_t ii = r - sL;
+                  im = ii < sdist ? ii : ii % sdist;
+                  started = true;
+                } else if (++im == sdist) {
+                  im = 0;
+                }
+                q = reinterpret_cast<const uint8_t*>(src0 + im);
+              }
+            }
+            zero |= (q == nullptr ? 1u : 0u) << j;
+            ad[j] = q == nullptr ? c.lit : q;  // c.lit is always readable
+          }
+          uint32_t lo4 = 0, hi4 = 0;
+#pragma unroll
+          for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t v = (zero >> j) & 1u ? 0u : (uint32_t)*ad[j];
+            if (j < 4) lo4 |= v << (8 * j);
+            else hi4 |= v << (8 * (j - 4));
+          }
+          acc[2 * hf] = lo4;
+          acc[2 * hf + 1] = hi4;
         }
         if (aligned && p0 == cb && pe1 == cb + 16) {
           *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
@@ -1377,9 +1386,10 @@ static hipError_t launch_expand(const DecodeArgs& a, uint32_t grid, uint32_t pla
                                 uint32_t waves, hipStream_t s) {
   if (grid == 0) return hipSuccess;
   switch (waves) {
-    case 2: hipLaunchKernelGGL(k_expand<128>, dim3(grid), dim3(128), 0, s, a, plan_lo, level); break;
+    case 1: hipLaunchKernelGGL(k_expand<64>, dim3(grid), dim3(64), 0, s, a, plan_lo, level); break;
+    case 4: hipLaunchKernelGGL(k_expand<256>, dim3(grid), dim3(256), 0, s, a, plan_lo, level); break;
     case 8: hipLaunchKernelGGL(k_expand<512>, dim3(grid), dim3(512), 0, s, a, plan_lo, level); break;
-    default: hipLaunchKernelGGL(k_expand<256>, dim3(grid), dim3(256), 0, s, a, plan_lo, level); break;
+    default: hipLaunchKernelGGL(k_expand<128>, dim3(grid), dim3(128), 0, s, a, plan_lo, level); break;
   }
   return hipGetLastError();
 }

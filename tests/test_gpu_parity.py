@@ -101,13 +101,14 @@ def test_decode_all_plan_copied_per_call(dev, ace, archives, case):
         assert _host(out) == ref
 
 
-SHAPES = [dict(mode=3, waves_per_block=2), dict(mode=1, waves_per_block=8, blocks_per_wg=1)]
+SHAPES = [dict(mode=3, waves_per_block=2), dict(mode=1, waves_per_block=8, blocks_per_wg=1),
+          dict(mode=1, waves_per_block=1)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=_case_id)
-@pytest.mark.parametrize("tuning", SHAPES, ids=["2waves", "8waves-1stream"])
+@pytest.mark.parametrize("tuning", SHAPES, ids=["2waves", "8waves-1stream", "1wave"])
 def test_decode_all_launch_shapes(dev, ace, archives, case, tuning):
-    """The other expansion workgroup sizes (128 and 512 threads, so other
+    """The other expansion workgroup sizes (64, 128 and 512 threads, so other
     tile sizes) and one entropy stream per wavefront give the same bytes."""
     x, a, ref = archives[case]
     arc = ace.Archive(a, device=dev)
