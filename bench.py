@@ -79,7 +79,7 @@ def main():
                          "one stream; 3: entropy decode per level on a second stream beside the "
                          "per-level expansion")
     ap.add_argument("--waves-per-block", type=int, default=0,
-                    help="wavefronts per block in the match expansion (2, 4, 8; 0 = library default)")
+                    help="wavefronts per block in the match expansion (1, 2, 4, 8; 0 = chosen per launch by its size)")
     ap.add_argument("--per-wave", type=int, default=0,
                     help="entropy streams per wavefront (1, or 2 when W <= 32; 0 = library default)")
     ap.add_argument("--seek-requests", type=int, default=2000)
@@ -133,8 +133,8 @@ def main():
             args.waves_per_block = tuned["waves_per_block"]
         if not args.per_wave:
             args.per_wave = tuned["blocks_per_wg"]
-        _log("autotune (%.1fs): W=%d, %d waves per block, %d streams per wave" % (
-            time.time() - t0, args.interleave, args.waves_per_block, args.per_wave))
+        _log("autotune (%.1fs): W=%d, %s waves per block, %d streams per wave" % (
+            time.time() - t0, args.interleave, args.waves_per_block or "auto", args.per_wave))
     t0 = time.time()
     a = encode(x, block_size=args.block, interleave=args.interleave, min_match=args.min_match,
                hash_len=args.min_match, max_chain=32, max_level=args.max_level)
@@ -230,7 +230,7 @@ def main():
             "n_total": len(x), "archive_bytes": len(a), "ratio": round(len(x) / len(a), 4),
             "block_size": args.block, "interleave": args.interleave,
             "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
-            "waves_per_block": args.waves_per_block or 2,
+            "waves_per_block": args.waves_per_block or "auto",
             "streams_per_wave": args.per_wave or (2 if args.interleave <= 32 else 1),
             "autotuned": tuned is not None,
             "mode": {1: "per-level launches, one stream",

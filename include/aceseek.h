@@ -67,8 +67,11 @@ typedef struct {
 /* Launch shape.  Zero fields take the library defaults; a value this build
  * does not offer is ACE_E_ARG.
  *  waves_per_block  wavefronts cooperating on one block's match expansion:
- *                   1, 2, 4 or 8 (0 = 2); each takes two sequences per lane
- *                   per tile
+ *                   1, 2, 4 or 8; each takes two sequences per lane per
+ *                   tile.  0 = per launch: 4 while the launch's blocks fit
+ *                   on the device at once as four-wavefront workgroups
+ *                   (then one block's latency sets the time), else 2 (more
+ *                   blocks in flight)
  *  blocks_per_wg    blocks whose streams one entropy wavefront decodes side
  *                   by side: 1, or 2 when the interleave is at most 32
  *                   (0 = 2 when possible)

@@ -1,8 +1,11 @@
 """Autotuner for the decode launch shape.
 
 Searches, on a sample of the workload, the interleave width W (32 or 64;
-the sample is re-encoded, since W is an archive parameter), the wavefronts
-per block of the match expansion and the entropy streams per wavefront.
+the sample is re-encoded, since W is an archive parameter) and the entropy
+streams per wavefront.  The wavefronts per block of the match expansion are
+left to the library's per-launch choice by default (0), which depends on
+each level's size: a sample's levels are smaller than the whole workload's,
+so a fixed count tuned on it would be biased toward large workgroups.
 Each candidate is timed as whole-archive decodes of the sample with HIP
 events; the fastest is cached as JSON keyed by (GPU architecture, block
 size, profile).
@@ -39,7 +42,7 @@ def _time_decode(arc, tuning, reps: int, torch) -> float:
 
 
 def tune(sample: bytes, profile: str, block_size: int = 16384, min_match: int = 20,
-         max_level: int = 16, widths=(32, 64), waves=(1, 2, 4), reps: int = 5,
+         max_level: int = 16, widths=(32, 64), waves=(0,), reps: int = 5,
          cache_path: str = DEFAULT_CACHE, log=None) -> dict:
     """Returns the best {"interleave", "waves_per_block", "blocks_per_wg",
     "mode"} (with its time) and caches it."""

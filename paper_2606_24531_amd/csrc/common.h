@@ -85,7 +85,9 @@ struct BatchArgs {
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
 // per_wave: streams one wavefront decodes (0 = 2 when W <= 32, else 1);
-// waves: wavefronts per block in the expansion (1, 2, 4 or 8; 0 = 2)
+// waves: wavefronts per block in the expansion (1, 2, 4 or 8; 0 = 4 while
+// the launch's blocks fit on the device at once as four-wavefront
+// workgroups, else 2)
 hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s);
 hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi, uint32_t waves,
                                hipStream_t s);
@@ -103,6 +105,9 @@ hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave,
 // lvl_dev; width = the most entries those levels can hold
 hipError_t launch_rans_levels_dev(const DecodeArgs& a, uint32_t lv_lo, uint32_t lv_hi, uint32_t width,
                                   uint32_t per_wave, hipStream_t s);
+// queries (once per device) what the automatic expansion shape needs; call
+// before a stream capture that launches expansions
+hipError_t prepare_expand_shapes();
 hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
                                    hipStream_t s);
 

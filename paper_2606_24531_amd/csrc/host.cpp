@@ -291,7 +291,7 @@ int check_tuning(const ace_archive* A, const ace_tuning* t) {
   if (!t) return ACE_OK;
   const uint32_t w = t->waves_per_block, p = t->blocks_per_wg;
   if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8)
-    return fail(ACE_E_ARG, "waves_per_block %u: 1, 2, 4 or 8 (0 = 2)", w);
+    return fail(ACE_E_ARG, "waves_per_block %u: 1, 2, 4 or 8 (0 = by launch size)", w);
   if (p > 2 || (p == 2 && A->W > 32))
     return fail(ACE_E_ARG, "blocks_per_wg %u: 1, or 2 when the interleave is at most 32", p);
   if (t->lut_variant != 0) return fail(ACE_E_ARG, "lut_variant %u: only 0 is built", t->lut_variant);
@@ -842,6 +842,10 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
         rc = fail(ACE_E_HIP, "stream or event creation failed");
         break;
       }
+    }
+    if (waves == 0 && prepare_expand_shapes() != hipSuccess) {
+      rc = fail(ACE_E_HIP, "device occupancy query failed");
+      break;
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       rc = fail(ACE_E_HIP, "graph capture could not start");

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -1380,11 +1381,37 @@ hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t p
   return launch_rans_any(a, lo, hi, -1, -1, per_wave, s);
 }
 
+// Four-wavefront expansion workgroups the current device holds at once
+// (0 if the query fails), cached per device.
+static uint32_t expand4_resident() {
+  static std::atomic<uint32_t> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  uint32_t v = cache[dev].load(std::memory_order_relaxed);
+  if (v) return v;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_expand<256>, 256, 0) != hipSuccess ||
+      cus <= 0 || per_cu <= 0)
+    return 0;
+  v = (uint32_t)cus * (uint32_t)per_cu;
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
+hipError_t prepare_expand_shapes() { return expand4_resident() ? hipSuccess : hipErrorUnknown; }
+
 // One expansion launch: grid blocks from plan_lo, or (level >= 0) the plan
-// range of that level read from device memory; waves = wavefronts per block.
+// range of that level read from device memory; waves = wavefronts per block,
+// 0 = chosen by the launch's size.  While the launch's blocks all fit on the
+// device at once as four-wavefront workgroups, one block's latency sets the
+// launch's time and four wavefronts per block shorten it; beyond that the
+// blocks in flight set it, and two-wavefront workgroups (same registers per
+// wavefront, half the LDS per block) keep twice as many.
 static hipError_t launch_expand(const DecodeArgs& a, uint32_t grid, uint32_t plan_lo, int level,
                                 uint32_t waves, hipStream_t s) {
   if (grid == 0) return hipSuccess;
+  if (waves == 0) waves = grid <= expand4_resident() ? 4u : 2u;
   switch (waves) {
     case 1: hipLaunchKernelGGL(k_expand<64>, dim3(grid), dim3(64), 0, s, a, plan_lo, level); break;
     case 4: hipLaunchKernelGGL(k_expand<256>, dim3(grid), dim3(256), 0, s, a, plan_lo, level); break;
