@@ -33,20 +33,44 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(v, d, 64);
-    if (lane >= (uint32_t)d) v += y;
-  }
-  return v;
+// Lane-shifted copy of v for an inclusive scan (DPP, no LDS): kCtl selects
+// the source lane (row_shr:n = 0x110 + n within rows of 16 lanes; 0x142 =
+// row_bcast:15, the last lane of each row into the next row; 0x143 =
+// row_bcast:31, lane 31 into rows 2 and 3) and kRows the rows written.
+// Lanes without a source, or in rows not written, read 0: the identity of
+// both sum and max over unsigned values.
+template <int kCtl, int kRows>
+__device__ __forceinline__ uint32_t dpp_src(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtl, kRows, 0xf, false);
 }
 
-__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+// Inclusive scan over aligned groups of G lanes (G = 32 or 64) under op (a
+// sum or a max): shifts by 1, 2, 4 and 8 within each row, then row 0's and
+// row 2's last lanes into rows 1 and 3; for G = 64 also lane 31 into rows 2
+// and 3.  Every lane of the wavefront must be active.
+template <uint32_t G, typename Op>
+__device__ __forceinline__ uint32_t grp_scan(uint32_t v, Op op) {
+  static_assert(G == 32 || G == 64, "groups of 32 or 64 lanes");
+  v = op(v, dpp_src<0x111, 0xf>(v));
+  v = op(v, dpp_src<0x112, 0xf>(v));
+  v = op(v, dpp_src<0x114, 0xf>(v));
+  v = op(v, dpp_src<0x118, 0xf>(v));
+  v = op(v, dpp_src<0x142, 0xa>(v));
+  if (G == 64) v = op(v, dpp_src<0x143, 0xc>(v));
   return v;
 }
+struct OpAdd {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; }
+};
+struct OpMax {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; }
+};
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t) { return grp_scan<64>(v, OpAdd{}); }
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) { return grp_scan<64>(v, OpMax{}); }
+// the value of lane 63 (uniform)
+__device__ __forceinline__ uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) { return lane63(wave_incl_sum(v, 0)); }
 
 __device__ __forceinline__ void flag(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
 
@@ -86,21 +110,15 @@ struct RansGroup {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Inclusive prefix sum and total over aligned groups of G lanes.
+// Inclusive prefix sum over aligned groups of G lanes, and the group's
+// total read from its last lane (group h = lane / G).
 template <uint32_t G>
-__device__ __forceinline__ uint32_t grp_incl_sum(uint32_t v, uint32_t g) {
-#pragma unroll
-  for (uint32_t d = 1; d < G; d <<= 1) {
-    uint32_t y = __shfl_up(v, d, G);
-    if (g >= d) v += y;
-  }
-  return v;
-}
+__device__ __forceinline__ uint32_t grp_incl_sum(uint32_t v) { return grp_scan<G>(v, OpAdd{}); }
 template <uint32_t G>
-__device__ __forceinline__ uint32_t grp_total(uint32_t v) {
-#pragma unroll
-  for (uint32_t d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, G);
-  return v;
+__device__ __forceinline__ uint32_t grp_last(uint32_t incl, uint32_t h) {
+  if (G == 64) return lane63(incl);
+  const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)incl, 31), t1 = lane63(incl);
+  return h ? t1 : t0;
 }
 
 // Whether any lane of group h has v set.
@@ -126,8 +144,9 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
                         : G == 64 ? ((uint32_t)src[g >> 1] >> ((g & 1) * 4)) & 0xFu
                                   : (uint32_t)src[g];
   const uint32_t cnt = __popc(bits);
-  const uint32_t before = grp_incl_sum<G>(cnt, g) - cnt;
-  const uint32_t present = grp_total<G>(cnt);
+  const uint32_t cnt_in = grp_incl_sum<G>(cnt);
+  const uint32_t before = cnt_in - cnt;
+  const uint32_t present = grp_last<G>(cnt_in, h);
   const uint32_t tsz = (32 + 2 * present + 3) & ~3u;
   if (on && (present == 0 || tsz + 4 * W > clen || ((clen - tsz - 4 * W) & 1))) bad = true;
   on = on && !bad;
@@ -137,8 +156,9 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     f[j] = (on && ((bits >> j) & 1)) ? ld16(src + 32 + 2 * (k++)) + 1 : 0;
     mysum += f[j];
   }
-  uint32_t cum = grp_incl_sum<G>(mysum, g) - mysum;
-  const uint32_t total = grp_total<G>(mysum);
+  const uint32_t sum_in = grp_incl_sum<G>(mysum);
+  uint32_t cum = sum_in - mysum;
+  const uint32_t total = grp_last<G>(sum_in, h);
   if (on && total != kM) bad = true;
   on = on && !bad;
   for (uint32_t j = g; j < 64; j += G) sm.u.b.starts[j] = 0ull;
@@ -164,7 +184,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     uint32_t pc = 0;
 #pragma unroll
     for (uint32_t q = 0; q < kWpl; q++) pc += __popcll(sm.u.b.starts[kWpl * g + q]);
-    int rank = (int)(grp_incl_sum<G>(pc, g) - pc) - 1;
+    int rank = (int)(grp_incl_sum<G>(pc) - pc) - 1;
     uint32_t cur = (on && rank >= 0) ? sm.u.b.by_rank[rank] : 0u;
     uint32_t* out32 = reinterpret_cast<uint32_t*>(sm.sym) + 16 * kWpl * g;
     if (on) {
@@ -379,8 +399,8 @@ struct ExpandSmem {
   static constexpr uint32_t kRound = 4 * kThreads;  // 16-byte chunks sorted per round
   static constexpr uint32_t kSeqBits = kThreads <= 64 ? 7 : kThreads <= 128 ? 8 : kThreads <= 256 ? 9 : 10;
   uint32_t list[kRound];  // per-byte chunks: chunk << kSeqBits | sequence
-  uint32_t cseq[kRound];  // sequence holding each chunk's first byte
-  uint32_t nbyte, carry;
+  uint32_t cseq[kRound];  // marks: the last sequence starting in each chunk (0 = none)
+  uint32_t nbyte;
   uint32_t dst[kSeq];     // block-relative start of the sequence
   uint32_t lm[kSeq];      // L | M << 16
   uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
@@ -404,7 +424,7 @@ __device__ __forceinline__ void wg_scan4(uint32_t (&v)[4], uint32_t (&t)[4], uin
   for (uint32_t j = 0; j < 4; j++) v[j] = wave_incl_sum(v[j], lane);
   if (kW == 1) {
 #pragma unroll
-    for (uint32_t j = 0; j < 4; j++) t[j] = __shfl(v[j], 63, 64);
+    for (uint32_t j = 0; j < 4; j++) t[j] = lane63(v[j]);
     return;
   }
   __syncthreads();
@@ -426,35 +446,44 @@ __device__ __forceinline__ void wg_scan4(uint32_t (&v)[4], uint32_t (&t)[4], uin
   }
 }
 
-// In place: v[j] = max(carry, every value up to and including this one) over
-// kThreads threads x 4 consecutive values; returns the overall maximum.
+// Running maximum over kRound = 4 * kThreads values held strided: thread t
+// holds the values at positions t + j * kThreads (j < 4).  In place,
+// v[j] = max(carry, every value at or before its position); returns the
+// maximum of all of them and carry.  One barrier (none for one wavefront);
+// the caller must order any earlier reads of sh before it.
 template <uint32_t kThreads>
-__device__ __forceinline__ uint32_t wg_max_scan4(uint32_t (&v)[4], uint32_t carry, uint32_t* sh) {
+__device__ __forceinline__ uint32_t wg_max_scan_strided4(uint32_t (&v)[4], uint32_t carry, uint32_t* sh) {
   constexpr uint32_t kW = kThreads / 64;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  v[1] = max(v[1], v[0]);
-  v[2] = max(v[2], v[1]);
-  v[3] = max(v[3], v[2]);
-  uint32_t t = v[3];
 #pragma unroll
-  for (uint32_t d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(t, d, 64);
-    if (lane >= d) t = max(t, y);
-  }
-  uint32_t before = __shfl_up(t, 1, 64);
-  if (lane == 0) before = 0;
-  __syncthreads();
-  if (lane == 63) sh[w] = t;
-  __syncthreads();
-  uint32_t pw = carry, all = carry;
-  for (uint32_t j = 0; j < kW; j++) {
-    if (j < w) pw = max(pw, sh[j]);
-    all = max(all, sh[j]);
-  }
-  before = max(before, pw);
+  for (uint32_t j = 0; j < 4; j++) v[j] = wave_incl_max(v[j]);
+  uint32_t run = carry;
+  if (kW == 1) {
 #pragma unroll
-  for (uint32_t j = 0; j < 4; j++) v[j] = max(v[j], before);
-  return all;
+    for (uint32_t j = 0; j < 4; j++) {
+      const uint32_t tot = lane63(v[j]);
+      v[j] = max(v[j], run);
+      run = max(run, tot);
+    }
+    return run;
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) sh[4 * w + j] = v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) {
+    uint32_t before = run, tot = run;
+    for (uint32_t q = 0; q < kW; q++) {
+      const uint32_t x = sh[4 * q + j];
+      if (q < w) before = max(before, x);
+      tot = max(tot, x);
+    }
+    v[j] = max(v[j], before);
+    run = tot;
+  }
+  return run;
 }
 
 __device__ __forceinline__ uint32_t find_seq(const uint32_t* sdst, uint32_t cnt, uint32_t p) {
@@ -676,6 +705,12 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const bool cached = dep_cnt <= kDepCache;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
+  // the chunk marks start cleared (each thread clears the entries it later
+  // reads, right after reading them), ordered before the first marks by the
+  // barriers of the token phase
+#pragma unroll
+  for (uint32_t j = 0; j < 4; j++) sm.cseq[tid + j * kThreads] = 0;
+  if (tid == 0) sm.nbyte = 0;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kSeq) {
     // ---- two sequences per thread: tokens, scans, first classification
     uint32_t L[2] = {0, 0}, M[2] = {0, 0};
@@ -875,17 +910,14 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     // the threads, so a wavefront does not pay for both kinds of work
     const uint32_t base = d0 & ~15u;
     const uint32_t nch = d1 > base ? (d1 - base + 15) / 16 : 0;
+    uint32_t carry = 0;  // the last sequence marked in earlier rounds
     for (uint32_t k0 = 0; k0 < nch; k0 += kRound) {
       const uint32_t kn = nch - k0 < kRound ? nch - k0 : kRound;
       // the sequence holding each chunk's first byte: every sequence marks
       // the first chunk whose first byte is at or after its start, then a
-      // running maximum over the chunks fills the rest
-      for (uint32_t j = tid; j < kRound; j += kThreads) sm.cseq[j] = 0;
-      if (tid == 0) {
-        sm.nbyte = 0;
-        if (k0 == 0) sm.carry = 0;
-      }
-      __syncthreads();
+      // running maximum over the chunks fills the rest.  Thread t reads
+      // (and clears) the marks of chunks t + j * kThreads, the chunks it
+      // classifies, so the scan leaves each thread exactly its own values.
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
         const uint32_t slot = tid + h * kThreads;
@@ -896,18 +928,16 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         }
       }
       __syncthreads();
-      {
-        uint32_t v[4];
+      uint32_t sqv[4];
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) v[j] = sm.cseq[4 * tid + j];
-        const uint32_t carry = sm.carry;
-        const uint32_t all = wg_max_scan4<kThreads>(v, carry, sm.scan);
-#pragma unroll
-        for (uint32_t j = 0; j < 4; j++) sm.cseq[4 * tid + j] = v[j];
-        __syncthreads();
-        if (tid == 0) sm.carry = all;
+      for (uint32_t j = 0; j < 4; j++) {
+        sqv[j] = sm.cseq[tid + j * kThreads];
+        sm.cseq[tid + j * kThreads] = 0;
       }
-      __syncthreads();
+      // every thread read the previous round's count before the barrier
+      // above; this round's additions come after the scan's barrier
+      if (tid == 0) sm.nbyte = 0;
+      carry = wg_max_scan_strided4<kThreads>(sqv, carry, sm.scan);
       // Phase A (LDS only): classify this thread's four chunks (a copy chunk
       // records its source; the others are appended to a list, one LDS
       // atomic per wavefront) and, when the tile is one round, follow this
@@ -927,7 +957,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         if (here) {
           const uint32_t p0 = cb < d0 ? d0 : cb;
           const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-          sq = sm.cseq[k - k0];
+          sq = sqv[j];
           const uint32_t fl = sm.dfl[sq] >> 24;
           if (aligned && p0 == cb && pe1 == cb + 16 && !(fl & kPoison)) {
             const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
@@ -957,7 +987,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         const uint32_t leader_b = mb ? (uint32_t)__builtin_ctzll(mb) : 64u;
         uint32_t bb = 0;
         if (lane == leader_b) bb = atomicAdd(&sm.nbyte, (uint32_t)__popcll(mb));
-        bb = __shfl(bb, leader_b & 63, 64);
+        bb = (uint32_t)__builtin_amdgcn_readlane((int)bb, (int)(leader_b & 63));
         const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
         if (byte) sm.list[bb + below_b] = (k << kSB) | sq;
       }
@@ -1091,16 +1121,20 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
             if (cb + j >= p0 && cb + j < pe1) c.out[cb + j] = (uint8_t)(acc[j >> 2] >> (8 * (j & 3)));
         }
       }
-      __syncthreads();
       // the slow bytes loaded above, after every chunk store of the round
-      if (slow_p != 0xFFFFFFFFu) c.out[slow_p] = (uint8_t)slow_v;
-      __syncthreads();
+      // (only a tile of one round resolves them here).  The list and the
+      // marks are next written after the next round's first barrier.
+      if (fold) {
+        __syncthreads();
+        if (slow_p != 0xFFFFFFFFu) c.out[slow_p] = (uint8_t)slow_v;
+      }
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
     // sequences, tiles or non-adjacent blocks), one byte per thread, each
     // followed back to its origin
     const uint32_t slow_from = nch <= kRound ? kThreads : 0u;  // the first ones went with the round
     if (n_slow > slow_from) {
+      __syncthreads();  // after every chunk store (placeholders included)
       for (uint32_t u = slow_from + tid; u < n_slow; u += kThreads) {
         const uint32_t p = slow_pos<kThreads>(sm, c, u);
         const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
