@@ -85,7 +85,7 @@ __device__ __forceinline__ uint64_t blk_of(const DecodeArgs& a, uint64_t x) {
 //
 // LDS holds each stream's 12-bit table as a 4096-byte slot -> symbol map plus
 // one packed word per symbol (f << 16 | cum), and a ring of two chunks of
-// renormalisation words (16 G bytes each), refilled from a register
+// renormalisation words (8 G bytes each), refilled from a register
 // prefetch so the decode loop never waits on HBM latency.  The table build's
 // scratch lives in the ring before the ring is filled.  Lane j of a group
 // owns state j; each step decodes symbols t*W .. t*W+W-1, and the lanes that
@@ -97,10 +97,10 @@ template <uint32_t G>
 struct RansGroup {
   uint8_t sym[4096];  // slot -> symbol
   uint32_t fc[256];   // symbol -> f << 16 | cum
-  uint8_t stage[16 * G + 16];  // decoded symbols not yet written out; the last 16 bytes
+  uint8_t stage[8 * G + 16];  // decoded symbols not yet written out; the last 16 bytes
                                // take the writes of idle lanes
   union {
-    uint4 ring[2 * G];  // 2 chunks x G lanes x 16 B
+    uint2 ring[2 * G];  // 2 chunks x G lanes x 8 B
     struct {
       unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
       uint8_t by_rank[256];           // k-th present symbol
@@ -136,7 +136,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
                                                   uint8_t* dst, RansGroup<G>& sm, uint32_t g, uint32_t h,
                                                   bool on) {
   constexpr uint32_t kSpl = 256 / G;      // symbols per lane in the table build
-  constexpr uint32_t kChunkW = 8 * G;     // words per ring chunk
+  constexpr uint32_t kChunkW = 4 * G;     // words per ring chunk (at least the kU * W of one check)
   // ---- frequency table: 32-byte presence bitmap, then f-1 per present symbol
   bool bad = on && clen < 32;
   on = on && !bad;
@@ -211,14 +211,14 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   if (on && g < W && x < kL) bad = true;
   bad = grp_any<G>(bad, h);
   on = on && !bad;
-  const uintptr_t a0 = (uintptr_t)wsrc & ~(uintptr_t)15;
+  const uintptr_t a0 = (uintptr_t)wsrc & ~(uintptr_t)7;
   const uint32_t hw = (uint32_t)((uintptr_t)wsrc - a0) >> 1;  // word 0 in chunk 0
-  const uint32_t nchunks = on ? (2 * (hw + nwords) + 16 * G - 1) / (16 * G) : 0;
-  const uint4* gch = reinterpret_cast<const uint4*>(a0);
+  const uint32_t nchunks = on ? (2 * (hw + nwords) + 8 * G - 1) / (8 * G) : 0;
+  const uint2* gch = reinterpret_cast<const uint2*>(a0);
   uint32_t committed = 0;
   for (; committed < 2 && committed < nchunks; committed++)
     sm.u.ring[(committed & 1) * G + g] = gch[committed * G + g];
-  uint4 pf = make_uint4(0, 0, 0, 0);
+  uint2 pf = make_uint2(0, 0);
   if (committed < nchunks) pf = gch[committed * G + g];
   wave_sync();
   const uint16_t* ring16 = reinterpret_cast<const uint16_t*>(sm.u.ring);
@@ -230,7 +230,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   // ring refill (or when the stage is full): the refill waits for its
   // prefetch, and a wait issued there then finds the earlier stores done.
   constexpr uint32_t kU = 4;  // steps per ring/stage check in the main loop
-  const uint32_t stage_steps = (16 * G / W) & ~(kU - 1);
+  const uint32_t stage_steps = (8 * G / W) & ~(kU - 1);
   uint32_t t0 = 0;  // first step held in the stage
   uint32_t so = g;  // this lane's stage offset for the next step
   auto flush = [&](uint32_t t) {
@@ -283,7 +283,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     const uint32_t xa = (kAll || act) ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
     rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
-    sm.stage[(kAll || act) ? so : 16 * G] = (uint8_t)s;  // idle lanes: a spare byte
+    sm.stage[(kAll || act) ? so : 8 * G] = (uint8_t)s;  // idle lanes: a spare byte
     so += W;
   };
   // main loop: steps where every state of both groups has a symbol, kU at a
@@ -321,7 +321,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
 // left in place (the expansion reads them there).  Also records where each
 // block's bytes will live.
 template <uint32_t G>
-__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
                                              int lv_hi) {
   __shared__ RansGroup<G> sm[64 / G];
   const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
