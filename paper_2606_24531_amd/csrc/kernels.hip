@@ -91,14 +91,13 @@ __device__ __forceinline__ uint64_t blk_of(const DecodeArgs& a, uint64_t x) {
 // owns state j; each step decodes symbols t*W .. t*W+W-1, and the lanes that
 // renormalise take consecutive words in lane order: word = running position
 // + (count of renormalising lanes below in the group).  The loop body is
-// branch-free apart from the ring refill.
+// branch-free apart from the ring refill, and each step's symbols are stored
+// straight to the output (one coalesced store per step, no LDS staging).
 // ---------------------------------------------------------------------------
 template <uint32_t G>
 struct RansGroup {
   uint8_t sym[4096];  // slot -> symbol
   uint32_t fc[256];   // symbol -> f << 16 | cum
-  uint8_t stage[8 * G + 16];  // decoded symbols not yet written out; the last 16 bytes
-                               // take the writes of idle lanes
   union {
     uint2 ring[2 * G];  // 2 chunks x G lanes x 8 B
     struct {
@@ -226,30 +225,12 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   const bool lane_on = on && g < W;
   const uint32_t my_steps = on ? (n + W - 1) / W : 0;
   const uint32_t nsteps = uniform(G == 64 ? my_steps : max(my_steps, (uint32_t)__shfl_xor(my_steps, 32, 64)));
-  // Decoded symbols go to the LDS stage and are written out right after a
-  // ring refill (or when the stage is full): the refill waits for its
-  // prefetch, and a wait issued there then finds the earlier stores done.
-  constexpr uint32_t kU = 4;  // steps per ring/stage check in the main loop
-  const uint32_t stage_steps = (8 * G / W) & ~(kU - 1);
-  uint32_t t0 = 0;  // first step held in the stage
-  uint32_t so = g;  // this lane's stage offset for the next step
-  auto flush = [&](uint32_t t) {
-    const uint32_t f0 = min(t0 * W, n), f1 = min(t * W, n), cnt = f1 - f0;
-    uint8_t* o = dst + f0;
-    uint32_t k = 0;
-    if ((((uintptr_t)o) & 3) == 0) {
-      for (k = 4 * g; k + 4 <= cnt; k += 4 * G)
-        *reinterpret_cast<uint32_t*>(o + k) = *reinterpret_cast<const uint32_t*>(sm.stage + k);
-      k = (cnt & ~3u) + g;
-    } else {
-      k = g;
-    }
-    for (; k < cnt; k += G) o[k] = sm.stage[k];
-    t0 = t;
-    so = g;
-  };
-  // Makes room for `steps` more steps: ring words and stage space.
-  auto prepare = [&](uint32_t t, uint32_t steps) {
+  // Each step's decoded symbols go straight to their output bytes: lane j
+  // writes byte t*W + j, so a step is one coalesced W-byte store.
+  constexpr uint32_t kU = 4;  // steps per ring check in the main loop
+  uint8_t* op = dst + g;      // this lane's next output byte
+  // Makes room for `steps` more steps in the word ring.
+  auto prepare = [&](uint32_t steps) {
     const bool refill = rp + steps * W > committed * kChunkW && committed < nchunks;  // group-uniform
     if (__ballot(refill)) {
       if (refill) {
@@ -257,11 +238,6 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
         committed++;
         if (committed < nchunks) pf = gch[committed * G + g];
       }
-      wave_sync();
-    }
-    const bool out = on && (refill || t - t0 + steps > stage_steps) && t > t0;  // group-uniform
-    if (__ballot(out)) {
-      if (out) flush(t);
       wave_sync();
     }
   };
@@ -283,8 +259,8 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     const uint32_t xa = (kAll || act) ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
     rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
-    sm.stage[(kAll || act) ? so : 8 * G] = (uint8_t)s;  // idle lanes: a spare byte
-    so += W;
+    if (kAll || act) *op = (uint8_t)s;
+    op += kAll ? G : W;  // kAll: W == G
   };
   // main loop: steps where every state of both groups has a symbol, kU at a
   // time with one check; then the ragged tail one step at a time
@@ -294,23 +270,21 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   uint32_t t = 0;
   if (W == G) {  // every lane holds a state: no per-lane activity in the main loop
     for (; t < t_full; t += kU) {
-      prepare(t, kU);
+      prepare(kU);
 #pragma unroll
       for (uint32_t u = 0; u < kU; u++) step(std::true_type{}, true);
     }
   } else {
     for (; t < t_full; t += kU) {
-      prepare(t, kU);
+      prepare(kU);
 #pragma unroll
       for (uint32_t u = 0; u < kU; u++) step(std::false_type{}, lane_on);
     }
   }
   for (; t < nsteps; t++) {
-    prepare(t, 1);
+    prepare(1);
     step(std::false_type{}, lane_on && g + t * W < n);
   }
-  wave_sync();
-  if (on) flush(nsteps);
   if (on && (rp - hw != nwords || (g < W && x != kL))) bad = true;
   return grp_any<G>(bad, h);
 }
@@ -321,7 +295,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
 // left in place (the expansion reads them there).  Also records where each
 // block's bytes will live.
 template <uint32_t G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
+__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
                                              int lv_hi) {
   __shared__ RansGroup<G> sm[64 / G];
   const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
