@@ -17,11 +17,38 @@ namespace {
 
 constexpr uint32_t kWave = 64;
 
+// Device memory seen through the global address space.  Loads and stores
+// through these pointers are global instructions, which count only against
+// the vector-memory counter; through a generic pointer they are flat
+// instructions, which also count against the LDS counter, so that a wait for
+// an LDS result would also wait for every load and store still in flight.
+#define ACE_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ ACE_GLOBAL T* gp(T* p) {
+  return (ACE_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const ACE_GLOBAL T* gp(const T* p) {
+  return (const ACE_GLOBAL T*)p;
+}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint8_t ld8(const uint8_t* p) { return *gp(p); }
+__device__ __forceinline__ void st8(uint8_t* p, uint8_t v) { *gp(p) = v; }
+__device__ __forceinline__ void st16(uint8_t* p, uint4 v) {  // 16-aligned p
+  u32x4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *gp(reinterpret_cast<u32x4*>(p)) = w;
+}
+
 __device__ __forceinline__ uint32_t ld16(const uint8_t* p) {
-  return (uint32_t)p[0] | ((uint32_t)p[1] << 8);
+  return (uint32_t)ld8(p) | ((uint32_t)ld8(p + 1) << 8);
 }
 __device__ __forceinline__ uint32_t ld32(const uint8_t* p) {
-  return *reinterpret_cast<const uint32_t*>(p);  // callers pass 4-aligned addresses
+  return *gp(reinterpret_cast<const uint32_t*>(p));  // callers pass 4-aligned addresses
 }
 __device__ __forceinline__ uint64_t ld64(const uint8_t* p) {
   return (uint64_t)ld32(p) | ((uint64_t)ld32(p + 4) << 32);
@@ -99,7 +126,7 @@ struct RansGroup {
   uint8_t sym[4096];  // slot -> symbol
   uint32_t fc[256];   // symbol -> f << 16 | cum
   union {
-    uint2 ring[2 * G];  // 2 chunks x G lanes x 8 B
+    u32x2 ring[2 * G];  // 2 chunks x G lanes x 8 B
     struct {
       unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
       uint8_t by_rank[256];           // k-th present symbol
@@ -213,11 +240,13 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   const uintptr_t a0 = (uintptr_t)wsrc & ~(uintptr_t)7;
   const uint32_t hw = (uint32_t)((uintptr_t)wsrc - a0) >> 1;  // word 0 in chunk 0
   const uint32_t nchunks = on ? (2 * (hw + nwords) + 8 * G - 1) / (8 * G) : 0;
-  const uint2* gch = reinterpret_cast<const uint2*>(a0);
+  const ACE_GLOBAL u32x2* gch = gp(reinterpret_cast<const u32x2*>(a0));
   uint32_t committed = 0;
   for (; committed < 2 && committed < nchunks; committed++)
     sm.u.ring[(committed & 1) * G + g] = gch[committed * G + g];
-  uint2 pf = make_uint2(0, 0);
+  u32x2 pf;
+  pf.x = 0;
+  pf.y = 0;
   if (committed < nchunks) pf = gch[committed * G + g];
   wave_sync();
   const uint16_t* ring16 = reinterpret_cast<const uint16_t*>(sm.u.ring);
@@ -259,7 +288,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     const uint32_t xa = (kAll || act) ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
     rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
-    if (kAll || act) *op = (uint8_t)s;
+    if (kAll || act) st8(op, (uint8_t)s);
     op += kAll ? G : W;  // kAll: W == G
   };
   // main loop: steps where every state of both groups has a symbol, kU at a
@@ -356,7 +385,8 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
 //     doubled (a pointer to a pointer becomes one) until each reaches a
 //     resolved span, so a chain of n such matches takes log2(n) rounds.
 // Output is then produced in 16-byte chunks: a chunk of one literal run or
-// of one resolved, non-wrapping match is a copy of five aligned dwords; the
+// of one resolved, non-wrapping match is one 16-byte load (global loads take
+// any byte alignment on this target) and one store; the
 // others are assembled byte by byte, every byte's address first and then the
 // loads together.  Spans that straddle sequences or blocks take the slow
 // path: follow the source back until it reaches a literal, a resolved span,
@@ -495,7 +525,7 @@ template <uint32_t kThreads>
 __device__ __forceinline__ uint64_t dep_loc(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
                                             uint32_t dep_cnt, uint64_t blk) {
   const int di = dep_cnt <= kDepCache ? dep_index(sm.deps, dep_cnt, (uint32_t)blk) : -1;
-  return di >= 0 ? sm.dloc[di] : a.loc[blk];
+  return di >= 0 ? sm.dloc[di] : *gp(a.loc + blk);
 }
 
 // Slow path: the address of the byte at block-relative p, following sources
@@ -543,6 +573,14 @@ __device__ __forceinline__ uint32_t slow_pos(const ExpandSmem<kThreads>& sm, con
   }
   const uint32_t Mk = sm.lm[lo] >> 16, Lk = sm.lm[lo] & 0xFFFFu;
   return sm.dst[lo] + Lk + (u - (sm.ptr[lo] - Mk));
+}
+
+// 16 bytes from any byte address (one global load: this target's global
+// loads take any alignment).
+typedef u32x4 u32x4_a1 __attribute__((aligned(1)));
+__device__ __forceinline__ uint4 ld16u(const uint8_t* p) {
+  const u32x4 v = *reinterpret_cast<const ACE_GLOBAL u32x4_a1*>(gp(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 // Readable bytes around a resolved span's address: back (capped at 31) and
@@ -630,7 +668,7 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
     if (load[k]) {
       const uint32_t* wp = reinterpret_cast<const uint32_t*>(V[k] & ~3ull);
 #pragma unroll
-      for (uint32_t q = 0; q < 5; q++) wv[k][q] = wp[q];
+      for (uint32_t q = 0; q < 5; q++) wv[k][q] = ld32(reinterpret_cast<const uint8_t*>(wp + q));
     } else {
 #pragma unroll
       for (uint32_t q = 0; q < 5; q++) wv[k][q] = 0;
@@ -705,7 +743,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) {
         const uint32_t d = deps[j];
         sm.deps[j] = d;
-        sm.dloc[j] = !ext_ok ? 0 : a.loc_linear ? a.dst_base + (uint64_t)d * a.B : a.loc[d];
+        sm.dloc[j] = !ext_ok ? 0 : a.loc_linear ? a.dst_base + (uint64_t)d * a.B : *gp(a.loc + d);
       }
     }
     // positions in sequence order: slots 0..kThreads-1 first, then the rest
@@ -750,7 +788,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
                   break;
                 }
                 if (contiguous) {
-                  const uint64_t lb = cached ? sm.dloc[di] : a.loc[blk];
+                  const uint64_t lb = cached ? sm.dloc[di] : *gp(a.loc + blk);
                   if (blk == b0) loc0 = lb;
                   else contiguous = lb == loc0 + (blk - b0) * a.B;
                 }
@@ -878,8 +916,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     const uint64_t d1w = (uint64_t)carry_pos + tp;
     const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
     // ---- output in 16-byte chunks, four per thread per round: copy chunks
-    // (one literal run, or one resolved match with no period wrap, whose
-    // five aligned source dwords are readable) are copied where they are
+    // (one literal run, or one resolved match with no period wrap) are
+    // copied where they are
     // classified; per-byte chunks are gathered in a list and spread over
     // the threads, so a wavefront does not pay for both kinds of work
     const uint32_t base = d0 & ~15u;
@@ -943,11 +981,11 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               vec = true;  // all literals (stream data has readable slack)
               src = c.lit + sm.lit[sq] + r0;
             } else if (r0 >= Ls && !(fl & kUnres)) {
-              const uint32_t ii0 = r0 - Ls, wn = sm.win[sq];
-              const uint64_t sa = sm.src0[sq] + ii0;
-              const uint32_t shp = (uint32_t)(sa & 3);
-              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu) && ii0 + (wn & 31u) >= shp && ii0 + 20 <= (wn >> 5) + shp;
-              src = reinterpret_cast<const uint8_t*>(sa);
+              // no period wrap inside the chunk: its 16 source bytes lie in
+              // the resolved span, which is readable
+              const uint32_t ii0 = r0 - Ls;
+              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu);
+              src = reinterpret_cast<const uint8_t*>(sm.src0[sq] + ii0);
             }
             if (vec) {
               vsrc[j] = src;
@@ -976,14 +1014,12 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // Phase B: every load of this thread is issued before any is used: the
       // copy chunks' source dwords, its slow byte, and (through the segment
       // path) its first listed chunk.
-      uint32_t w[4][5];
+      // (a copy chunk's source is one 16-byte load at any byte alignment;
+      // the others read 16 bytes at c.lit, which is always readable)
+      uint4 w[4];
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
-        const uint32_t* wp = reinterpret_cast<const uint32_t*>(vsrc[j] - ((uintptr_t)vsrc[j] & 3));
-#pragma unroll
-        for (uint32_t q = 0; q < 5; q++) w[j][q] = cbv[j] != 0xFFFFFFFFu ? wp[q] : 0u;
-      }
-      const uint32_t slow_v = slow_a ? (uint32_t)*slow_a : 0u;
+      for (uint32_t j = 0; j < 4; j++) w[j] = ld16u(vsrc[j]);
+      const uint32_t slow_v = slow_a ? (uint32_t)ld8(slow_a) : 0u;
       bool seg_done = false;
       uint32_t seg_cb = 0, o4[4] = {0, 0, 0, 0};
       if (tid < nby) {
@@ -995,17 +1031,9 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           seg_done = seg_chunk<kThreads>(sm, c, seg_cb, e & kSM, d1, o4);
       }
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
-        if (cbv[j] != 0xFFFFFFFFu) {
-          const uint32_t sh = (uint32_t)((uintptr_t)vsrc[j] & 3);
-          *reinterpret_cast<uint4*>(c.out + cbv[j]) =
-              make_uint4(__builtin_amdgcn_alignbyte(w[j][1], w[j][0], sh),
-                         __builtin_amdgcn_alignbyte(w[j][2], w[j][1], sh),
-                         __builtin_amdgcn_alignbyte(w[j][3], w[j][2], sh),
-                         __builtin_amdgcn_alignbyte(w[j][4], w[j][3], sh));
-        }
-      }
-      if (seg_done) *reinterpret_cast<uint4*>(c.out + seg_cb) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+      for (uint32_t j = 0; j < 4; j++)
+        if (cbv[j] != 0xFFFFFFFFu) st16(c.out + cbv[j], w[j]);
+      if (seg_done) st16(c.out + seg_cb, make_uint4(o4[0], o4[1], o4[2], o4[3]));
       // per-byte path: listed chunks the segment path declined or that lie
       // beyond the first kThreads entries.  Every byte's source address
       // first, then the 16 loads back to back.  The current sequence's
@@ -1023,7 +1051,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         if (ei != tid && aligned && p0 == cb && pe1 == cb + 16) {
           uint32_t q4[4];
           if (seg_chunk<kThreads>(sm, c, cb, s, d1, q4)) {
-            *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(q4[0], q4[1], q4[2], q4[3]);
+            st16(c.out + cb, make_uint4(q4[0], q4[1], q4[2], q4[3]));
             continue;
           }
         }
@@ -1080,7 +1108,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           uint32_t lo4 = 0, hi4 = 0;
 #pragma unroll
           for (uint32_t j = 0; j < 8; j++) {
-            const uint32_t v = (zero >> j) & 1u ? 0u : (uint32_t)*ad[j];
+            const uint32_t v = (zero >> j) & 1u ? 0u : (uint32_t)ld8(ad[j]);
             if (j < 4) lo4 |= v << (8 * j);
             else hi4 |= v << (8 * (j - 4));
           }
@@ -1088,11 +1116,11 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           acc[2 * hf + 1] = hi4;
         }
         if (aligned && p0 == cb && pe1 == cb + 16) {
-          *reinterpret_cast<uint4*>(c.out + cb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+          st16(c.out + cb, make_uint4(acc[0], acc[1], acc[2], acc[3]));
         } else {
 #pragma unroll
           for (uint32_t j = 0; j < 16; j++)
-            if (cb + j >= p0 && cb + j < pe1) c.out[cb + j] = (uint8_t)(acc[j >> 2] >> (8 * (j & 3)));
+            if (cb + j >= p0 && cb + j < pe1) st8(c.out + cb + j, (uint8_t)(acc[j >> 2] >> (8 * (j & 3))));
         }
       }
       // the slow bytes loaded above, after every chunk store of the round
@@ -1100,7 +1128,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // marks are next written after the next round's first barrier.
       if (fold) {
         __syncthreads();
-        if (slow_p != 0xFFFFFFFFu) c.out[slow_p] = (uint8_t)slow_v;
+        if (slow_p != 0xFFFFFFFFu) st8(c.out + slow_p, (uint8_t)slow_v);
       }
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
@@ -1112,7 +1140,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       for (uint32_t u = slow_from + tid; u < n_slow; u += kThreads) {
         const uint32_t p = slow_pos<kThreads>(sm, c, u);
         const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
-        c.out[p] = q ? *q : (uint8_t)0;
+        st8(c.out + p, q ? ld8(q) : (uint8_t)0);
       }
       __syncthreads();
     }
