@@ -602,9 +602,9 @@ __device__ __forceinline__ uint32_t dword_mask(uint32_t j, uint32_t lo, uint32_t
 
 // Segment path for a 16-byte output chunk [cb, cb+16) inside the tile: the
 // chunk is cut at literal/match and sequence boundaries into at most four
-// segments over at most two sequences, each copied from one contiguous
-// source with five aligned dword loads (all issued before any is used) and
-// merged by byte mask.  Bytes of slow spans are left as placeholders (the
+// segments over at most two sequences.  Each segment's source, shifted so
+// that its byte j lines up with output byte j, is one 16-byte load (all
+// issued before any is used), merged by byte mask.  Bytes of slow spans are left as placeholders (the
 // slow pass writes them), bytes of poisoned sequences as zeros.  Returns
 // false (the caller takes the per-byte path) for a period wrap inside a
 // segment, a third sequence, or a source window that is not known readable.
@@ -640,7 +640,7 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
           V[2 * q] = (uint64_t)(uintptr_t)A - (x - cb);
           lo[2 * q] = x - cb;
           hi[2 * q] = h - cb;
-          load[2 * q] = true;  // literal streams are readable 31 bytes before and 20 after
+          load[2 * q] = true;  // literal streams are readable 31 bytes before and 16 after
           x = h;
         }
         if (x < end) {  // match part
@@ -651,8 +651,8 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
             const uint64_t A = sm.src0[sq] + ii0;
             const uint64_t v = A - (x - cb);
             const uint32_t wn = sm.win[sq], back = (wn & 31u) + ii0, fwd = (wn >> 5) - ii0;
-            const uint32_t need_back = (x - cb) + (uint32_t)(v & 3);
-            ok = ok && ii0 + (end - x) <= d && need_back <= back && 20 - need_back <= fwd;
+            const uint32_t need_back = x - cb;  // bytes read before the segment's source
+            ok = ok && ii0 + (end - x) <= d && need_back <= back && 16 - need_back <= fwd;
             V[2 * q + 1] = v;
             load[2 * q + 1] = true;
           }
@@ -662,28 +662,19 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
     }
   }
   if (!ok || x < cb + 16) return false;
-  uint32_t wv[kC][5];
+  uint4 wv[kC];
 #pragma unroll
-  for (uint32_t k = 0; k < kC; k++) {
-    if (load[k]) {
-      const uint32_t* wp = reinterpret_cast<const uint32_t*>(V[k] & ~3ull);
-#pragma unroll
-      for (uint32_t q = 0; q < 5; q++) wv[k][q] = ld32(reinterpret_cast<const uint8_t*>(wp + q));
-    } else {
-#pragma unroll
-      for (uint32_t q = 0; q < 5; q++) wv[k][q] = 0;
-    }
-  }
+  for (uint32_t k = 0; k < kC; k++)
+    wv[k] = load[k] ? ld16u(reinterpret_cast<const uint8_t*>(V[k])) : make_uint4(0, 0, 0, 0);
 #pragma unroll
   for (uint32_t j = 0; j < 4; j++) out[j] = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kC; k++) {
-    const uint32_t sh = (uint32_t)(V[k] & 3);
+    const uint32_t v4[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
 #pragma unroll
     for (uint32_t j = 0; j < 4; j++) {
       const uint32_t m = dword_mask(j, lo[k], hi[k]);
-      const uint32_t v = __builtin_amdgcn_alignbyte(wv[k][j + 1], wv[k][j], sh);
-      out[j] = (out[j] & ~m) | (v & m);
+      out[j] = (out[j] & ~m) | (v4[j] & m);
     }
   }
   return true;
