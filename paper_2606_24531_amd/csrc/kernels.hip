@@ -411,7 +411,6 @@ struct ExpandSmem {
   uint32_t dfl[kSeq];     // min(d, 2^24 - 1) | flags << 24
   uint32_t win[kSeq];     // readable bytes around src0: back (0..31) | forward << 5
   uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
-  uint64_t O[kSeq];
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
   uint32_t deps[kDepCache];
   uint64_t dloc[kDepCache];  // location of each cached dependency's first byte
@@ -514,8 +513,10 @@ __device__ __forceinline__ int dep_index(const uint32_t* deps, uint32_t cnt, uin
 struct BlockCtx {
   uint64_t bs;       // absolute start of the block
   uint32_t blen, n_lit, d0, cnt, dep_cnt;
+  uint32_t t0, ow;   // the tile's first sequence; offset width in bytes
   uint8_t* out;      // the block's first byte
-  const uint8_t* lit;  // the block's literal stream
+  const uint8_t* lit;   // the block's literal stream
+  const uint8_t* offs;  // the block's offset stream (O_k of sequence k at ow * k)
   bool ext_ok;
 };
 
@@ -549,7 +550,8 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
       if (fl & kExt) n_ext++;
       return reinterpret_cast<const uint8_t*>(sm.src0[s] + im);
     }
-    const uint64_t src = sm.O[s] + im;
+    const uint32_t k = c.t0 + s;  // O is read back from the token stream (rare path)
+    const uint64_t src = (c.ow == 4 ? (uint64_t)ld32(c.offs + 4ull * k) : ld64(c.offs + 8ull * k)) + im;
     if (src < c.bs) {
       if (!c.ext_ok) return nullptr;
       n_ext++;
@@ -704,6 +706,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   c.lit = pe.raw[0] != kCoded ? a.arch + pe.raw[0] : a.lit + (uint64_t)i * a.B;
   const uint8_t* lens = pe.raw[1] != kCoded ? a.arch + pe.raw[1] : a.lens + 4ull * pe.seq_base;
   const uint8_t* offs = pe.raw[2] != kCoded ? a.arch + pe.raw[2] : a.offs + (uint64_t)a.ow * pe.seq_base;
+  c.offs = offs;
+  c.ow = a.ow;
   const bool aligned = (((uintptr_t)c.out) & 15) == 0;
   const bool cached = dep_cnt <= kDepCache;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
@@ -743,6 +747,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     const uint32_t tp = st[0] + st[2], tl = st[1] + st[3];
     const uint32_t d0 = carry_pos;
     c.d0 = d0;
+    c.t0 = t0;
     c.cnt = (n_seq - t0) < kSeq ? (n_seq - t0) : kSeq;
     const uint32_t pos_h[2] = {carry_pos + sv[0] - (L[0] + M[0]), carry_pos + st[0] + sv[2] - (L[1] + M[1])};
     const uint32_t lit_h[2] = {carry_lit + sv[1] - L[0], carry_lit + st[1] + sv[3] - L[1]};
@@ -816,7 +821,6 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       sm.lit[slot] = litk;
       sm.dfl[slot] = dist | (fl << 24);
       sm.win[slot] = win;
-      sm.O[slot] = O[h];
       sm.src0[slot] = src0;
     }
     __syncthreads();
