@@ -277,7 +277,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     const uint32_t slot = x & (kM - 1);
     const uint32_t s = sm.sym[slot];
     const uint32_t e = sm.fc[s];
-    const uint32_t xn = __umul24(e >> 16, x >> kProbBits) + slot - (e & 0xFFFu);
+    const uint32_t xn = __umul24(e >> 16, x >> kProbBits) + (slot - (e & 0xFFFFu));  // low half: cum
     const bool lt = xn < kL;
     const bool need = kAll ? lt : (act && lt);
     const uint64_t m = __builtin_amdgcn_ballot_w64(need);
@@ -947,9 +947,10 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       carry = wg_max_scan_strided4<kThreads>(sqv, carry, sm.scan);
       // Phase A (LDS only): classify this thread's four chunks (a copy chunk
       // records its source; the others are appended to a list, one LDS
-      // atomic per wavefront) and, when the tile is one round, follow this
-      // thread's slow byte back to its source.
-      const bool fold = nch <= kRound;  // slow bytes written in this round
+      // atomic per wavefront) and, in the tile's last round, follow this
+      // thread's slow byte back to its source (a slow byte's source is never
+      // in this tile's output, so it can be read before the tile is done).
+      const bool fold = k0 + kRound >= nch;  // last round: slow bytes written here
       const uint8_t* vsrc[4];
       uint32_t cbv[4];
 #pragma unroll
@@ -1118,9 +1119,9 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
             if (cb + j >= p0 && cb + j < pe1) st8(c.out + cb + j, (uint8_t)(acc[j >> 2] >> (8 * (j & 3))));
         }
       }
-      // the slow bytes loaded above, after every chunk store of the round
-      // (only a tile of one round resolves them here).  The list and the
-      // marks are next written after the next round's first barrier.
+      // the slow bytes loaded above, after every chunk store of the tile
+      // (only its last round resolves them).  The list and the marks are
+      // next written after the next round's first barrier.
       if (fold) {
         __syncthreads();
         if (slow_p != 0xFFFFFFFFu) st8(c.out + slow_p, (uint8_t)slow_v);
@@ -1129,7 +1130,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
     // sequences, tiles or non-adjacent blocks), one byte per thread, each
     // followed back to its origin
-    const uint32_t slow_from = nch <= kRound ? kThreads : 0u;  // the first ones went with the round
+    const uint32_t slow_from = nch > 0 ? kThreads : 0u;  // the first ones went with the last round
     if (n_slow > slow_from) {
       __syncthreads();  // after every chunk store (placeholders included)
       for (uint32_t u = slow_from + tid; u < n_slow; u += kThreads) {
