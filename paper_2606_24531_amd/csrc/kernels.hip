@@ -593,29 +593,47 @@ __device__ __forceinline__ void st16u(uint8_t* p, uint4 v) {  // any byte alignm
   *reinterpret_cast<ACE_GLOBAL u32x4_a1*>(gp(p)) = w;
 }
 
-// Copies len bytes of the decoded data from absolute position lo to dst: 16
-// bytes per thread per step, one 16-byte load and store when the 16 source
-// bytes lie in one block, byte by byte otherwise.  loc[c] is block c's
+// Copies len bytes of the decoded data from absolute position lo to dst.
+// Each thread takes four 16-byte chunks per step (a blockDim.x * 16 stride
+// apart, so every load and store instruction is coalesced), issues the loads
+// of those whose 16 source bytes lie in one block, then the stores; chunks
+// that cross a block edge or the end go byte by byte.  loc[c] is block c's
 // location.
 __device__ __forceinline__ void copy_range(const DecodeArgs& a, const uint64_t* loc, uint64_t lo,
                                            uint64_t len, uint8_t* dst) {
-  for (uint64_t j0 = threadIdx.x * 16ull; j0 < len; j0 += (uint64_t)blockDim.x * 16) {
-    uint64_t pos = lo + j0;
-    uint64_t c = blk_of(a, pos);
-    uint64_t cend = (c + 1) * a.B;
-    const uint8_t* base = reinterpret_cast<const uint8_t*>(*gp(loc + c)) - c * a.B;
-    if (j0 + 16 <= len && pos + 16 <= cend) {
-      st16u(dst + j0, ld16u(base + pos));
-      continue;
+  constexpr uint32_t kU = 4;
+  const uint64_t stride = (uint64_t)blockDim.x * 16;
+  for (uint64_t j0 = threadIdx.x * 16ull; j0 < len; j0 += kU * stride) {
+    const uint8_t* src[kU];
+    bool fast[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; u++) {
+      const uint64_t j = j0 + u * stride, pos = lo + j;
+      const uint64_t c = blk_of(a, pos);
+      fast[u] = j + 16 <= len && pos + 16 <= (c + 1) * a.B;
+      src[u] = fast[u] ? reinterpret_cast<const uint8_t*>(*gp(loc + c)) + (pos - c * a.B) : nullptr;
     }
-    const uint64_t jn = j0 + 16 < len ? j0 + 16 : len;
-    for (uint64_t j = j0; j < jn; j++, pos++) {
-      if (pos >= cend) {
-        c++;
-        cend += a.B;
-        base = reinterpret_cast<const uint8_t*>(*gp(loc + c)) - c * a.B;
+    uint4 v[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; u++) v[u] = fast[u] ? ld16u(src[u]) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (uint32_t u = 0; u < kU; u++) {
+      const uint64_t j = j0 + u * stride;
+      if (fast[u]) {
+        st16u(dst + j, v[u]);
+      } else if (j < len) {
+        uint64_t pos = lo + j, c = blk_of(a, pos), cend = (c + 1) * a.B;
+        const uint8_t* base = reinterpret_cast<const uint8_t*>(*gp(loc + c)) - c * a.B;
+        const uint64_t jn = j + 16 < len ? j + 16 : len;
+        for (uint64_t q = j; q < jn; q++, pos++) {
+          if (pos >= cend) {
+            c++;
+            cend += a.B;
+            base = reinterpret_cast<const uint8_t*>(*gp(loc + c)) - c * a.B;
+          }
+          st8(dst + q, ld8(base + pos));
+        }
       }
-      st8(dst + j, ld8(base + pos));
     }
   }
 }
