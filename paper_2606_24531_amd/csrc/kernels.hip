@@ -1004,13 +1004,17 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // thread's slow byte back to its source (a slow byte's source is never
       // in this tile's output, so it can be read before the tile is done).
       const bool fold = k0 + kRound >= nch;  // last round: slow bytes written here
-      const uint8_t* vsrc[4];
+      // a copy chunk's 16 source bytes are loaded as soon as it is classified
+      // (one load at any byte alignment; other chunks read 16 bytes at c.lit,
+      // which is always readable), so the loads are in flight during the
+      // rest of the classification, the list barrier and the segment path
+      uint4 w[4];
       uint32_t cbv[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         const uint32_t k = k0 + tid + j * kThreads;
         cbv[j] = 0xFFFFFFFFu;
-        vsrc[j] = c.lit;
+        const uint8_t* vsrc = c.lit;
         const bool here = k < k0 + kn;
         const uint32_t cb = base + 16 * k;
         bool vec = false;
@@ -1037,11 +1041,12 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               src = reinterpret_cast<const uint8_t*>(sm.src0[sq] + ii0);
             }
             if (vec) {
-              vsrc[j] = src;
+              vsrc = src;
               cbv[j] = cb;
             }
           }
         }
+        w[j] = ld16u(vsrc);
         const bool byte = here && !vec;
         const uint64_t mb = __builtin_amdgcn_ballot_w64(byte);
         const uint32_t lane = tid & 63;
@@ -1058,17 +1063,11 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         slow_p = slow_pos<kThreads>(sm, c, tid);
         slow_a = resolve_addr<kThreads>(a, sm, c, slow_p, n_ext);
       }
+      const uint32_t slow_v = slow_a ? (uint32_t)ld8(slow_a) : 0u;
       __syncthreads();
       const uint32_t nby = sm.nbyte;
-      // Phase B: every load of this thread is issued before any is used: the
-      // copy chunks' source dwords, its slow byte, and (through the segment
-      // path) its first listed chunk.
-      // (a copy chunk's source is one 16-byte load at any byte alignment;
-      // the others read 16 bytes at c.lit, which is always readable)
-      uint4 w[4];
-#pragma unroll
-      for (uint32_t j = 0; j < 4; j++) w[j] = ld16u(vsrc[j]);
-      const uint32_t slow_v = slow_a ? (uint32_t)ld8(slow_a) : 0u;
+      // Phase B: the segment path's loads for this thread's first listed
+      // chunk, then the stores.
       bool seg_done = false;
       uint32_t seg_cb = 0, o4[4] = {0, 0, 0, 0};
       if (tid < nby) {
