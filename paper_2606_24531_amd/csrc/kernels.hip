@@ -499,15 +499,16 @@ __device__ __forceinline__ uint32_t find_seq(const uint32_t* sdst, uint32_t cnt,
 }
 
 // Index of c in the ascending list, or -1.
-__device__ __forceinline__ int dep_index(const uint32_t* deps, uint32_t cnt, uint32_t c) {
-  uint32_t lo = 0, hi = cnt;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    uint32_t v = deps[mid];
-    if (v == c) return (int)mid;
-    if (v < c) lo = mid + 1; else hi = mid;
-  }
-  return -1;
+// Branch-free: pos becomes the count of entries below c by binary lifting
+// (steps 2^k .. 1, the largest 2^k <= cnt), so the step count depends only
+// on cnt, which is uniform over the workgroup.
+template <typename P>
+__device__ __forceinline__ int dep_index(P deps, uint32_t cnt, uint32_t c) {
+  if (cnt == 0) return -1;
+  uint32_t pos = 0;
+  for (uint32_t step = 1u << (31 - __clz(cnt)); step; step >>= 1)
+    if (pos + step <= cnt && deps[pos + step - 1] < c) pos += step;
+  return pos < cnt && deps[pos] == c ? (int)pos : -1;
 }
 
 struct BlockCtx {
@@ -831,7 +832,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
               const uint64_t b0 = blk_of(a, O[h]);
               for (uint64_t blk = b0; blk * a.B < end; blk++) {
                 const int di = cached ? dep_index(sm.deps, dep_cnt, (uint32_t)blk)
-                                      : dep_index(deps, dep_cnt, (uint32_t)blk);
+                                      : dep_index(gp(deps), dep_cnt, (uint32_t)blk);
                 if (di < 0) {
                   fl = kPoison;
                   break;
