@@ -94,18 +94,19 @@ def main():
     ap.add_argument("--serve-count", type=int, default=3000)
     ap.add_argument("--suite", default="",
                     help="instead of the headline decode, run the other workloads and print one "
-                         "JSON line each: cfg1 (1 MiB genome, decode + every block sought with the "
-                         "three-phase check), cfg3 (1 GiB mixed, 16 and 64 KiB blocks, DAG facts), "
-                         "cfg3u (the same archive uncapped: depth and ratio only), cfg4 (100k "
-                         "seeks on the cfg3 16 KiB archive: one graph replay vs one launch per seek)")
+                         "JSON line each: genome1m (1 MiB genome, decode + every block sought with "
+                         "the three-phase check), mixed1g (1 GiB mixed, 16 and 64 KiB blocks, DAG "
+                         "facts), mixed1g-uncapped (the same archive uncapped: depth and ratio only), "
+                         "seeks100k (100k seeks on the 1 GiB mixed 16 KiB archive: one graph replay "
+                         "vs one launch per seek)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run one device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's decode path runs on a single "
-              "MI355X (see DESIGN.md for how it would shard); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the decode path runs on a single MI355X; "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -419,7 +420,7 @@ def suite_main(args):
         d.update(n_gpus=1, data="synthetic", dtype="u8")
         print(json.dumps(d), flush=True)
 
-    if "cfg1" in which:
+    if "genome1m" in which:
         x = gen.genome(1 << 20, 1)
         a = encode(x, block_size=16384, interleave=32, min_match=20, hash_len=20, max_chain=32)
         arc = Archive(a, device=dev)
@@ -444,7 +445,7 @@ def suite_main(args):
             arc.check()
             good = good and phase1 and torch.equal(buf[lo:hi], xd[lo:hi]) and \
                 torch.equal(buf[:lo], before[:lo]) and torch.equal(buf[hi:], before[hi:])
-        _log("cfg1: decode %.4f ms, %d block seeks, three-phase %s" % (ms, arc.n_blocks, good))
+        _log("genome1m: decode %.4f ms, %d block seeks, three-phase %s" % (ms, arc.n_blocks, good))
         emit({"metric": "2-layer decode GB/s (full archive); single-block seek latency",
               "config": {"workload": "genome 1 MiB, 16 KiB blocks, 32-way rANS, uncapped",
                          "ratio": round(len(x) / len(a), 4), "depth": arc.depth},
@@ -453,12 +454,12 @@ def suite_main(args):
               "seek_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
               "three_phase_all_blocks": good})
     arc16 = x3 = None
-    if which & {"cfg3", "cfg4", "cfg3u"}:
+    if which & {"mixed1g", "seeks100k", "mixed1g-uncapped"}:
         t0 = time.time()
         x3 = gen.mixed(1 << 30, 3)
-        _log("cfg3: generated 1 GiB mixed in %.1fs" % (time.time() - t0))
+        _log("mixed1g: generated 1 GiB mixed in %.1fs" % (time.time() - t0))
         x3d = torch.frombuffer(bytearray(x3), dtype=torch.uint8).to(dev)
-        for B in ((16384, 65536) if "cfg3" in which else (16384,)):
+        for B in ((16384, 65536) if "mixed1g" in which else (16384,)):
             tuned = tune(x3[:32 << 20], "mixed", block_size=B, min_match=16, max_level=16)
             t0 = time.time()
             a = encode(x3, block_size=B, interleave=tuned["interleave"], min_match=16, hash_len=16,
@@ -466,10 +467,10 @@ def suite_main(args):
             enc_s = time.time() - t0
             arc = Archive(a, device=dev)
             shape = dict(mode=1, waves_per_block=tuned["waves_per_block"], blocks_per_wg=tuned["blocks_per_wg"])
-            if "cfg3" in which:
+            if "mixed1g" in which:
                 ms, ok = _time_decode(arc, x3d, shape, 10)
                 facts = _dag_facts(a)
-                _log("cfg3 B=%d: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
+                _log("mixed1g B=%d: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
                     B, len(x3) / len(a), arc.depth, ms, len(x3) / ms / 1e6, ok))
                 emit({"metric": "2-layer decode GB/s (full archive)",
                       "config": dict({"workload": "mixed 1 GiB, %d KiB blocks, %d-way rANS, level cap 16" % (
@@ -481,7 +482,7 @@ def suite_main(args):
                 arc16 = (arc, shape)
             else:
                 arc.close()
-        if "cfg3u" in which:
+        if "mixed1g-uncapped" in which:
             t0 = time.time()
             au = encode(x3, block_size=16384, interleave=64, min_match=16, hash_len=16, max_chain=32,
                         max_level=0)
@@ -491,7 +492,7 @@ def suite_main(args):
                                   "ratio": round(len(x3) / len(au), 4), "encode_s": round(time.time() - t0, 1)},
                                  **facts)})
             del au
-    if "cfg4" in which:
+    if "seeks100k" in which:
         arc, shape = arc16
         n = len(x3)
         rng = np.random.default_rng(4)
@@ -519,7 +520,7 @@ def suite_main(args):
             tb = float(np.median(times))
             res[sub] = {"latency_ms": round(1e3 * tb, 3), "req_per_s": round(sub / tb, 1),
                         "out_GB_per_s": round(float(ln[:sub].sum()) / tb / 1e9, 2)}
-            _log("cfg4 batch %d: %.3f ms, %.0f req/s" % (sub, 1e3 * tb, sub / tb))
+            _log("seeks100k batch %d: %.3f ms, %.0f req/s" % (sub, 1e3 * tb, sub / tb))
             bt.close()
         # every output of the full batch checked against the original bytes on
         # a sample of requests
