@@ -159,9 +159,9 @@ int ace_check(void* d_ws, void* stream);
  * A batch context owns a HIP graph captured once on `stream`.  Each run
  * uploads the request descriptors (one small host-to-device copy) and
  * replays the graph: device-side planning (targets of every request, their
- * dependency closure, a level-ordered plan), one persistent decode of the
- * union into workspace slots, and a gather of every request to its output
- * offset.  Capacity is fixed at creation; counts are read on the device, so
+ * dependency closure, a level-ordered plan), the decode of the union into
+ * workspace slots (one entropy launch, one expansion launch per level), and
+ * a gather of every request to its output offset.  Capacity is fixed at creation; counts are read on the device, so
  * any batch up to the capacity replays the same graph.  The workspace must
  * stay dedicated to the context.  Runs are asynchronous on the stream; a run
  * waits for the previous run of the same context to have started reading its
@@ -173,6 +173,18 @@ int ace_batch_create(const ace_archive* a, uint32_t max_requests, void* d_ws, ui
 /* Request i writes [lo_i, hi_i) at d_out + h_out_off[i]. */
 int ace_batch_run(ace_batch* b, const ace_range* h_ranges, uint32_t n, uint8_t* d_out,
                   const uint64_t* h_out_off);
+/* Decoded-block cache for serving.  The archive stays compressed-resident
+ * (Section 9), but every seek's closure reaches down to the lowest
+ * dependency levels, and a range decode is latency-bound (Section 7).  This
+ * call decodes every block of levels [0, levels) once, into the first slots
+ * of the batch's workspace, and keeps them: later runs neither plan nor
+ * decode those blocks (their closures stop there) and read them in place.
+ * Costs no extra memory (the workspace already has a slot per block).
+ * Synchronous on the batch's stream (it waits for a pending run first).
+ * Once per context: a second call is ACE_E_ARG; levels above the archive's
+ * depth are ACE_E_ARG; 0 keeps nothing.  ACE_E_CORRUPT if the decode of the
+ * kept levels failed (their blocks are then not kept). */
+int ace_batch_pin(ace_batch* b, uint32_t levels);
 void ace_batch_destroy(ace_batch* b);
 
 /* Waits for the stream, then reads and clears the workspace's counter of

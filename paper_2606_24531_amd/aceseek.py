@@ -20,6 +20,7 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
            "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters",
            "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
+           "ace_batch_pin",
            "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan"]
 
 
@@ -76,6 +77,7 @@ def lib():
         L.ace_batch_workspace_bytes.argtypes = [vp, u32, u64p]
         L.ace_batch_create.argtypes = [vp, u32, vp, u64, C.POINTER(Tuning), vp, C.POINTER(vp)]
         L.ace_batch_run.argtypes = [vp, vp, u32, vp, vp]
+        L.ace_batch_pin.argtypes = [vp, u32]
         L.ace_batch_destroy.argtypes = [vp]
         L.ace_batch_destroy.restype = None
         L.ace_set_timing.argtypes = [C.c_int]
@@ -362,6 +364,13 @@ class Batch:
                                    C.c_void_p(out.data_ptr()), offs.ctypes.data_as(C.c_void_p)))
         cur.wait_stream(self.stream)  # later work on the caller's stream sees the bytes
         return out
+
+    def pin(self, levels: int):
+        """Decodes dependency levels [0, levels) once and keeps them for every
+        later run (see ace_batch_pin)."""
+        torch = self.arc._torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.arc.device))
+        _check(lib().ace_batch_pin(self._h, int(levels)))
 
     def check(self):
         _check(lib().ace_check(C.c_void_p(self.ws.data_ptr()), _stream_ptr(self.stream)))

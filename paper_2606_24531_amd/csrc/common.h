@@ -81,6 +81,8 @@ struct BatchArgs {
   uint32_t* n_plan_dev;
   uint32_t* lvl_dev;       // depth + 1 plan boundaries per level
   uint64_t* loc;
+  const uint8_t* pin;        // per block: 1 = decoded once and kept (its loc stays valid)
+  const uint32_t* pin_base;  // slots taken by kept blocks; planned blocks go after them
 };
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.

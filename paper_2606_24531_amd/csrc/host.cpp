@@ -691,11 +691,16 @@ struct ace_batch {
   bool pending = false;
   hipStream_t s2 = nullptr;     // the entropy branch of the captured graph
   std::vector<hipEvent_t> ev;   // fork + one per level (capture edges only)
+  DecodeArgs a{};               // the captured decode's arguments
+  uint32_t waves = 0, per_wave = 0;
+  uint64_t off_plan = 0, off_pin = 0, off_pinbase = 0;
+  uint32_t pinned_levels = 0;
 };
 
 namespace {
 struct BatchLayout {
-  uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, done, lit, lens, offs, slots, desc, total;
+  uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, done, lit, lens, offs, slots, desc, pin, pinbase,
+      total;
 };
 
 BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
@@ -720,6 +725,8 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   L.offs = take((uint64_t)A->ow * A->all_seq);
   L.slots = take((uint64_t)A->B * A->nb);
   L.desc = take(16 + 24ull * cap);
+  L.pin = take(align_up(A->nb, 4));
+  L.pinbase = take(4);
   L.total = o;
   return L;
 }
@@ -794,6 +801,18 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     ba.n_plan_dev = reinterpret_cast<uint32_t*>(b->ws + L.nplan);
     ba.lvl_dev = reinterpret_cast<uint32_t*>(b->ws + L.lvl);
     ba.loc = reinterpret_cast<uint64_t*>(b->ws + L.loc);
+    ba.pin = b->ws + L.pin;
+    ba.pin_base = reinterpret_cast<const uint32_t*>(b->ws + L.pinbase);
+    b->off_plan = L.plan;
+    b->off_pin = L.pin;
+    b->off_pinbase = L.pinbase;
+    // nothing kept yet: every block is planned when needed, from slot 0
+    if (launch_fill_u32(reinterpret_cast<uint32_t*>(b->ws + L.pin), 0u, align_up(A->nb, 4) / 4, s) != hipSuccess ||
+        launch_fill_u32(reinterpret_cast<uint32_t*>(b->ws + L.pinbase), 0u, 1, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(ACE_E_HIP, "clearing the kept-block table failed");
+      break;
+    }
     DecodeArgs a{};
     a.arch = A->d_arch;
     a.plan = ba.plan;
@@ -828,6 +847,9 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     }
     if ((rc = check_tuning(A, t)) != ACE_OK) break;
     const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
+    b->a = a;
+    b->waves = waves;
+    b->per_wave = per_wave;
     // the late levels' entropy decode on a branch of the graph, beside the
     // early levels' decode (mode 3)
     const bool overlap = mode == kModeOverlap && A->depth > 1;
@@ -896,6 +918,42 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     return rc;
   }
   *out = b;
+  return ACE_OK;
+}
+
+extern "C" int ace_batch_pin(ace_batch* b, uint32_t levels) {
+  if (!b) return fail(ACE_E_ARG, "null argument");
+  const ace_archive* A = b->A;
+  if (b->pinned_levels) return fail(ACE_E_ARG, "this batch already keeps %u levels", b->pinned_levels);
+  if (levels > A->depth) return fail(ACE_E_ARG, "%u levels requested, the archive has %u", levels, A->depth);
+  if (levels == 0) return ACE_OK;
+  // the plan, token scratch and slots are shared with the replays
+  if (b->pending) HIP_TRY(hipEventSynchronize(b->done));
+  b->pending = false;
+  hipStream_t s = b->stream;
+  // levels [0, levels) are a prefix of the whole-archive level order and are
+  // closed under dependencies: entry i decodes into slot i
+  const uint32_t P = A->all_levels[levels];
+  std::vector<PlanEntry> e(A->all_plan.begin(), A->all_plan.begin() + P);
+  for (uint32_t i = 0; i < P; i++) e[i].dst = (uint64_t)i * A->B;
+  std::vector<uint8_t> pin(align_up(A->nb, 4), 0);
+  for (uint32_t i = 0; i < P; i++) pin[e[i].block] = 1;
+  DecodeArgs a = b->a;
+  a.plan = reinterpret_cast<const PlanEntry*>(b->ws + b->off_plan);
+  a.n_plan = P;
+  a.n_plan_dev = nullptr;
+  a.lvl_dev = nullptr;
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_plan, e.data(), sizeof(PlanEntry) * P, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_rans(a, 0, P, b->per_wave, s));
+  for (uint32_t l = 0; l < levels; l++)
+    HIP_TRY(launch_expand_level(a, A->all_levels[l], A->all_levels[l + 1], b->waves, s));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pin, pin.data(), pin.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pinbase, &P, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, b->ws, 4, hipMemcpyDeviceToHost));
+  if (err) return fail(ACE_E_CORRUPT, "decoding the kept levels failed (device error word 0x%x)", err);
+  b->pinned_levels = levels;
   return ACE_OK;
 }
 

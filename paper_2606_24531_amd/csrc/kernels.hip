@@ -1313,6 +1313,8 @@ __global__ __launch_bounds__(256) void k_copy(DecodeArgs a, const CopyItem* item
 // top (dependencies always sit at lower levels); compact the marked blocks,
 // in level order, into a plan whose entries decode into workspace slots;
 // after the decode, gather each request's range to its output offset.
+// Kept blocks (decoded once, in the first pin_base slots) are never marked:
+// their locations stay valid, and closures stop at them.
 // ---------------------------------------------------------------------------
 __global__ void k_bmark(BatchArgs b) {
   const uint64_t n = b.desc[0];
@@ -1320,7 +1322,8 @@ __global__ void k_bmark(BatchArgs b) {
        r += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = b.desc[2 + 3 * r], hi = b.desc[3 + 3 * r];
     if (hi <= lo || hi > b.n_total) continue;
-    for (uint64_t blk = lo / b.B; blk <= (hi - 1) / b.B; blk++) b.need[blk] = 1;
+    for (uint64_t blk = lo / b.B; blk <= (hi - 1) / b.B; blk++)
+      if (!b.pin[blk]) b.need[blk] = 1;
   }
 }
 
@@ -1332,7 +1335,10 @@ __global__ void k_bclose(BatchArgs b, uint32_t level) {
     const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
     const uint32_t dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
     const uint32_t* deps = reinterpret_cast<const uint32_t*>(b.arch + kHdr + (uint64_t)kBlk * b.n_blocks) + dep_off;
-    for (uint32_t k = 0; k < dep_cnt; k++) b.need[deps[k]] = 1;
+    for (uint32_t k = 0; k < dep_cnt; k++) {
+      const uint32_t d = deps[k];
+      if (!b.pin[d]) b.need[d] = 1;
+    }
   }
 }
 
@@ -1376,7 +1382,7 @@ __global__ __launch_bounds__(1024) void k_bcompact(BatchArgs b) {
       PlanEntry e{};
       e.block = blk;
       e.seq_base = seq;
-      e.dst = (uint64_t)pos * b.B;
+      e.dst = (uint64_t)(*b.pin_base + pos) * b.B;
       e.pay = ld64(be);
       e.n_seq = ns;
       e.dep_off = ld32(be + 20);

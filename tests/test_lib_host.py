@@ -149,4 +149,5 @@ def test_argument_errors_before_device_work(lib):
         assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(bad_t), None) == lib.E_ARG
     r = np.array([0, 100_001], dtype=np.uint64)
     assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), 1, C.byref(ws)) == lib.E_RANGE
+    assert L.ace_batch_pin(None, 1) == lib.E_ARG
     L.ace_archive_close(h)
