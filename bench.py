@@ -92,6 +92,9 @@ def main():
                     help="archive sizes as a fraction of 4/2/1/1 GiB")
     ap.add_argument("--serve-rates", default="1000,5000,20000,100000")
     ap.add_argument("--serve-count", type=int, default=3000)
+    ap.add_argument("--serve-keep", type=int, default=-1,
+                    help="serving: keep this many of each archive's lowest dependency levels "
+                         "decoded per slot (captured batch graphs); -1 = plain batched seeks")
     ap.add_argument("--suite", default="",
                     help="instead of the headline decode, run the other workloads and print one "
                          "JSON line each: genome1m (1 MiB genome, decode + every block sought with "
@@ -342,8 +345,10 @@ def serve_main(args):
         del x
     rates = [float(r) for r in args.serve_rates.split(",")]
     runs = []
+    keep = args.serve_keep if args.serve_keep >= 0 else None
+    backend = GpuBackend(arcs, slots=4, keep_levels=keep, max_batch=4096)
     for rate in rates:
-        srv = Server(GpuBackend(arcs, slots=4), budget_bytes=32 << 30, slots=4, max_batch=4096)
+        srv = Server(backend, budget_bytes=32 << 30, slots=4, max_batch=4096)
         reqs, wall = poisson_run(srv, list(arcs), n_total, rate=rate, count=args.serve_count,
                                  seed=int(rate), min_len=16, max_len=16 << 20)
         torch.cuda.synchronize()
@@ -358,7 +363,8 @@ def serve_main(args):
         "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
         "config": {"workload": "resident genome/fastq/text/mixed archives at %.4g of 4/2/1/1 GiB, "
                                "Poisson arrivals, 16 B..16 MiB log-uniform, 32 GiB budget, 4 slots"
-                               % args.serve_scale},
+                               % args.serve_scale,
+                   "kept_levels": keep},
         "runs": runs}), flush=True)
 
 

@@ -7,7 +7,9 @@ are grouped per archive into a batch as soon as one of K in-flight slots is
 free; each slot owns a HIP stream and a workspace, so batches on different
 slots overlap on the device.  A batch is one seek_batch call (one
 dependency-ordered decode of the union of the requests' closures, then one
-gather).  Latency is measured from a request's scheduled arrival to the
+gather), or, with keep_levels, one replay of a captured batch graph per
+(slot, archive) whose lowest dependency levels stay decoded (ace_batch_pin),
+so closures stop there.  Latency is measured from a request's scheduled arrival to the
 completion of its batch, so queueing is included.
 
 The device work goes through a backend object so the scheduling logic can
@@ -42,13 +44,21 @@ class Request:
 class GpuBackend:
     """Slots on HIP streams, decoding with libaceseek's batched seek."""
 
-    def __init__(self, archives: dict, slots: int, device="cuda:0"):
+    def __init__(self, archives: dict, slots: int, device="cuda:0", keep_levels=None, max_batch: int = 4096):
         import torch
         self.torch = torch
         self.archives = archives
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.ws = [None] * slots
+        # kept levels: a batch graph per (slot, archive), its lowest levels decoded once
+        self.batches = {}
+        if keep_levels is not None:
+            for slot in range(slots):
+                for name, arc in archives.items():
+                    bt = arc.batch(max_batch, stream=self.streams[slot])
+                    bt.pin(min(int(keep_levels), arc.depth))
+                    self.batches[(slot, name)] = bt
 
     def launch(self, slot: int, name: str, reqs):
         torch = self.torch
@@ -57,13 +67,17 @@ class GpuBackend:
         hi = np.array([r.hi for r in reqs], dtype=np.uint64)
         lens = (hi - lo).astype(np.int64)
         offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
-        need = arc.workspace_bytes((lo, hi))
         s = self.streams[slot]
+        bt = self.batches.get((slot, name))
         with torch.cuda.stream(s):
-            if self.ws[slot] is None or self.ws[slot].numel() < need:
-                self.ws[slot] = torch.zeros(max(need, 256), dtype=torch.uint8, device=self.device)
             out = torch.empty(max(int(lens.sum()), 1), dtype=torch.uint8, device=self.device)
-            arc.seek_batch((lo, hi), out=out, out_offsets=offs, ws=self.ws[slot], stream=s)
+            if bt is not None:
+                bt.run((lo, hi), out, offs)
+            else:
+                need = arc.workspace_bytes((lo, hi))
+                if self.ws[slot] is None or self.ws[slot].numel() < need:
+                    self.ws[slot] = torch.zeros(max(need, 256), dtype=torch.uint8, device=self.device)
+                arc.seek_batch((lo, hi), out=out, out_offsets=offs, ws=self.ws[slot], stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         views = [out[int(o):int(o) + int(n)] for o, n in zip(offs, lens)]
@@ -74,7 +88,11 @@ class GpuBackend:
 
     def finish(self, handle):
         ev, views, slot, name = handle
-        self.archives[name].check(ws=self.ws[slot], stream=self.streams[slot])
+        bt = self.batches.get((slot, name))
+        if bt is not None:
+            bt.check()
+        else:
+            self.archives[name].check(ws=self.ws[slot], stream=self.streams[slot])
         return views
 
 

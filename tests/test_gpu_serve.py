@@ -1,6 +1,7 @@
 """Continuous batching on the GPU: requests arriving while others run are
 admitted into free slots (each slot its own HIP stream and workspace), and
-every result is byte-identical alone and in the mix."""
+every result is byte-identical alone and in the mix, with plain batched
+seeks and with captured batch graphs that keep level 0 decoded."""
 import numpy as np
 import pytest
 
@@ -10,7 +11,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_results_same_alone_and_in_mix(orc):
+@pytest.mark.parametrize("keep", [None, 1], ids=["plain", "kept-level-0"])
+def test_results_same_alone_and_in_mix(orc, keep):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2606_24531_amd import Archive, encode
@@ -19,7 +21,8 @@ def test_results_same_alone_and_in_mix(orc):
           "text": gen.text(2 << 20, 53)}
     arcs = {k: Archive(encode(v, block_size=16384, interleave=32, min_match=16, hash_len=16,
                               max_level=8), device="cuda:0") for k, v in xs.items()}
-    srv = Server(GpuBackend(arcs, slots=3), budget_bytes=8 << 20, slots=3, max_batch=64)
+    srv = Server(GpuBackend(arcs, slots=3, keep_levels=keep, max_batch=64), budget_bytes=8 << 20, slots=3,
+                 max_batch=64)
     reqs, wall = poisson_run(srv, list(xs), {k: len(v) for k, v in xs.items()}, rate=3000.0,
                              count=400, seed=5, min_len=16, max_len=1 << 20)
     rep = latency_report(reqs, wall)
