@@ -44,8 +44,10 @@ def test_graph_batch_replays(orc, tuning):
     bt.close()
 
 
-@pytest.mark.parametrize("levels", [1, 2, "all"])
-def test_graph_batch_with_kept_levels(orc, levels):
+@pytest.mark.parametrize("levels,W,tuning", [(1, 32, None), (2, 32, None), ("all", 32, None),
+                                             (2, 64, dict(mode=3)), (1, 64, dict(mode=1, waves_per_block=4))],
+                         ids=["keep1", "keep2", "keep-all", "keep2-W64-overlap", "keep1-W64-4waves"])
+def test_graph_batch_with_kept_levels(orc, levels, W, tuning):
     """Keeping the lowest dependency levels decoded (ace_batch_pin): later
     batches neither plan nor decode those blocks, and every request still
     equals the original bytes, including requests that lie entirely in kept
@@ -56,11 +58,11 @@ def test_graph_batch_with_kept_levels(orc, levels):
     from paper_2606_24531_amd.aceseek import AceError, E_ARG
     x = gen.mixed(3 << 20, 13)
     # uncapped: 54 dependency levels on this input
-    a = encode(x, block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=0)
+    a = encode(x, block_size=16384, interleave=W, min_match=16, hash_len=16, max_level=0)
     arc = Archive(a, device="cuda:0")
     assert arc.depth >= 3
     keep = arc.depth if levels == "all" else levels
-    bt = arc.batch(300)
+    bt = arc.batch(300, tuning=tuning)
     with pytest.raises(AceError) as ei:
         bt.pin(arc.depth + 1)
     assert ei.value.code == E_ARG
