@@ -1014,40 +1014,27 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         const uint32_t k = k0 + tid + j * kThreads;
-        cbv[j] = 0xFFFFFFFFu;
-        const uint8_t* vsrc = c.lit;
         const bool here = k < k0 + kn;
         const uint32_t cb = base + 16 * k;
-        bool vec = false;
-        uint32_t sq = 0;
-        if (here) {
-          const uint32_t p0 = cb < d0 ? d0 : cb;
-          const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-          sq = sqv[j];
-          const uint32_t fl = sm.dfl[sq] >> 24;
-          if (aligned && p0 == cb && pe1 == cb + 16 && !(fl & kPoison)) {
-            const uint32_t end_s = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
-            const uint32_t r0 = cb - sm.dst[sq], Ls = sm.lm[sq] & 0xFFFFu;
-            const uint8_t* src = nullptr;
-            if (cb + 16 > end_s) {
-              vec = false;
-            } else if (r0 + 16 <= Ls) {
-              vec = true;  // all literals (stream data has readable slack)
-              src = c.lit + sm.lit[sq] + r0;
-            } else if (r0 >= Ls && !(fl & kUnres)) {
-              // no period wrap inside the chunk: its 16 source bytes lie in
-              // the resolved span, which is readable
-              const uint32_t ii0 = r0 - Ls;
-              vec = ii0 + 16 <= (sm.dfl[sq] & 0xFFFFFFu);
-              src = reinterpret_cast<const uint8_t*>(sm.src0[sq] + ii0);
-            }
-            if (vec) {
-              vsrc = src;
-              cbv[j] = cb;
-            }
-          }
-        }
-        w[j] = ld16u(vsrc);
+        // branch-free: every LDS field the decision needs is read at once
+        // (sq is a valid slot even for chunks past the tile's end)
+        const uint32_t sq = sqv[j] < c.cnt ? sqv[j] : c.cnt - 1;
+        const uint32_t dfl = sm.dfl[sq], sd = sm.dst[sq], lmv = sm.lm[sq], litv = sm.lit[sq];
+        const uint32_t sn = sm.dst[sq + 1 < kSeq ? sq + 1 : sq];
+        const uint64_t s0 = sm.src0[sq];
+        const uint32_t fl = dfl >> 24, Ls = lmv & 0xFFFFu;
+        const uint32_t end_s = sq + 1 < c.cnt ? sn : d1;
+        const uint32_t r0 = cb - sd, ii0 = r0 - Ls;  // used only when the chunk is whole
+        const bool whole = here && aligned && cb >= d0 && cb + 16 <= d1 && cb + 16 <= end_s && !(fl & kPoison);
+        // all literals (stream data has readable slack), or a resolved match
+        // with no period wrap inside the chunk (its 16 source bytes lie in
+        // the resolved span, which is readable)
+        const bool lit_ok = r0 + 16 <= Ls;
+        const bool mat_ok = r0 >= Ls && !(fl & kUnres) && ii0 + 16 <= (dfl & 0xFFFFFFu);
+        const bool vec = whole && (lit_ok || mat_ok);
+        const uint8_t* src = lit_ok ? c.lit + litv + r0 : reinterpret_cast<const uint8_t*>(s0 + ii0);
+        cbv[j] = vec ? cb : 0xFFFFFFFFu;
+        w[j] = ld16u(vec ? src : c.lit);  // c.lit is always readable
         const bool byte = here && !vec;
         const uint64_t mb = __builtin_amdgcn_ballot_w64(byte);
         const uint32_t lane = tid & 63;
