@@ -673,6 +673,14 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
   bool load[kC];
   uint32_t x = cb;
   bool ok = true;
+  // the two candidate sequences' fields, read at once (indices clamped into
+  // the tile arrays; values past c.cnt are never used)
+  constexpr uint32_t kSeq = ExpandSmem<kThreads>::kSeq;
+  const uint32_t s1 = s + 1 < kSeq ? s + 1 : s, s2 = s + 2 < kSeq ? s + 2 : s;
+  const uint32_t dst_q[3] = {sm.dst[s], sm.dst[s1], sm.dst[s2]};
+  const uint32_t lm_q[2] = {sm.lm[s], sm.lm[s1]}, dfl_q[2] = {sm.dfl[s], sm.dfl[s1]};
+  const uint32_t lit_q[2] = {sm.lit[s], sm.lit[s1]}, win_q[2] = {sm.win[s], sm.win[s1]};
+  const uint64_t src_q[2] = {sm.src0[s], sm.src0[s1]};
 #pragma unroll
   for (uint32_t q = 0; q < 2; q++) {
     load[2 * q] = load[2 * q + 1] = false;
@@ -680,10 +688,10 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
     V[2 * q] = V[2 * q + 1] = 0;
     const uint32_t sq = s + q;
     if (x < cb + 16 && sq < c.cnt) {
-      const uint32_t sd = sm.dst[sq];
-      const uint32_t se = sq + 1 < c.cnt ? sm.dst[sq + 1] : d1;
-      const uint32_t L = sm.lm[sq] & 0xFFFFu;
-      const uint32_t dfl = sm.dfl[sq], f = dfl >> 24, d = dfl & 0xFFFFFFu;
+      const uint32_t sd = dst_q[q];
+      const uint32_t se = sq + 1 < c.cnt ? dst_q[q + 1] : d1;
+      const uint32_t L = lm_q[q] & 0xFFFFu;
+      const uint32_t dfl = dfl_q[q], f = dfl >> 24, d = dfl & 0xFFFFFFu;
       const uint32_t end = se < cb + 16 ? se : cb + 16;
       if (f & kPoison) {
         lo[2 * q] = x - cb;  // zeros: a segment with no load
@@ -692,7 +700,7 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
       } else {
         if (x < sd + L) {  // literal run
           const uint32_t h = sd + L < end ? sd + L : end;
-          const uint8_t* A = c.lit + sm.lit[sq] + (x - sd);
+          const uint8_t* A = c.lit + lit_q[q] + (x - sd);
           V[2 * q] = (uint64_t)(uintptr_t)A - (x - cb);
           lo[2 * q] = x - cb;
           hi[2 * q] = h - cb;
@@ -704,9 +712,9 @@ __device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const 
           lo[2 * q + 1] = x - cb;
           hi[2 * q + 1] = end - cb;
           if (!(f & kUnres)) {
-            const uint64_t A = sm.src0[sq] + ii0;
+            const uint64_t A = src_q[q] + ii0;
             const uint64_t v = A - (x - cb);
-            const uint32_t wn = sm.win[sq], back = (wn & 31u) + ii0, fwd = (wn >> 5) - ii0;
+            const uint32_t wn = win_q[q], back = (wn & 31u) + ii0, fwd = (wn >> 5) - ii0;
             const uint32_t need_back = x - cb;  // bytes read before the segment's source
             ok = ok && ii0 + (end - x) <= d && need_back <= back && 16 - need_back <= fwd;
             V[2 * q + 1] = v;
