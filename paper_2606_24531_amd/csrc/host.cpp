@@ -947,12 +947,18 @@ extern "C" int ace_batch_pin(ace_batch* b, uint32_t levels) {
   HIP_TRY(launch_rans(a, 0, P, b->per_wave, s));
   for (uint32_t l = 0; l < levels; l++)
     HIP_TRY(launch_expand_level(a, A->all_levels[l], A->all_levels[l + 1], b->waves, s));
-  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pin, pin.data(), pin.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pinbase, &P, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   uint32_t err = 0;
   HIP_TRY(hipMemcpy(&err, b->ws, 4, hipMemcpyDeviceToHost));
-  if (err) return fail(ACE_E_CORRUPT, "decoding the kept levels failed (device error word 0x%x)", err);
+  if (err) {  // reported here, so cleared; nothing is marked kept
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(b->ws, &zero, 4, hipMemcpyHostToDevice));
+    return fail(ACE_E_CORRUPT, "decoding the kept levels failed (device error word 0x%x)", err);
+  }
+  // only a complete decode is marked kept
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pin, pin.data(), pin.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->off_pinbase, &P, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   b->pinned_levels = levels;
   return ACE_OK;
 }

@@ -91,3 +91,31 @@ def test_lengths_that_miss_the_block(ace, orc, mode):
     arc = ace.Archive(a, device="cuda:0")
     assert arc.decode_all(tuning=dict(mode=mode)).cpu().numpy().tobytes() == x
     arc.check()
+
+
+def test_damaged_kept_level_is_not_kept(ace, orc):
+    """ace_batch_pin over a level whose stream is damaged reports
+    ACE_E_CORRUPT, clears the sticky word it read, keeps nothing (a second
+    call is allowed and fails the same way), and the batch still replays."""
+    x = gen.genome(1 << 18, 6)
+    a = orc.encode(x, block_size=4096, interleave=32, flags=1)
+    nb = (len(x) + 4095) // 4096
+    b = next(i for i in range(nb) if block_entry(a, i)["level"] == 0 and stream_desc(a, i, 0)["mode"] == 1)
+    sd = stream_desc(a, b, 0)
+    nsym = sum(1 for s in range(256) if (a[sd["data_at"] + s // 8] >> (s % 8)) & 1)
+    st = sd["data_at"] + ((32 + 2 * nsym + 3) & ~3)
+    bad = _patch(a, st + 4, "<I", struct.unpack_from("<I", a, st + 4)[0] ^ 0x100)
+    arc = ace.Archive(bad, device="cuda:0")
+    bt = arc.batch(8)
+    for _ in range(2):
+        with pytest.raises(ace.AceError) as e:
+            bt.pin(1)
+        assert e.value.code == ace.E_CORRUPT
+        bt.check()  # the word the failed call read was cleared
+    lo, hi = b * 4096 + 10, b * 4096 + 50
+    out = torch.zeros(hi - lo, dtype=torch.uint8, device="cuda:0")
+    bt.run(([lo], [hi]), out)
+    with pytest.raises(ace.AceError) as e:
+        bt.check()  # the damaged block was planned and decoded again, not read as kept
+    assert e.value.code == ace.E_CORRUPT
+    bt.close()
