@@ -52,9 +52,13 @@ extern "C" {
  *  hash_len    bytes hashed per position, 1 .. 64
  *  max_chain   hash-chain candidates examined per position
  *  max_level   0 = unbounded; else every block's dependency level < max_level
- *  flags       stream-mode policy: 0 = rANS only where smaller, 1 = always
- *              rANS, 2 = always raw
+ *  flags       bits 0-1, stream-mode policy: 0 = rANS only where smaller,
+ *              1 = always rANS, 2 = always raw; bit 2 (ACE_ENC_WIDE_OFFSETS):
+ *              store absolute offsets in 8 bytes even when every position
+ *              fits in 4 (the width archives above 4 GiB need); other bits
+ *              are ACE_E_ARG
  *  n_threads   host threads for the parse (0 = all cores) */
+#define ACE_ENC_WIDE_OFFSETS 4u
 typedef struct {
   uint32_t block_size, interleave, min_match, hash_len, max_chain, max_level, flags, n_threads;
 } ace_encode_params;

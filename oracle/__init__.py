@@ -18,6 +18,10 @@ _SOURCES = ["common.c", "ans.c", "encode.c", "decode.c"]
 
 OK, E_ARG, E_RANGE, E_CORRUPT, E_NOSPACE, E_NOMEM = 0, -1, -2, -3, -4, -7
 MODE_AUTO, MODE_RANS, MODE_RAW = 0, 1, 2
+WIDE_OFFSETS = 4  # flags bit: 8-byte offsets at any size
+
+
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-shared", "-fPIC"]
 
 
 def build(force: bool = False) -> str:
@@ -29,8 +33,7 @@ def build(force: bool = False) -> str:
                                                          os.path.join(_HERE, "internal.h")]):
             return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           "-o", tmp] + srcs)
+    subprocess.check_call(["gcc"] + CFLAGS + ["-o", tmp] + srcs)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -72,6 +75,8 @@ def lib():
                                    u32p, u32p, u32p, u64p, C.c_void_p, C.c_uint64, u64p]
         L.orc_info.argtypes = [C.c_void_p, C.c_uint64, u64p, u32p, u32p, u32p, u32p]
         L.orc_decode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64]
+        L.orc_decode_levels.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_int,
+                                        C.POINTER(C.c_int)]
         L.orc_seek.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_closure.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p,
                                   u32p]
@@ -190,6 +195,18 @@ def decode(a: bytes) -> bytes:
     out = np.empty(max(n, 1), dtype=np.uint8)
     _check(lib().orc_decode(p, len(keep), out.ctypes.data_as(C.c_void_p), n))
     return out[:n].tobytes()
+
+
+def decode_levels(a: bytes, threads: int = 0):
+    """Decode with each dependency level's blocks in parallel on `threads`
+    host threads (0 = all).  Returns (bytes, threads used)."""
+    p, keep = _buf(a)
+    n = info(a)["n_total"]
+    out = np.empty(max(n, 1), dtype=np.uint8)
+    used = C.c_int(0)
+    _check(lib().orc_decode_levels(p, len(keep), out.ctypes.data_as(C.c_void_p), n, int(threads),
+                                   C.byref(used)))
+    return out[:n].tobytes(), used.value
 
 
 def decode_rc(a: bytes) -> int:

@@ -13,6 +13,7 @@
  * closure helper lists the blocks the paper's isolated seek needs (Section 3:
  * a block decodes once the blocks holding its source bytes are present).
  */
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 #include "internal.h"
@@ -345,4 +346,70 @@ int orc_block_tokens(const uint8_t* a, uint64_t len, uint32_t block, uint8_t* li
     *n_seq = e.n_seq;
   }
   return rc;
+}
+
+/* Whole-archive decode with the blocks of one dependency level decoded in
+ * parallel (OpenMP), levels in increasing order: a block's dependencies all
+ * sit at lower levels (Section 2: a block decodes once the blocks holding
+ * its sources are present), so the blocks of one level are independent.
+ * Each block goes through the same decode_block as the sequential decoder.
+ * This is the all-cores CPU baseline, not a second definition of decode: on
+ * any error the sequential decoder is run to report it. */
+int orc_decode_levels(const uint8_t* a, uint64_t len, uint8_t* out, uint64_t cap, int threads,
+                      int* threads_used) {
+  hdr_t h;
+  int rc = parse_header(a, len, &h);
+  if (rc) return rc;
+  if (cap < h.n) return orc_fail(ORC_E_NOSPACE, "output needs %llu bytes", (unsigned long long)h.n);
+  if (h.n && !out) return orc_fail(ORC_E_ARG, "null output");
+  uint32_t nb = h.nb, depth = h.depth;
+  uint32_t* stored = (uint32_t*)malloc(sizeof(uint32_t) * (nb ? nb : 1));
+  uint32_t* levels = (uint32_t*)malloc(sizeof(uint32_t) * (nb ? nb : 1));
+  uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (nb ? nb : 1));
+  uint32_t* lstart = (uint32_t*)calloc((size_t)depth + 2, sizeof(uint32_t));
+  if (!stored || !levels || !order || !lstart) {
+    free(stored); free(levels); free(order); free(lstart);
+    return orc_fail(ORC_E_NOMEM, "out of memory");
+  }
+  for (uint32_t b = 0; b < nb && !rc; b++) {
+    blk_t e;
+    rc = read_block(&h, b, &e);
+    if (!rc && e.level >= depth) rc = orc_fail(ORC_E_CORRUPT, "block %u: level %u not below depth %u", b, e.level, depth);
+    if (!rc) {
+      stored[b] = e.level;
+      lstart[e.level + 1]++;
+    }
+  }
+  if (!rc) {
+    for (uint32_t l = 0; l < depth; l++) lstart[l + 1] += lstart[l];
+    uint32_t* fill = (uint32_t*)malloc(sizeof(uint32_t) * (depth ? depth : 1));
+    if (!fill) rc = orc_fail(ORC_E_NOMEM, "out of memory");
+    for (uint32_t l = 0; !rc && l < depth; l++) fill[l] = lstart[l];
+    for (uint32_t b = 0; !rc && b < nb; b++) order[fill[stored[b]]++] = b;
+    free(fill);
+  }
+  int used = 1;
+  int failed = rc != 0;
+  for (uint32_t l = 0; l < depth && !failed; l++) {
+    const int64_t lo = lstart[l], hi = lstart[l + 1];
+#pragma omp parallel num_threads(threads > 0 ? threads : omp_get_max_threads())
+    {
+#pragma omp single
+      used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 8) reduction(| : failed)
+      for (int64_t j = lo; j < hi; j++) {
+        uint32_t lv = 0;
+        if (decode_block(&h, order[j], levels, out, &lv)) failed = 1;
+        else levels[order[j]] = lv;
+      }
+    }
+  }
+  free(stored); free(levels); free(order); free(lstart);
+  if (threads_used) *threads_used = used;
+  if (failed) return orc_decode(a, len, out, cap);  /* reports the error */
+  if (h.max_level && depth > h.max_level)
+    return orc_fail(ORC_E_CORRUPT, "a level reaches %u, above the stated cap %u", depth - 1, h.max_level - 1);
+  if (orc_fnv1a64(out, h.n) != rd64(a + 56))
+    return orc_fail(ORC_E_CORRUPT, "decoded bytes do not match the stored FNV-1a-64");
+  return ORC_OK;
 }

@@ -173,7 +173,8 @@ static int assemble(const uint8_t* x, uint64_t n, uint32_t B, uint32_t W, uint32
   uint64_t nb64 = n ? (n + B - 1) / B : 0;
   if (nb64 > 0xFFFFFFFFull) return orc_fail(ORC_E_ARG, "too many blocks");
   uint32_t nb = (uint32_t)nb64;
-  uint32_t ow = n <= (1ull << 32) ? 4 : 8;
+  /* offsets take 8 bytes once a position can exceed 32 bits, or on request */
+  uint32_t ow = (n <= (1ull << 32) && !(flags & ORC_WIDE_OFFSETS)) ? 4 : 8;
   uint32_t *level = NULL, **deps = NULL, *dcnt = NULL;
   enc_stream* st = NULL;
   uint64_t* seq0 = NULL;
@@ -345,6 +346,7 @@ static int check_params(uint64_t n, const orc_params* p) {
   if (p->hash_len < 1 || p->hash_len > 64) return orc_fail(ORC_E_ARG, "hash_len outside 1..64");
   if (p->min_match < p->hash_len) return orc_fail(ORC_E_ARG, "min_match below hash_len");
   if ((p->flags & 3) == 3) return orc_fail(ORC_E_ARG, "bad stream-mode policy");
+  if (p->flags & ~7u) return orc_fail(ORC_E_ARG, "unknown flag bits");
   (void)n;
   return ORC_OK;
 }
@@ -353,7 +355,7 @@ int orc_encode_bound(uint64_t n, const orc_params* p, uint64_t* bound) {
   int rc = check_params(n, p);
   if (rc) return rc;
   uint64_t B = p->block_size, nb = n ? (n + B - 1) / B : 0;
-  uint64_t W = p->interleave, ow = n <= (1ull << 32) ? 4 : 8;
+  uint64_t W = p->interleave, ow = (n <= (1ull << 32) && !(p->flags & ORC_WIDE_OFFSETS)) ? 4 : 8;
   uint64_t total = ORC_HDR + ORC_BLK * nb + 16;
   for (uint64_t b = 0; b < nb; b++) {
     uint64_t len = (b + 1) * B <= n ? B : n - b * B;
@@ -507,7 +509,7 @@ int orc_assemble(const uint8_t* x, uint64_t n, uint32_t block_size, uint32_t int
                  const uint32_t* M, const uint64_t* O, uint8_t* dst, uint64_t cap,
                  uint64_t* out_len) {
   if (block_size < 1 || block_size > (1u << 24) || interleave < 1 || interleave > 64 ||
-      (flags & 3) == 3 || !out_len || (!x && n))
+      (flags & 3) == 3 || (flags & ~7u) || !out_len || (!x && n))
     return orc_fail(ORC_E_ARG, "assemble: bad arguments");
   uint8_t* arch = NULL;
   uint64_t alen = 0;

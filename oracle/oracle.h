@@ -50,6 +50,9 @@ typedef struct {
 
 /* Stream-mode policy (flags & 3). */
 enum { ORC_MODE_AUTO = 0, ORC_MODE_RANS = 1, ORC_MODE_RAW = 2 };
+/* flags bit 2: store offsets in 8 bytes even when every position fits in 4
+ * (the format's width for outputs above 4 GiB; encoder policy only). */
+enum { ORC_WIDE_OFFSETS = 4 };
 
 const char* orc_last_error(void);
 uint64_t orc_fnv1a64(const uint8_t* p, uint64_t n);
@@ -86,6 +89,11 @@ int orc_info(const uint8_t* a, uint64_t len, uint64_t* n_total,
              uint32_t* interleave);
 /* Full validation and sequential decode into out (cap >= n_total). */
 int orc_decode(const uint8_t* a, uint64_t len, uint8_t* out, uint64_t cap);
+/* The same decode with the blocks of each dependency level decoded in
+ * parallel on `threads` host threads (0 = all; OpenMP), levels in order.
+ * The all-cores CPU baseline; *threads_used receives the team size. */
+int orc_decode_levels(const uint8_t* a, uint64_t len, uint8_t* out, uint64_t cap, int threads,
+                      int* threads_used);
 /* out[0 .. hi-lo) = decode(a)[lo:hi). */
 int orc_seek(const uint8_t* a, uint64_t len, uint64_t lo, uint64_t hi,
              uint8_t* out);

@@ -305,6 +305,12 @@ void code_stream(const uint8_t* sym, uint32_t n, uint32_t W, uint32_t policy, En
   for (size_t i = 0; i < words.size(); i++) put16(wp + 2 * i, words[words.size() - 1 - i]);
 }
 
+// Bytes per stored absolute offset: 4 while every position fits in 32 bits,
+// else 8; ACE_ENC_WIDE_OFFSETS asks for 8 at any size.
+uint32_t offset_width(uint64_t n, uint32_t flags) {
+  return (n > (1ull << 32) || (flags & ACE_ENC_WIDE_OFFSETS)) ? 8u : 4u;
+}
+
 int check(uint64_t n, const ace_encode_params* p) {
   if (!p) return efail(ACE_E_ARG, "null parameters");
   if (p->block_size < 1 || p->block_size > (1u << 24)) return efail(ACE_E_ARG, "block_size outside 1..2^24");
@@ -312,6 +318,7 @@ int check(uint64_t n, const ace_encode_params* p) {
   if (p->hash_len < 1 || p->hash_len > 64) return efail(ACE_E_ARG, "hash_len outside 1..64");
   if (p->min_match < p->hash_len) return efail(ACE_E_ARG, "min_match below hash_len");
   if ((p->flags & 3) == 3) return efail(ACE_E_ARG, "unknown stream-mode policy");
+  if (p->flags & ~7u) return efail(ACE_E_ARG, "unknown flag bits 0x%x", p->flags & ~7u);
   if (n > (1ull << 32)) return efail(ACE_E_ARG, "inputs above 4 GiB are not supported by this encoder");
   return ACE_OK;
 }
@@ -344,7 +351,7 @@ extern "C" int ace_encode_bound(uint64_t n, const ace_encode_params* p, uint64_t
     const uint64_t len = std::min<uint64_t>(B, n - b * B);
     uint64_t nseq = std::min<uint64_t>(len, len / p->min_match + len / 65535 + 2);
     const uint64_t dep = std::min<uint64_t>(b, 2 * nseq + 1);
-    const uint64_t syms[3] = {len, 4 * nseq, 4 * nseq};
+    const uint64_t syms[3] = {len, 4 * nseq, offset_width(n, p->flags) * nseq};
     uint64_t sz = 16 + 48 + 4 * dep;
     for (int t = 0; t < 3; t++) sz += 3 + ((p->flags & 3) == 1 ? 544 + 4 * W + 2 * syms[t] : syms[t]);
     total += sz;
@@ -360,7 +367,7 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
   if ((!x && n) || !out_len) return efail(ACE_E_ARG, "null argument");
   const unsigned T = thread_count(p->n_threads);
   const uint64_t B = p->block_size, nb = n ? (n + B - 1) / B : 0;
-  const uint32_t W = p->interleave, policy = p->flags & 3, ow = 4;
+  const uint32_t W = p->interleave, policy = p->flags & 3, ow = offset_width(n, p->flags);
   Chains C;
   // optional progress lines on stderr (environment ACESEEK_ENCODE_PROGRESS=1),
   // for callers that must show a long encode is alive
@@ -428,7 +435,7 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
       pos += sq[k].L + sq[k].M;
       put16(&lens[4 * k], sq[k].L);
       put16(&lens[4 * k + 2], sq[k].M);
-      put32(&offs[ow * k], (uint32_t)sq[k].O);
+      for (uint32_t i = 0; i < ow; i++) offs[ow * k + i] = (uint8_t)(sq[k].O >> (8 * i));
     }
     code_stream(lit.data(), (uint32_t)lit.size(), W, policy, st[3 * b]);
     code_stream(lens.data(), (uint32_t)lens.size(), W, policy, st[3 * b + 1]);

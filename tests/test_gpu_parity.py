@@ -55,6 +55,8 @@ CASES = [
     ("fastq", 600_000, 16384, 1, 4, 1, 20),           # one lane per stream
     ("genome", 500_000, 1000, 7, 0, 2, 20),           # non-power-of-two blocks, raw
     ("text", 100_000, 37, 3, 0, 0, 4),                # tiny blocks, thousands of them
+    ("mixed", 1_500_007, 16384, 32, 8, 4, 16),        # 8-byte offsets (the >4 GiB width)
+    ("genome", 700_003, 4096, 64, 0, 6, 20),          # 8-byte offsets, raw streams, uncapped
 ]
 
 
@@ -152,6 +154,25 @@ def test_seek_ranges_match_oracle(dev, ace, archives, orc, tuning):
             got = _host(arc.seek(lo, hi, tuning=tuning))
             arc.check()
             assert got == x[lo:hi], (c[0], lo, hi)
+
+
+@pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)
+def test_wide_offset_seeks_match_oracle(dev, ace, archives, orc, tuning):
+    """Seeks through archives whose offsets are stored in 8 bytes."""
+    rng = np.random.default_rng(15)
+    for c in CASES[-2:]:
+        x, a, _ = archives[c]
+        assert a[15] == 8
+        arc = ace.Archive(a, device=dev)
+        n, B = len(x), c[2]
+        ranges = [(0, n), (n - 3, n), (B - 1, B + 1)]
+        for _ in range(20):
+            lo = int(rng.integers(0, n))
+            ranges.append((lo, int(min(n, lo + int(np.exp(rng.uniform(0, np.log(4 * B + 1))))))))
+        for lo, hi in ranges:
+            got = _host(arc.seek(lo, hi, tuning=tuning))
+            arc.check()
+            assert got == x[lo:hi] == orc.seek(a, lo, hi), (c[0], lo, hi)
 
 
 @pytest.mark.parametrize("tuning", MODES, ids=MODE_IDS)

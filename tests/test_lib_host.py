@@ -33,7 +33,8 @@ def test_every_declared_symbol_is_exported(lib):
 @pytest.mark.parametrize("name,mm", [("genome", 20), ("fastq", 20), ("text", 16), ("random", 16),
                                      ("mixed", 16)])
 @pytest.mark.parametrize("B,W,cap,flags", [(16384, 32, 0, 0), (16384, 32, 8, 0), (4096, 64, 3, 1),
-                                           (1000, 7, 0, 2), (65536, 1, 16, 0)])
+                                           (1000, 7, 0, 2), (65536, 1, 16, 0), (16384, 32, 8, 4),
+                                           (4096, 64, 0, 5), (1000, 3, 0, 6)])
 def test_encoder_matches_oracle_encoder(orc, lib, name, mm, B, W, cap, flags):
     x = gen.by_name(name, 400_000, 21)
     kw = dict(block_size=B, interleave=W, min_match=mm, hash_len=mm, max_chain=32,
@@ -41,6 +42,14 @@ def test_encoder_matches_oracle_encoder(orc, lib, name, mm, B, W, cap, flags):
     a = lib.encode(x, **kw)
     assert a == orc.encode(x, **kw)
     assert orc.decode(a) == x
+
+
+def test_unknown_encoder_flags_are_rejected(orc, lib):
+    x = gen.text(10_000, 1)
+    with pytest.raises(lib.AceError):
+        lib.encode(x, flags=8)
+    with pytest.raises(orc.OracleError):
+        orc.encode(x, flags=8)
 
 
 def test_encoder_threads_do_not_change_output(lib):

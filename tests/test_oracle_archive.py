@@ -42,6 +42,30 @@ def test_forced_stream_modes(orc, flags):
     assert orc.decode(a) == x
 
 
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_wide_offsets(orc, policy):
+    """8-byte offsets (the width an output above 4 GiB needs) forced on a
+    small input: the parse is the same, every stored offset is the 4-byte
+    one zero-extended, and the archive decodes to the input."""
+    x = gen.mixed(600_000, 9)
+    kw = dict(block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=8)
+    a4 = orc.encode(x, flags=policy, **kw)
+    a8 = orc.encode(x, flags=policy | orc.WIDE_OFFSETS, **kw)
+    assert header(a4)["off_width"] == 4 and header(a8)["off_width"] == 8
+    assert orc.decode(a8) == x
+    nb = header(a8)["n_blocks"]
+    for b in range(nb):
+        t4, t8 = orc.block_tokens(a4, b), orc.block_tokens(a8, b)
+        assert all(np.array_equal(u, v) for u, v in zip(t4, t8))
+        if policy == 2:  # raw streams: the stored bytes themselves
+            d4, d8 = stream_desc(a4, b, 2), stream_desc(a8, b, 2)
+            o4 = np.frombuffer(a4, np.uint8, d4["n_sym"], d4["data_at"]).reshape(-1, 4)
+            o8 = np.frombuffer(a8, np.uint8, d8["n_sym"], d8["data_at"]).reshape(-1, 8)
+            assert np.array_equal(o8[:, :4], o4) and not o8[:, 4:].any()
+    for lo, hi in [(0, len(x)), (123_457, 345_679), (len(x) - 10, len(x))]:
+        assert orc.seek(a8, lo, hi) == x[lo:hi]
+
+
 def test_seek_equals_slice_and_three_phase_every_block(orc):
     # the paper's core experiment, on the small genome workload: every block
     # sought singly, checked in three phases
@@ -183,3 +207,29 @@ def test_random_bit_flips_never_crash(orc, raw_archive):
     assert set(codes) <= {0, orc.E_CORRUPT}
     # only padding bytes may hide a flip
     assert codes.count(orc.E_CORRUPT) >= 0.9 * len(codes)
+
+
+@pytest.mark.parametrize("name,mm,B,cap", [("mixed", 16, 16384, 8), ("genome", 20, 4096, 0),
+                                           ("text", 16, 1000, 0)])
+def test_level_parallel_decode_equals_sequential(orc, name, mm, B, cap):
+    """The all-cores baseline decodes each dependency level's blocks in
+    parallel; its output is the sequential decode's, at any thread count."""
+    x = gen.by_name(name, 700_001, 23)
+    a = orc.encode(x, block_size=B, interleave=32, min_match=mm, hash_len=mm, max_level=cap)
+    for t in (1, 3, 0):
+        y, used = orc.decode_levels(a, t)
+        assert y == x
+        assert used >= 1 and (t == 0 or used == t)
+
+
+def test_level_parallel_decode_reports_corruption(orc):
+    x = gen.fastq(200_000, 5)
+    a = bytearray(orc.encode(x, block_size=4096, interleave=8, max_level=4))
+    e = block_entry(bytes(a), 7)
+    d = stream_desc(bytes(a), 7, 1)
+    a[d["data_at"] + d["comp_len"] // 2] ^= 0x40  # damage one block's LEN stream
+    with pytest.raises(orc.OracleError) as ex:
+        orc.decode_levels(bytes(a), 4)
+    assert ex.value.code == orc.E_CORRUPT
+    assert ex.value.code == orc.decode_rc(bytes(a))
+    assert e["n_seq"] > 0
