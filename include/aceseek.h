@@ -203,6 +203,16 @@ int ace_read_counters(void* d_ws, void* stream, uint64_t* ext_src_bytes);
  * ace_last_timings waits for the last timed decode and returns the two
  * phases' durations in milliseconds. */
 int ace_set_timing(int on);
+
+/* Per-block clock trace for measurement.  While d_trace is set (device
+ * memory of `bytes` bytes; null turns the trace off), each whole-archive
+ * decode or seek issued by the calling thread records, per planned block i
+ * (plan order = level order), eight u64 values of the device's 100 MHz
+ * constant clock at d_trace[8 i ...]: the start and end of the block's match
+ * expansion, then start and end of its LIT, LEN and OFF entropy decode (left
+ * untouched for streams stored raw).  A decode that plans more blocks than
+ * bytes / 64 fails with ACE_E_NOSPACE.  The caller owns the buffer. */
+int ace_set_block_trace(void* d_trace, uint64_t bytes);
 int ace_last_timings(float* ms_entropy, float* ms_match);
 
 #ifdef __cplusplus

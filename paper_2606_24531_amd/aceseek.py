@@ -21,7 +21,8 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_seek", "ace_seek_batch", "ace_check", "ace_read_counters",
            "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
            "ace_batch_pin",
-           "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan"]
+           "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan",
+           "ace_set_block_trace"]
 
 
 class AceError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
         L.ace_batch_destroy.argtypes = [vp]
         L.ace_batch_destroy.restype = None
         L.ace_set_timing.argtypes = [C.c_int]
+        L.ace_set_block_trace.argtypes = [vp, u64]
         L.ace_last_timings.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.ace_plan_bytes.argtypes = [vp, u64p]
         L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
@@ -175,6 +177,16 @@ def stream_table(data) -> dict:
 
 def set_timing(on: bool):
     _check(lib().ace_set_timing(1 if on else 0))
+
+
+def set_block_trace(trace=None):
+    """Per-block clock trace of this thread's later decodes into `trace` (a
+    device uint8/int64 tensor, 64 bytes per planned block); None turns it off."""
+    if trace is None:
+        _check(lib().ace_set_block_trace(None, 0))
+    else:
+        _check(lib().ace_set_block_trace(C.c_void_p(trace.data_ptr()),
+                                         trace.numel() * trace.element_size()))
 
 
 def last_timings():

@@ -64,6 +64,10 @@ struct DecodeArgs {
   // memory (null for host-planned calls)
   const uint32_t* n_plan_dev;
   const uint32_t* lvl_dev;
+  // per-block clock trace (null: off): eight u64 per plan entry, the 100 MHz
+  // device clock at the start and end of its expansion and of each of its
+  // three entropy streams
+  unsigned long long* trace;
 };
 
 // Device-side planning of a batch of seeks (captured once in a HIP graph).

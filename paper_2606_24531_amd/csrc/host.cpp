@@ -247,6 +247,9 @@ struct PhaseTimer {
   bool recorded = false;
 };
 thread_local PhaseTimer g_timer;
+// per-block clock trace of this thread's decodes (null: off)
+thread_local unsigned long long* g_trace = nullptr;
+thread_local uint64_t g_trace_entries = 0;
 
 hipError_t timer_pair(std::vector<hipEvent_t>& v, size_t k) {
   while (v.size() < 2 * (k + 1)) {
@@ -428,6 +431,12 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.done = reinterpret_cast<uint32_t*>(ws + L.done);
   a.epoch = 1;
   a.wait_ticks = 10000000ull;  // 100 ms
+  if (g_trace) {
+    if (g_trace_entries < n_plan)
+      return fail(ACE_E_NOSPACE, "the block trace holds %llu entries, the decode plans %llu",
+                  (unsigned long long)g_trace_entries, (unsigned long long)n_plan);
+    a.trace = g_trace;
+  }
   if (n_plan && !resident) HIP_TRY(hipMemcpyAsync(ws + L.plan, entries, sizeof(PlanEntry) * n_plan,
                                      hipMemcpyHostToDevice, s));
   if (n_items) HIP_TRY(hipMemcpyAsync(ws + L.items, items, sizeof(CopyItem) * n_items,
@@ -984,6 +993,13 @@ extern "C" int ace_batch_run(ace_batch* b, const ace_range* r, uint32_t n, uint8
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   HIP_TRY(hipEventRecord(b->done, b->stream));
   b->pending = true;
+  return ACE_OK;
+}
+
+extern "C" int ace_set_block_trace(void* d_trace, uint64_t bytes) {
+  if (d_trace && bytes < 64) return fail(ACE_E_NOSPACE, "a block trace needs 64 bytes per planned block");
+  g_trace = static_cast<unsigned long long*>(d_trace);
+  g_trace_entries = d_trace ? bytes / 64 : 0;
   return ACE_OK;
 }
 

@@ -22,7 +22,14 @@ constexpr uint32_t kWave = 64;
 // the vector-memory counter; through a generic pointer they are flat
 // instructions, which also count against the LDS counter, so that a wait for
 // an LDS result would also wait for every load and store still in flight.
+#ifndef ACE_GLOBAL
 #define ACE_GLOBAL __attribute__((address_space(1)))
+#endif
+// An empty asm that makes the compiler treat x as changed (keeps a value
+// computed for every lane instead of under a branch).
+#ifndef ACE_OPAQUE
+#define ACE_OPAQUE(x) __asm__ volatile("" : "+v"(x))
+#endif
 template <typename T>
 __device__ __forceinline__ ACE_GLOBAL T* gp(T* p) {
   return (ACE_GLOBAL T*)p;
@@ -284,7 +291,7 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
     const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
     const uint32_t pos = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(G == 64 || h == 0 ? mlo : 0u, rp));
     uint32_t wd = ring16[(pos & (2 * kChunkW - 1))];
-    __asm__ volatile("" : "+v"(wd));  // read for every lane: keeps the update branch-free
+    ACE_OPAQUE(wd);  // read for every lane: keeps the update branch-free
     const uint32_t xa = (kAll || act) ? xn : x;
     x = need ? ((xn << 16) | wd) : xa;
     rp += (uint32_t)(G == 64 ? __popcll(m) : __popc(h ? mhi : mlo));
@@ -363,7 +370,12 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
                : t == 1 ? a.lens + 4ull * seq_base
                         : a.offs + (uint64_t)a.ow * seq_base;
   const uint8_t* src = a.arch + pay + off;
+  const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
   if (rans_decode_group<G>(src, clen, n, a.W, dst, sm[h], g, h, on) && g == 0) flag(a.err, kErrCorrupt);
+  if (a.trace && on && g == 0) {
+    a.trace[8ull * i + 2 + 2 * t] = c0;
+    a.trace[8ull * i + 3 + 2 * t] = (unsigned long long)wall_clock64();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1217,7 +1229,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     i = a.lvl_dev[level] + blockIdx.x;
     if (i >= a.lvl_dev[level + 1]) return;
   }
+  const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
   expand_block<kThreads>(a, i, sm);
+  if (a.trace && threadIdx.x == 0) {
+    a.trace[8ull * i] = c0;
+    a.trace[8ull * i + 1] = (unsigned long long)wall_clock64();
+  }
 }
 
 // ---------------------------------------------------------------------------

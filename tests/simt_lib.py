@@ -1,0 +1,110 @@
+"""Driver for the CPU build of libaceseek (tests/simt): the library's own
+kernels and host code, executed lane by lane on the host, with numpy arrays
+standing in for device memory.  Test infrastructure only."""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "simt"))
+
+ARCH_PAD = 4096
+_lib = None
+
+
+class Tuning(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in ("waves_per_block", "blocks_per_wg", "lut_variant",
+                                          "grid_wgs", "mode")]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("SIMT_LIB")
+        if not path:
+            import build as simt_build
+            path = simt_build.build()
+        L = C.CDLL(path)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        u64p, u32p = C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
+        L.ace_last_error.restype = C.c_char_p
+        L.ace_archive_open.argtypes = [vp, u64, vp, C.POINTER(vp)]
+        L.ace_archive_close.argtypes = [vp]
+        L.ace_archive_close.restype = None
+        L.ace_archive_info.argtypes = [vp, u64p, u32p, u32p, u32p]
+        L.ace_workspace_bytes.argtypes = [vp, vp, u32, u64p]
+        L.ace_decode_all.argtypes = [vp, vp, u64, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_seek.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_seek_batch.argtypes = [vp, vp, u32, vp, vp, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_check.argtypes = [vp, vp]
+        L.ace_read_counters.argtypes = [vp, vp, u64p]
+        _lib = L
+    return _lib
+
+
+class AceError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("aceseek (cpu build) error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc:
+        raise AceError(rc, lib().ace_last_error().decode(errors="replace"))
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Archive:
+    """An archive opened by the CPU build: host arrays play device memory."""
+
+    def __init__(self, data: bytes):
+        self.host = np.frombuffer(data, dtype=np.uint8)
+        self.dev = np.zeros(len(data) + ARCH_PAD, dtype=np.uint8)
+        self.dev[:len(data)] = self.host
+        h = C.c_void_p()
+        _check(lib().ace_archive_open(_p(self.host), len(data), _p(self.dev), C.byref(h)))
+        self._h = h
+        n, B, nb, depth = C.c_uint64(0), C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
+        _check(lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)))
+        self.n_total, self.block_size, self.n_blocks, self.depth = n.value, B.value, nb.value, depth.value
+
+    def close(self):
+        if self._h:
+            lib().ace_archive_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, ranges=None):
+        b = C.c_uint64(0)
+        if ranges is None:
+            _check(lib().ace_workspace_bytes(self._h, None, 0, C.byref(b)))
+        else:
+            r = np.ascontiguousarray(np.asarray(ranges, dtype=np.uint64).reshape(-1))
+            _check(lib().ace_workspace_bytes(self._h, _p(r), len(r) // 2, C.byref(b)))
+        return np.zeros(max(b.value, 256), dtype=np.uint8)
+
+    def decode_all(self, tuning=None):
+        out = np.zeros(max(self.n_total, 1), dtype=np.uint8)
+        ws = self.workspace()
+        t = C.byref(Tuning(**tuning)) if tuning else None
+        _check(lib().ace_decode_all(self._h, _p(out), self.n_total, _p(ws), ws.size, t, None))
+        _check(lib().ace_check(_p(ws), None))
+        return out[:self.n_total].tobytes()
+
+    def seek(self, lo, hi, tuning=None):
+        out = np.zeros(max(hi - lo, 1), dtype=np.uint8)
+        ws = self.workspace([lo, hi])
+        t = C.byref(Tuning(**tuning)) if tuning else None
+        _check(lib().ace_seek(self._h, lo, hi, _p(out), _p(ws), ws.size, t, None))
+        _check(lib().ace_check(_p(ws), None))
+        return out[:hi - lo].tobytes()
