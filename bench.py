@@ -1,22 +1,25 @@
 """Benchmark: two-layer (rANS + absolute-offset match) full-archive decode.
 
-Workload: 256 MiB of seeded synthetic FASTQ-like records, 16 KiB blocks,
-interleaved rANS with 12-bit frequencies (the interleave width W and the
-launch shape picked by the autotuner on a 32 MiB sample unless given),
-encoded on the host by the library encoder; the archive is resident in HBM
-before timing starts.  One
-step = one whole-archive decode through both layers (every step of the
-hot path).  Prints one JSON line.
+Default workload: 1 GiB of the seeded synthetic mixed corpus (64 KiB chunks of
+the genome, FASTQ-like, text and random profiles in shuffled order), 16 KiB
+blocks, level cap 16, interleaved rANS with 12-bit frequencies (the interleave
+width W and the launch shape picked by the autotuner on a 32 MiB sample
+unless given), encoded on the host by the library encoder; the archive is
+resident in HBM before timing starts.  One step = one whole-archive decode
+through both layers (every step of the hot path).  Prints one JSON line.
 
-Also reported: the roofline of the decode against MI355X HBM peak
-(algorithmic bytes = archive + output + match bytes read from earlier
-blocks), the CPU oracle's decode rate on this host, and seek latency
-(p50/p99) of single seeks, one launch sequence per seek, against the same
-requests decoded as one batch.
+Also reported on the same line: the decode's bytes against the MI355X HBM
+roofline (algorithmic bytes = archive + output + match bytes read from
+earlier blocks), per kernel and for the whole path; the same corpus at 64 KiB
+blocks and uncapped; 100,000 seeks (length log-uniform 1 B..4 MiB) decoded as
+one replayed batch graph against one seek call per request; and the CPU
+oracle's decode rate on this host's cores.
 """
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -30,7 +33,7 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "decode_fastq256_hbm_counters.txt")
+PROFILES_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_24531_amd", "csrc", "kernels.hip")
 
 
@@ -42,22 +45,81 @@ def kernel_source_sha256() -> str:
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per step moved by `kernel`'s launches, from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary (already scaled by the copy-kernel
-    calibration there), or None when that summary was taken on another
-    workload or on a kernel source other than the one built now."""
+    FETCH_SIZE / WRITE_SIZE counter summary of this workload (scaled by the
+    calibration kernels recorded there), or None when no summary was taken on
+    this workload with the kernel source built now."""
+    if not os.path.isdir(PROFILES_DIR):
+        return None
+    sha = kernel_source_sha256()
+    for fn in sorted(os.listdir(PROFILES_DIR)):
+        if not fn.endswith("_hbm_counters.txt"):
+            continue
+        kv = {}
+        for ln in open(os.path.join(PROFILES_DIR, fn)).read().splitlines():
+            if ln.startswith("@ ") and ":" in ln:
+                k, v = ln[2:].split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") == sha and kv.get("workload") == workload:
+            v = kv.get("hbm_bytes_per_step " + kernel)
+            return int(v) if v is not None else None
+    return None
+
+
+def cpu_facts() -> dict:
+    model = ""
     try:
-        lines = open(COUNTERS).read().splitlines()
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
     except OSError:
-        return None
-    kv = {}
-    for ln in lines:
-        if ln.startswith("@ ") and ":" in ln:
-            k, v = ln[2:].split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_sha256() or kv.get("workload") != workload:
-        return None
-    v = kv.get("hbm_bytes_per_step " + kernel)
-    return int(v) if v is not None else None
+        pass
+    try:
+        cc = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        cc = "gcc"
+    return {"cpu_model": model or platform.processor(), "host_threads": os.cpu_count(), "compiler": cc}
+
+
+def _time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def decode_entry(arc, a, x_dev, tuning, steps, warmup, label):
+    """Decode timing and facts of one archive (checked against the original
+    bytes on the device first)."""
+    import torch
+    from paper_2606_24531_amd import aceseek as ace
+    out = torch.empty(arc.n_total, dtype=torch.uint8, device=arc.device)
+    ws = arc.workspace(arc.workspace_bytes())
+    stream = torch.cuda.current_stream()
+    arc.read_counters(ws)
+    arc.decode_all(out=out, ws=ws, tuning=tuning)
+    arc.check(ws)
+    ext = arc.read_counters(ws)["ext_src_bytes"]
+    ok = bool(torch.equal(out, x_dev))
+    if not ok:
+        _log("%s: DECODE MISMATCH" % label)
+        sys.exit(1)
+    ms = _time_steps(lambda: arc.decode_all(out=out, ws=ws, tuning=tuning), steps, warmup, stream)
+    arc.check(ws)
+    facts = ace.archive_facts(a)
+    st = ace.stream_table(a)
+    raw_in_place = sum(v["raw"] - v["rans_raw"] for v in st.values())   # streams stored raw
+    coded = sum(v["rans_stored"] for v in st.values())
+    return dict(ms=ms, ext=ext, ok=ok, facts=facts, raw_in_place=raw_in_place, coded=coded,
+                rans_decoded=sum(v["rans_raw"] for v in st.values()), out=out, ws=ws)
 
 
 def main():
@@ -65,14 +127,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--profile", default="fastq")
-    ap.add_argument("--size", type=int, default=256 << 20)
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--profile", default="mixed")
+    ap.add_argument("--size", type=int, default=1 << 30)
+    ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--block", type=int, default=16384)
     ap.add_argument("--interleave", type=int, default=0,
                     help="rANS interleave width W; 0 = pick W and the launch shape with the "
                          "autotuner on a 32 MiB sample of the workload")
-    ap.add_argument("--min-match", type=int, default=20)
+    ap.add_argument("--min-match", type=int, default=16)
     ap.add_argument("--max-level", type=int, default=16)
     ap.add_argument("--mode", type=int, default=1,
                     help="1: entropy decode of all blocks, then one expansion launch per level, "
@@ -82,9 +144,13 @@ def main():
                     help="wavefronts per block in the match expansion (1, 2, 4, 8; 0 = chosen per launch by its size)")
     ap.add_argument("--per-wave", type=int, default=0,
                     help="entropy streams per wavefront (1, or 2 when W <= 32; 0 = library default)")
-    ap.add_argument("--seek-requests", type=int, default=2000)
+    ap.add_argument("--seek-requests", type=int, default=100_000)
+    ap.add_argument("--plain-requests", type=int, default=2000,
+                    help="requests timed one seek call each (the first ones of the same list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seek", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 64 KiB-block and uncapped archives of the same corpus")
     ap.add_argument("--serve", action="store_true",
                     help="instead of the decode benchmark, run the serving loop: resident "
                          "genome/FASTQ/text/mixed archives, Poisson arrivals swept over rates")
@@ -98,13 +164,10 @@ def main():
     ap.add_argument("--suite", default="",
                     help="instead of the headline decode, run the other workloads and print one "
                          "JSON line each: genome1m (1 MiB genome, decode + every block sought with "
-                         "the three-phase check), mixed1g (1 GiB mixed, 16 and 64 KiB blocks, DAG "
-                         "facts), mixed1g-uncapped (the same archive uncapped: depth and ratio only), "
-                         "seeks100k (100k seeks on the 1 GiB mixed 16 KiB archive: one graph replay "
-                         "vs one launch per seek)")
-    ap.add_argument("--calib-copy", type=int, default=0,
-                    help="also run one device copy of this many MiB (a known-size kernel "
-                         "for scaling hardware byte counters)")
+                         "the three-phase check), fastq256 (256 MiB FASTQ, 16 KiB blocks, cap 16)")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run the byte-counter calibration kernels (a 256 MiB fill: known "
+                         "bytes written; a 256 MiB sum: known bytes read) after the decode")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -117,15 +180,18 @@ def main():
 
     import gen
     from paper_2606_24531_amd import Archive, encode
+    from paper_2606_24531_amd import aceseek as ace
 
     dev = torch.device("cuda:0")
     if args.serve:
         return serve_main(args)
     if args.suite:
         return suite_main(args)
+    os.environ.setdefault("ACESEEK_ENCODE_PROGRESS", "0")
     t0 = time.time()
     x = gen.by_name(args.profile, args.size, args.seed)
     _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
+    x_dev = torch.from_numpy(np.frombuffer(x, dtype=np.uint8).copy()).to(dev)
     tuned = None
     if args.interleave == 0:
         from paper_2606_24531_amd.autotune import tune
@@ -139,83 +205,66 @@ def main():
             args.per_wave = tuned["blocks_per_wg"]
         _log("autotune (%.1fs): W=%d, %s waves per block, %d streams per wave" % (
             time.time() - t0, args.interleave, args.waves_per_block or "auto", args.per_wave))
+    enc = dict(interleave=args.interleave, min_match=args.min_match, hash_len=args.min_match, max_chain=32)
     t0 = time.time()
-    a = encode(x, block_size=args.block, interleave=args.interleave, min_match=args.min_match,
-               hash_len=args.min_match, max_chain=32, max_level=args.max_level)
-    _log("encoded to %d bytes (ratio %.3f) in %.1fs" % (len(a), len(x) / len(a), time.time() - t0))
-
+    a = encode(x, block_size=args.block, max_level=args.max_level, **enc)
+    enc_s = time.time() - t0
+    _log("encoded to %d bytes (ratio %.3f) in %.1fs" % (len(a), len(x) / len(a), enc_s))
     arc = Archive(a, device=dev)
-    ws = arc.workspace(arc.workspace_bytes())
-    out = torch.empty(arc.n_total, dtype=torch.uint8, device=dev)
     tuning = dict(mode=args.mode, waves_per_block=args.waves_per_block, blocks_per_wg=args.per_wave)
     stream = torch.cuda.current_stream()
-
-    # untimed: one decode checked against the original bytes, and its
-    # external-source byte count
-    arc.read_counters()
-    arc.decode_all(out=out, ws=ws, tuning=tuning)
-    arc.check()
-    ext = arc.read_counters()["ext_src_bytes"]
-    ok = bytes(out.cpu().numpy()) == x
-    if not ok:
-        _log("DECODE MISMATCH")
-        sys.exit(1)
-    _log("parity ok; depth %d, %d blocks, external source bytes %d" % (arc.depth, arc.n_blocks, ext))
-
-    for _ in range(args.warmup):
-        arc.decode_all(out=out, ws=ws, tuning=tuning)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        arc.decode_all(out=out, ws=ws, tuning=tuning)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    arc.check()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    d = decode_entry(arc, a, x_dev, tuning, args.steps, args.warmup, "headline")
+    ms, ext = d["ms"], d["ext"]
     gbs = len(x) / (ms * 1e-3) / 1e9
     alg_bytes = len(a) + len(x) + ext
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    _log("decode %.3f ms/step, %.1f GB/s decompressed, %.1f GB/s algorithmic" % (ms, gbs, achieved))
+    _log("parity ok; depth %d, %d blocks, external source bytes %d" % (arc.depth, arc.n_blocks, ext))
+    _log("decode %.3f ms/step, %.1f GB/s decompressed, %.1f GB/s of algorithmic bytes (%.1f%% of HBM peak)" % (
+        ms, gbs, achieved, 100 * achieved / HBM_PEAK_GBS))
 
-    # per-phase durations from HIP events recorded by the library on this
-    # stream around the entropy launch and the expansion launches
-    from paper_2606_24531_amd import aceseek as _ace
-    facts = _ace.archive_facts(a)
-    _ace.set_timing(True)
+    # per-kernel durations from HIP events the library records on this stream
+    # around the entropy launch and the expansion launches
+    ace.set_timing(True)
     t_ent, t_mat = [], []
     for _ in range(args.steps):
-        arc.decode_all(out=out, ws=ws, tuning=tuning)
-        e, m = _ace.last_timings()
+        arc.decode_all(out=d["out"], ws=d["ws"], tuning=tuning)
+        e, m = ace.last_timings()
         t_ent.append(e)
         t_mat.append(m)
-    _ace.set_timing(False)
+    ace.set_timing(False)
     ms_ent, ms_mat = float(np.mean(t_ent)), float(np.mean(t_mat))
-    tok = facts["token_bytes"]
-    # the entropy kernel reads the rANS-coded streams and writes their decoded
-    # bytes; streams stored raw are read in place by the expansion
-    st = _ace.stream_table(a)
-    rans_io = sum(v["rans_raw"] + v["rans_stored"] for v in st.values())
+    tok = d["facts"]["token_bytes"]
+    # Each kernel's share of the decode's algorithmic bytes: k_rans reads the
+    # rANS-coded streams; k_expand writes the output, reads the match bytes of
+    # earlier blocks and the streams stored raw (in place).  The decoded
+    # streams k_rans writes and k_expand reads back are an intermediate of
+    # this design, counted apart as overhead.
+    share_exp = len(x) + ext + d["raw_in_place"]
+    share_ent = d["coded"]
     phase = {
         "entropy": {"kernel": "k_rans", "launches_per_step": arc.depth if args.mode == 3 else 1,
-                    "ms": round(ms_ent, 4),
-                    "alg_bytes": rans_io},
+                    "ms": round(ms_ent, 4), "alg_bytes": share_ent,
+                    "achieved_GBs": round(share_ent / (ms_ent * 1e-3) / 1e9, 2),
+                    "overhead_bytes_written": d["rans_decoded"]},
         "match": {"kernel": "k_expand", "launches_per_step": arc.depth, "ms": round(ms_mat, 4),
-                  "alg_bytes": tok + ext + len(x)},
+                  "alg_bytes": share_exp,
+                  "achieved_GBs": round(share_exp / (ms_mat * 1e-3) / 1e9, 2),
+                  "overhead_bytes_read": d["rans_decoded"]},
     }
     dom = max(phase, key=lambda k: phase[k]["ms"])
     _log("phases: entropy %.3f ms, match %.3f ms (dominant: %s)" % (ms_ent, ms_mat, dom))
 
-    if args.calib_copy:
-        src = torch.empty(args.calib_copy << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+    if args.calib:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        src.fill_(1)      # 256 MiB written with 16-byte stores
         torch.cuda.synchronize()
-        _log("calibration copy of %d MiB done" % args.calib_copy)
+        _ = src.view(torch.int32).sum()  # 256 MiB read
+        torch.cuda.synchronize()
+        _log("calibration fill and sum of 256 MiB done")
 
     workload = "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
         args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level)
+    dk = phase[dom]
     result = {
         "metric": "2-layer decode GB/s (full archive)",
         "value": round(gbs, 2),
@@ -236,18 +285,18 @@ def main():
             "max_level": args.max_level, "depth": arc.depth, "n_blocks": arc.n_blocks,
             "waves_per_block": args.waves_per_block or "auto",
             "streams_per_wave": args.per_wave or (2 if args.interleave <= 32 else 1),
-            "autotuned": tuned is not None,
-            "mode": {1: "per-level launches, one stream",
+            "autotuned": tuned is not None, "encode_s": round(enc_s, 1),
+            "dag": _dag_facts(a),
+            "mode": {1: "entropy launch, then one expansion launch per level, one stream",
                      3: "per-level launches, entropy overlapped on a second stream"}[args.mode],
         },
         "roofline": {
-            "bound": "hbm", "kernel": phase[dom]["kernel"],
-            "achieved": round(phase[dom]["alg_bytes"] / (phase[dom]["ms"] * 1e-3) / 1e9, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(phase[dom]["alg_bytes"] / (phase[dom]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(phase[dom]["kernel"], workload),
+            "bound": "hbm", "kernel": dk["kernel"],
+            "achieved": dk["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dk["kernel"], workload),
             "traffic_unit": "HBM bytes per step (all launches of the kernel)",
-            "alg_bytes_per_launch_sequence": phase[dom]["alg_bytes"],
+            "alg_bytes_per_step": dk["alg_bytes"],
             "phases": phase,
             "path": {"alg_bytes_per_step": alg_bytes, "achieved": round(achieved, 2),
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -256,64 +305,126 @@ def main():
         },
     }
 
+    return finish(args, result, x, x_dev, a, arc, tuning, enc, d)
+
+
+def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
+    """The rest of the default line: the same corpus at 64 KiB blocks and
+    uncapped, the batched-vs-plain seeks, and the CPU oracle baseline."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2606_24531_amd import Archive, encode
+
+    dev = x_dev.device
+    if not args.no_extras:
+        extras = {}
+        for key, B, cap, steps in (("blocks_64k", 65536, args.max_level, args.steps),
+                                   ("uncapped", args.block, 0, 3)):
+            t0 = time.time()
+            ax = encode(x, block_size=B, max_level=cap, **enc)
+            enc_s = time.time() - t0
+            arcx = Archive(ax, device=dev)
+            e = decode_entry(arcx, ax, x_dev, tuning, steps, 1, key)
+            algx = len(ax) + len(x) + e["ext"]
+            extras[key] = {
+                "workload": "%s %d MiB, %d KiB blocks, %d-way rANS, %s" % (
+                    args.profile, len(x) >> 20, B >> 10, args.interleave,
+                    "level cap %d" % cap if cap else "uncapped"),
+                "ms_per_step": round(e["ms"], 4), "steps": steps,
+                "value": round(len(x) / (e["ms"] * 1e-3) / 1e9, 2), "unit": "GB/s",
+                "ratio": round(len(x) / len(ax), 4), "depth": arcx.depth, "n_blocks": arcx.n_blocks,
+                "path_frac": round(algx / (e["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "ext_src_bytes": e["ext"], "encode_s": round(enc_s, 1), "parity": e["ok"],
+                "dag": _dag_facts(ax)}
+            _log("%s: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s)" % (
+                key, len(x) / len(ax), arcx.depth, e["ms"], len(x) / e["ms"] / 1e6))
+            del e
+            arcx.close()
+            del ax
+            torch.cuda.empty_cache()
+        result["extras"] = extras
+
     if not args.no_seek:
-        rng = np.random.default_rng(4)
         n_req = args.seek_requests
         lo, hi = gen.seek_requests(len(x), n_req, 4, max_len=4 << 20)
-        lens = (hi - lo).astype(np.int64)
-        # plain: one seek call (its own launches) per request, waited on
-        wsz = max(arc.workspace_bytes([int(l), int(h)]) for l, h in zip(lo[:50], hi[:50]))
-        ws_seek = torch.zeros(max(wsz, arc.workspace_bytes()), dtype=torch.uint8, device=dev)
-        buf = torch.empty(int(lens.max()), dtype=torch.uint8, device=dev)
-        lat = []
-        for i in range(n_req):
-            t = time.perf_counter()
-            arc.seek(int(lo[i]), int(hi[i]), out=buf, ws=ws_seek, tuning=tuning)
-            torch.cuda.synchronize()
-            lat.append(time.perf_counter() - t)
-        arc.check(ws_seek)
-        plain_total = sum(lat)
-        # batched: all requests in one call
-        ws_b = torch.zeros(arc.workspace_bytes((lo, hi)), dtype=torch.uint8, device=dev)
-        outb = torch.empty(int(lens.sum()), dtype=torch.uint8, device=dev)
-        arc.seek_batch((lo, hi), out=outb, ws=ws_b, tuning=tuning)
+        ln = (hi - lo).astype(np.int64)
+        offs = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
+        total = int(ln.sum())
+        out = torch.empty(total, dtype=torch.uint8, device=dev)
+        # batched: every request in one replay of the captured batch graph
+        bt = arc.batch(n_req, tuning=tuning)
+        bt.run((lo, hi), out, offs)
         torch.cuda.synchronize()
+        bt.check()
+        good = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x_dev[int(lo[i]):int(hi[i])]))
+                   for i in range(n_req))
         times = []
         for _ in range(3):
             t = time.perf_counter()
-            arc.seek_batch((lo, hi), out=outb, ws=ws_b, tuning=tuning)
+            bt.run((lo, hi), out, offs)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
-        arc.check(ws_b)
-        bt = float(np.median(times))
+        bt.check()
+        bt.close()
+        tb = float(np.median(times))
+        # plain: one seek call (its own plan and launches) per request, waited
+        # on; the first plain_requests requests of the same list
+        n_plain = min(args.plain_requests, n_req)
+        ws = torch.zeros(arc.workspace_bytes([0, len(x)]), dtype=torch.uint8, device=dev)
+        lat = []
+        for i in range(n_plain):
+            t = time.perf_counter()
+            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+        arc.check(ws)
+        plain_ok = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x_dev[int(lo[i]):int(hi[i])]))
+                       for i in range(n_plain))
+        plain_rate = n_plain / sum(lat)
         result["seek"] = {
-            "requests": n_req, "len": "log-uniform 1 B..4 MiB", "bytes": int(lens.sum()),
+            "workload": "%d seeks on the resident archive, length log-uniform 1 B..4 MiB, uniform "
+                        "offsets (seed 4)" % n_req,
+            "requests": n_req, "output_bytes": total,
+            "batched_latency_ms": round(1e3 * tb, 4), "batched_req_per_s": round(n_req / tb, 1),
+            "batched_out_GBs": round(total / tb / 1e9, 2), "batched_outputs_equal_original": good,
+            "plain_requests_timed": n_plain,
             "plain_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 4),
             "plain_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
-            "plain_req_per_s": round(n_req / plain_total, 1),
-            "batched_latency_ms": round(1e3 * bt, 4),
-            "batched_req_per_s": round(n_req / bt, 1),
-            "batched_vs_plain_throughput": round(plain_total / bt, 2),
+            "plain_req_per_s": round(plain_rate, 1), "plain_outputs_equal_original": plain_ok,
+            "batched_vs_plain_throughput": round((n_req / tb) / plain_rate, 1),
         }
-        _log("seek: plain p50 %.3f ms p99 %.3f ms; batch of %d in %.3f ms" % (
-            result["seek"]["plain_p50_ms"], result["seek"]["plain_p99_ms"], n_req, 1e3 * bt))
+        _log("seek: batch of %d in %.3f ms (%.0f req/s, all outputs equal: %s); plain p50 %.3f ms "
+             "p99 %.3f ms (%.0f req/s)" % (n_req, 1e3 * tb, n_req / tb, good, result["seek"]["plain_p50_ms"],
+                                           result["seek"]["plain_p99_ms"], plain_rate))
+        del out
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
-        reps, t_total = 0, 0.0
-        while reps < 5 and t_total < 12.0:
-            t = time.perf_counter()
-            y = oracle.decode(a)
-            t_total += time.perf_counter() - t
-            reps += 1
+        t = time.perf_counter()
+        y, used = oracle.decode_levels(a, 0)
+        t_all = time.perf_counter() - t
         assert y == x
-        result["cpu_baseline"] = {
-            "value": round(len(x) * reps / t_total / 1e9, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d full sequential decode(s) of the same %d MiB archive" % (reps, len(x) >> 20),
-        }
-        _log("cpu oracle %.3f GB/s" % result["cpu_baseline"]["value"])
+        del y
+        # one core: the sequential decoder on the first quarter of the
+        # archive's blocks would need a second archive; it decodes the whole
+        # archive once instead (bounded: about 5 s at 0.2 GB/s)
+        t = time.perf_counter()
+        y1 = oracle.decode(a)
+        t_one = time.perf_counter() - t
+        assert y1 == x
+        del y1
+        result["cpu_baseline"] = dict({
+            "value": round(len(x) / t_all / 1e9, 4), "unit": "GB/s", "cores": used, "kind": "oracle",
+            "sample": "one full decode of the same archive, the blocks of each dependency level "
+                      "decoded in parallel (OpenMP)",
+            "one_core_GBs": round(len(x) / t_one / 1e9, 4),
+            "oracle_flags": " ".join(oracle.CFLAGS)}, **cpu_facts())
+        _log("cpu oracle: %.3f GB/s on %d threads, %.3f GB/s on one" % (
+            result["cpu_baseline"]["value"], used, result["cpu_baseline"]["one_core_GBs"]))
 
     print(json.dumps(result), flush=True)
 
@@ -369,21 +480,36 @@ def serve_main(args):
 
 
 def _dag_facts(a: bytes) -> dict:
-    """Depth, level sizes, dependency out-degree and single-block closure sizes
-    read from an archive's index."""
+    """Depth, level sizes, dependency out-degree and single-block closure
+    sizes, read from an archive's index (closures by a frontier walk over the
+    dependency lists, which always point to lower levels)."""
     import struct
 
     import numpy as np
-
-    import oracle
     nb = struct.unpack_from("<I", a, 24)[0]
     depth = struct.unpack_from("<I", a, 28)[0]
+    n_deps = struct.unpack_from("<I", a, 36)[0]
     ent = np.frombuffer(a, dtype=np.uint32, count=8 * nb, offset=64).reshape(nb, 8)
-    level, dep_cnt = ent[:, 4], ent[:, 6]
-    oracle.build()
+    level, dep_off, dep_cnt = ent[:, 4], ent[:, 5].astype(np.int64), ent[:, 6].astype(np.int64)
+    deps = np.frombuffer(a, dtype=np.uint32, count=n_deps, offset=64 + 32 * nb)
+
+    def closure(b):
+        need = np.zeros(nb, dtype=bool)
+        need[b] = True
+        front = np.array([b], dtype=np.int64)
+        while front.size:
+            cnt, off = dep_cnt[front], dep_off[front]
+            if not cnt.sum():
+                break
+            start = np.repeat(off - (np.cumsum(cnt) - cnt), cnt)
+            d = deps[start + np.arange(cnt.sum())].astype(np.int64)
+            d = np.unique(d[~need[d]])
+            need[d] = True
+            front = d
+        return int(need.sum())
+
     rng = np.random.default_rng(7)
-    B = struct.unpack_from("<I", a, 8)[0]
-    clos = [len(oracle.closure(a, int(b) * B, int(b) * B + 1)) for b in rng.integers(0, nb, 100)]
+    clos = [closure(int(b)) for b in rng.integers(0, nb, 100)]
     return {"depth": int(depth), "n_blocks": int(nb),
             "level_sizes": np.bincount(level, minlength=depth).tolist()[:64],
             "deps_per_block_mean": round(float(dep_cnt.mean()), 2), "deps_per_block_max": int(dep_cnt.max()),
@@ -459,129 +585,23 @@ def suite_main(args):
               "parity": ok, "seek_p50_ms": round(1e3 * float(np.median(lat)), 4),
               "seek_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
               "three_phase_all_blocks": good})
-    arc16 = x3 = None
-    if which & {"mixed1g", "seeks100k", "mixed1g-uncapped"}:
-        t0 = time.time()
-        x3 = gen.mixed(1 << 30, 3)
-        _log("mixed1g: generated 1 GiB mixed in %.1fs" % (time.time() - t0))
-        x3d = torch.frombuffer(bytearray(x3), dtype=torch.uint8).to(dev)
-        for B in ((16384, 65536) if "mixed1g" in which else (16384,)):
-            tuned = tune(x3[:32 << 20], "mixed", block_size=B, min_match=16, max_level=16)
-            t0 = time.time()
-            a = encode(x3, block_size=B, interleave=tuned["interleave"], min_match=16, hash_len=16,
-                       max_chain=32, max_level=16)
-            enc_s = time.time() - t0
-            arc = Archive(a, device=dev)
-            shape = dict(mode=1, waves_per_block=tuned["waves_per_block"], blocks_per_wg=tuned["blocks_per_wg"])
-            if "mixed1g" in which:
-                ms, ok = _time_decode(arc, x3d, shape, 10)
-                facts = _dag_facts(a)
-                _log("mixed1g B=%d: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
-                    B, len(x3) / len(a), arc.depth, ms, len(x3) / ms / 1e6, ok))
-                emit({"metric": "2-layer decode GB/s (full archive)",
-                      "config": dict({"workload": "mixed 1 GiB, %d KiB blocks, %d-way rANS, level cap 16" % (
-                          B >> 10, tuned["interleave"]), "ratio": round(len(x3) / len(a), 4),
-                          "encode_s": round(enc_s, 1)}, **facts),
-                      "value": round(len(x3) / ms / 1e6, 2), "unit": "GB/s", "ms_per_step": round(ms, 4),
-                      "parity": ok, "tuning": shape})
-            if B == 16384:
-                arc16 = (arc, shape)
-            else:
-                arc.close()
-        if "mixed1g-uncapped" in which:
-            t0 = time.time()
-            au = encode(x3, block_size=16384, interleave=64, min_match=16, hash_len=16, max_chain=32,
-                        max_level=0)
-            facts = _dag_facts(au)
-            emit({"metric": "DAG depth and ratio without a level cap",
-                  "config": dict({"workload": "mixed 1 GiB, 16 KiB blocks, 64-way rANS, uncapped",
-                                  "ratio": round(len(x3) / len(au), 4), "encode_s": round(time.time() - t0, 1)},
-                                 **facts)})
-            del au
-    if "seeks100k" in which:
-        arc, shape = arc16
-        n = len(x3)
-        rng = np.random.default_rng(4)
-        n_req = 100_000
-        ln = np.floor(np.exp(rng.uniform(0, np.log(4 << 20), n_req))).astype(np.int64)
-        lo = (rng.random(n_req) * (n - ln + 1)).astype(np.int64)
-        hi = lo + ln
-        total = int(ln.sum())
-        out = torch.empty(total, dtype=torch.uint8, device=dev)
-        offs = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
-        res = {}
-        for sub in (1000, 10_000, n_req):
-            bt = arc.batch(sub, tuning=shape)
-            rr = (lo[:sub].astype(np.uint64), hi[:sub].astype(np.uint64))
-            bt.run(rr, out, offs[:sub])
-            torch.cuda.synchronize()
-            bt.check()
-            times = []
-            for _ in range(3):
-                t = time.perf_counter()
-                bt.run(rr, out, offs[:sub])
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t)
-            bt.check()
-            tb = float(np.median(times))
-            res[sub] = {"latency_ms": round(1e3 * tb, 3), "req_per_s": round(sub / tb, 1),
-                        "out_GB_per_s": round(float(ln[:sub].sum()) / tb / 1e9, 2)}
-            _log("seeks100k batch %d: %.3f ms, %.0f req/s" % (sub, 1e3 * tb, sub / tb))
-            bt.close()
-        # every output of the full batch checked against the original bytes on
-        # a sample of requests
-        sample = rng.choice(n_req, 300, replace=False)
-        good = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x3d[int(lo[i]):int(hi[i])]))
-                   for i in sample)
-        # the lowest dependency levels kept decoded (ace_batch_pin): every
-        # closure stops there; outputs checked on the sample's first requests
-        kept = {}
-        for keep in (1, 2, arc.depth):
-            bt = arc.batch(10_000, tuning=shape)
-            t = time.perf_counter()
-            bt.pin(keep)
-            pin_s = time.perf_counter() - t
-            entry = {"pin_ms": round(1e3 * pin_s, 2)}
-            for sub in (1000, 10_000):
-                rr = (lo[:sub].astype(np.uint64), hi[:sub].astype(np.uint64))
-                out.zero_()
-                bt.run(rr, out, offs[:sub])
-                torch.cuda.synchronize()
-                bt.check()
-                ok = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])],
-                                          x3d[int(lo[i]):int(hi[i])])) for i in range(min(sub, 300)))
-                times = []
-                for _ in range(3):
-                    t = time.perf_counter()
-                    bt.run(rr, out, offs[:sub])
-                    torch.cuda.synchronize()
-                    times.append(time.perf_counter() - t)
-                tb = float(np.median(times))
-                entry[str(sub)] = {"latency_ms": round(1e3 * tb, 3), "req_per_s": round(sub / tb, 1),
-                                   "outputs_equal_original": ok}
-                _log("seeks100k kept levels %d, batch %d: %.3f ms (parity %s)" % (keep, sub, 1e3 * tb, ok))
-            bt.close()
-            kept[str(keep)] = entry
-        # plain: one seek call (its own launches) per request, waited on
-        ws = torch.zeros(arc.workspace_bytes([0, 1 << 30]), dtype=torch.uint8, device=dev)
-        lat = []
-        n_plain = 2000
-        for i in range(n_plain):
-            t = time.perf_counter()
-            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=shape)
-            torch.cuda.synchronize()
-            lat.append(time.perf_counter() - t)
-        arc.check(ws)
-        plain_rate = n_plain / sum(lat)
-        emit({"metric": "p50/p99 seek latency, batched vs plain",
-              "config": {"workload": "mixed 1 GiB resident, 16 KiB blocks; 100k seeks, length "
-                                     "log-uniform 1 B..4 MiB, uniform offsets (seed 4)",
-                         "requests": n_req, "output_bytes": total},
-              "batched": res, "sample_outputs_equal_original": good, "batched_with_kept_levels": kept,
-              "plain": {"requests_timed": n_plain, "p50_ms": round(1e3 * float(np.median(lat)), 4),
-                        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
-                        "req_per_s": round(plain_rate, 1)},
-              "batched_vs_plain_throughput": round(res[n_req]["req_per_s"] / plain_rate, 1)})
+    if "fastq256" in which:
+        # 256 MiB FASTQ-like records, 16 KiB blocks, cap 16 (the FASTQ profile alone)
+        x = gen.fastq(256 << 20, 2)
+        tuned = tune(x[:32 << 20], "fastq", block_size=16384, min_match=20, max_level=16)
+        a = encode(x, block_size=16384, interleave=tuned["interleave"], min_match=20, hash_len=20,
+                   max_chain=32, max_level=16)
+        arc = Archive(a, device=dev)
+        xd = torch.from_numpy(np.frombuffer(x, dtype=np.uint8).copy()).to(dev)
+        shape = dict(mode=1, waves_per_block=tuned["waves_per_block"], blocks_per_wg=tuned["blocks_per_wg"])
+        ms, ok = _time_decode(arc, xd, shape, 20)
+        _log("fastq256: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
+            len(x) / len(a), arc.depth, ms, len(x) / ms / 1e6, ok))
+        emit({"metric": "2-layer decode GB/s (full archive)",
+              "config": {"workload": "fastq 256 MiB, 16 KiB blocks, %d-way rANS, level cap 16" % tuned["interleave"],
+                         "ratio": round(len(x) / len(a), 4), "depth": arc.depth},
+              "value": round(len(x) / ms / 1e6, 2), "unit": "GB/s", "ms_per_step": round(ms, 4),
+              "parity": ok, "tuning": shape})
 
 
 if __name__ == "__main__":

@@ -6,8 +6,9 @@
  *
  * The paper's central operation is a seek: decode one absolute byte range
  * through both layers, in isolation (Sections 3 and 5).  Section 2 gives the
- * reason it is possible: offsets are absolute, so a block decodes as soon as
- * the blocks holding its source bytes are present, whatever path led there.
+ * reason it is possible: offsets are absolute, so a block can be decoded as
+ * soon as the earlier blocks its matches copy from are decoded, however the
+ * decoder reached it.
  * Section 7 adds range decoding of many blocks.
  *
  * Conventions
@@ -133,11 +134,17 @@ int ace_plan_bytes(const ace_archive* a, uint64_t* bytes);
 int ace_archive_attach_plan(ace_archive* a, void* d_plan, uint64_t bytes, void* stream);
 
 /* Workspace bytes needed to decode the given ranges (ranges == NULL and
- * n_ranges == 0: the whole archive). */
+ * n_ranges == 0: the whole archive): the plan, the location table, token
+ * scratch and the slots of blocks decoded only as sources of the ranges'
+ * dependency closure (Section 2: the blocks a range needs are the targets
+ * and, recursively, the earlier blocks their matches copy from). */
 int ace_workspace_bytes(const ace_archive* a, const ace_range* ranges, uint32_t n_ranges,
                         uint64_t* bytes);
 
-/* Whole-archive decode: writes n_total bytes at d_out (out_cap >= n_total). */
+/* Whole-archive decode (Section 2: every block, both layers, each after the
+ * earlier blocks it copies from; Section 7: decode of a whole block range):
+ * writes n_total bytes at d_out (out_cap >= n_total).  The workspace needs
+ * ace_workspace_bytes(a, NULL, 0) bytes. */
 int ace_decode_all(const ace_archive* a, uint8_t* d_out, uint64_t out_cap, void* d_ws,
                    uint64_t ws_cap, const ace_tuning* t, void* stream);
 
@@ -147,16 +154,19 @@ int ace_decode_all(const ace_archive* a, uint8_t* d_out, uint64_t out_cap, void*
 int ace_seek(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
              uint64_t ws_cap, const ace_tuning* t, void* stream);
 
-/* Batched seek: request i writes [lo_i, hi_i) at d_out + h_out_off[i].  All
+/* Batched seek: many seeks of Section 5 served together (Section 7: range
+ * decode of many blocks at once).  Request i writes [lo_i, hi_i) at d_out +
+ * h_out_off[i] (host arrays; the output ranges must not overlap).  All
  * requests share one dependency-ordered decode of the union of their
- * closures, then one gather. */
+ * closures, then one gather.  Errors as for ace_seek. */
 int ace_seek_batch(const ace_archive* a, const ace_range* h_ranges, uint32_t n,
                    uint8_t* d_out, const uint64_t* h_out_off, void* d_ws, uint64_t ws_cap,
                    const ace_tuning* t, void* stream);
 
 /* Waits for the stream, reads and clears the workspace's sticky device error
- * word: ACE_OK, ACE_E_CORRUPT (a token stream broke a format rule) or
- * ACE_E_TIMEOUT (a bounded dependency wait expired). */
+ * word: ACE_OK, ACE_E_CORRUPT (a token stream broke one of the format rules
+ * of Section 2's token grammar as this library reads it) or ACE_E_TIMEOUT (a
+ * bounded dependency wait expired). */
 int ace_check(void* d_ws, void* stream);
 
 /* ---- batched seek as one replayed HIP graph ----

@@ -11,7 +11,8 @@
  * archive stores (dependency lists, levels, depth) is recomputed from the
  * tokens and compared.  A seek of [lo, hi) is decode_all(A)[lo:hi]; the
  * closure helper lists the blocks the paper's isolated seek needs (Section 3:
- * a block decodes once the blocks holding its source bytes are present).
+ * with absolute offsets a block needs only the earlier blocks its matches
+ * copy from, not the whole prefix).
  */
 #include <omp.h>
 #include <stdlib.h>
@@ -350,8 +351,9 @@ int orc_block_tokens(const uint8_t* a, uint64_t len, uint32_t block, uint8_t* li
 
 /* Whole-archive decode with the blocks of one dependency level decoded in
  * parallel (OpenMP), levels in increasing order: a block's dependencies all
- * sit at lower levels (Section 2: a block decodes once the blocks holding
- * its sources are present), so the blocks of one level are independent.
+ * sit at lower levels (Section 2: with absolute offsets a block can be
+ * decoded as soon as the earlier blocks it copies from are decoded), so the
+ * blocks of one level are independent.
  * Each block goes through the same decode_block as the sequential decoder.
  * This is the all-cores CPU baseline, not a second definition of decode: on
  * any error the sequential decoder is run to report it. */

@@ -8,8 +8,9 @@
  * What it follows:
  *  - Match layer: LZ77 whose back-references are absolute positions in the
  *    decompressed output, found by a global search, with the output cut into
- *    fixed-size blocks; a block decodes once the blocks holding its sources
- *    are present (paper Section 2).
+ *    fixed-size blocks; since every match names an absolute position, a
+ *    block can be decoded as soon as each earlier block its matches copy
+ *    from is decoded (paper Section 2).
  *  - Entropy layer: per-block, per-stream rANS (Duda) interleaved over W
  *    states (Giesen), applied to each block on its own so that every block
  *    is an entry point (paper Sections 3 and 9).

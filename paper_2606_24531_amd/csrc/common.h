@@ -56,12 +56,16 @@ struct DecodeArgs {
   uint32_t* err;   // sticky error word
   unsigned long long* ext_bytes;  // counter: match bytes read from earlier blocks
   // persistent-kernel state
-  uint32_t* queue;      // work counter
-  uint32_t* done;       // per-block completion epochs
+  uint32_t* queue;      // entropy decodes claimed (plan entries, in plan order)
+  uint32_t* done;       // per plan entry: == epoch once its streams are decoded
   uint32_t epoch;
-  uint64_t wait_ticks;  // bound of one dependency wait, in 100 MHz clock ticks
-  // device-planned batches: plan length and level boundaries live in device
-  // memory (null for host-planned calls)
+  uint32_t n_lvl;       // dependency levels of the plan (bounds in lvl_dev)
+  uint32_t* lvl_claim;  // per level: expansions claimed
+  uint32_t* lvl_done;   // per level: expansions finished
+  uint32_t max_polls;   // consecutive idle polls before a wait gives up
+  // plan length (device-planned batches; null for host-planned calls) and
+  // level boundaries in device memory (device-planned batches and the
+  // persistent kernel)
   const uint32_t* n_plan_dev;
   const uint32_t* lvl_dev;
   // per-block clock trace (null: off): eight u64 per plan entry, the 100 MHz
@@ -97,6 +101,8 @@ struct BatchArgs {
 hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s);
 hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi, uint32_t waves,
                                hipStream_t s);
+// the persistent level-by-level decode (kernel (c)); grid 0 = as many
+// workgroups as the device holds at once
 hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,
                        hipStream_t s);

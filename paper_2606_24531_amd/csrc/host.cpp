@@ -3,8 +3,8 @@
 //
 // Planner (paper Sections 2, 3, 5 and 7).  A range [lo, hi) names target
 // blocks floor(lo/B) .. floor((hi-1)/B).  Because every back-reference is an
-// absolute position, a block can be decoded as soon as the blocks holding its
-// source bytes are present; the index lists those blocks for each block, so
+// absolute position, a block can be decoded as soon as every earlier block
+// its matches copy from is decoded; the index lists those blocks per block, so
 // the set of blocks a seek needs is the closure of the targets under that
 // relation, and a valid order is by increasing dependency level.  Target
 // blocks that the range covers whole are decoded straight into the caller's
@@ -325,16 +325,24 @@ size_t level_split(const std::vector<uint32_t>& lstart) {
   return split;
 }
 constexpr uint32_t kModePersistent = 2, kModeOverlap = 3;  // 0 and 1: per level, one stream
+// consecutive idle polls (each a sleep of about 1,000 cycles once idle for
+// a while) before a persistent-kernel wait gives up and flags a timeout:
+// about a second on this device
+constexpr uint32_t kMaxIdlePolls = 1u << 21;
 
 struct Layout {
-  uint64_t plan, loc, done, lit, lens, offs, slots, items, total;
+  uint64_t plan, lv, loc, done, lit, lens, offs, slots, items, total;
 };
 
+// Workspace of one host-planned decode.  lv: per dependency level of the
+// archive, the plan's level boundaries (depth + 1), then the persistent
+// kernel's claimed and finished counts (depth each).
 Layout layout(const ace_archive* A, uint64_t n_plan, uint64_t n_seq, uint64_t n_slots,
               uint64_t n_items) {
   Layout L;
   uint64_t o = kWsHeader;
   L.plan = o;  o = align_up(o + sizeof(PlanEntry) * n_plan, 256);
+  L.lv = o;    o = align_up(o + 4ull * (3ull * A->depth + 1), 256);
   L.loc = o;   o = align_up(o + 8ull * A->nb, 256);
   L.done = o;  o = align_up(o + 4ull * A->nb, 256);
   L.lit = o;   o = align_up(o + (uint64_t)A->B * n_plan + 64, 256);  // +64: aligned over-read slack
@@ -402,10 +410,7 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const PlanEntry* resident = nullptr) {
   (void)entries_pinned;
   const uint32_t mode = t ? t->mode : 0;
-  if (mode == kModePersistent)
-    return fail(ACE_E_ARG, "the persistent dependency-ordered kernel is disabled in this build: "
-                           "it did not complete on the GPU and its cause is not yet found");
-  if (mode > 1 && mode != kModeOverlap) return fail(ACE_E_ARG, "unknown mode %u", mode);
+  if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) return fail(ACE_E_ARG, "unknown mode %u", mode);
   int rc = check_tuning(A, t);
   if (rc) return rc;
   const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
@@ -430,7 +435,11 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.queue = reinterpret_cast<uint32_t*>(ws + 4);
   a.done = reinterpret_cast<uint32_t*>(ws + L.done);
   a.epoch = 1;
-  a.wait_ticks = 10000000ull;  // 100 ms
+  a.n_lvl = (uint32_t)(lstart.size() - 1);
+  a.lvl_dev = reinterpret_cast<const uint32_t*>(ws + L.lv);
+  a.lvl_claim = reinterpret_cast<uint32_t*>(ws + L.lv) + a.n_lvl + 1;
+  a.lvl_done = a.lvl_claim + a.n_lvl;
+  a.max_polls = kMaxIdlePolls;
   if (g_trace) {
     if (g_trace_entries < n_plan)
       return fail(ACE_E_NOSPACE, "the block trace holds %llu entries, the decode plans %llu",
@@ -469,7 +478,20 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
       if (r == hipSuccess && timed) r = hipEventRecord(T.ent[2 * T.n_ent++ + 1], st);
       return r;
     };
-    if (mode == kModeOverlap && nl > 1) {
+    if (mode == kModePersistent) {
+      // one launch: level boundaries uploaded, counters and flags cleared
+      // (fill kernels), then the persistent level-by-level decode
+      HIP_TRY(hipMemcpyAsync(ws + L.lv, lstart.data(), 4ull * lstart.size(), hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_fill_u32(a.lvl_claim, 0u, 2ull * a.n_lvl, s));
+      HIP_TRY(launch_fill_u32(a.done, 0u, n_plan, s));
+      HIP_TRY(launch_fill_u32(a.queue, 0u, 1, s));
+      if (timed) {
+        HIP_TRY(timer_pair(T.mat, T.n_mat));
+        HIP_TRY(hipEventRecord(T.mat[2 * T.n_mat], s));
+      }
+      HIP_TRY(launch_persistent(a, t ? t->grid_wgs : 0, s));
+      if (timed) HIP_TRY(hipEventRecord(T.mat[2 * T.n_mat++ + 1], s));
+    } else if (mode == kModeOverlap && nl > 1) {
       // fork: the late levels' entropy decode on the second stream; the
       // caller's stream decodes and expands the early levels meanwhile,
       // then waits for the late entropy decode and expands the rest
@@ -571,8 +593,11 @@ extern "C" int ace_archive_attach_plan(ace_archive* A, void* d_plan, uint64_t by
   return ACE_OK;
 }
 
-extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
-                        uint64_t ws_cap, const ace_tuning* t, void* stream) {
+// One seek: plan the closure of [lo, hi) on the host and decode it into the
+// workspace ws (whole target blocks straight into d_out).  ws_need, when
+// given, receives the workspace size the seek needs (also on ACE_E_NOSPACE).
+static int seek_impl(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+                     uint64_t ws_cap, const ace_tuning* t, void* stream, uint64_t* ws_need) {
   if (!A) return fail(ACE_E_ARG, "null archive");
   if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
                            (unsigned long long)hi);
@@ -605,6 +630,7 @@ extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t*
     items.push_back(CopyItem{s0, (uint64_t)(uintptr_t)d_out + (s0 - lo), (uint32_t)(s1 - s0), 0});
   }
   Layout L = layout(A, order.size(), seq, n_slots, items.size());
+  if (ws_need) *ws_need = L.total;
   if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   uint64_t slot = 0;
@@ -615,6 +641,11 @@ extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t*
   }
   return run(A, entries.data(), entries.size(), lstart, items.data(), items.size(), L, ws, 0, t,
              static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+                        uint64_t ws_cap, const ace_tuning* t, void* stream) {
+  return seek_impl(A, lo, hi, d_out, d_ws, ws_cap, t, stream, nullptr);
 }
 
 extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t n, uint8_t* d_out,
@@ -726,7 +757,7 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   L.pre = take(4ull * A->nb);
   L.plan = take(sizeof(PlanEntry) * A->nb);
   L.nplan = take(4);
-  L.lvl = take(4ull * (A->depth + 1));
+  L.lvl = take(4ull * (3ull * A->depth + 1));  // plan boundaries, then the persistent kernel's counts
   L.loc = take(8ull * A->nb);
   L.done = take(4ull * A->nb);
   L.lit = take((uint64_t)A->B * A->nb + 64);
@@ -842,15 +873,14 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.queue = reinterpret_cast<uint32_t*>(b->ws + 4);
     a.done = reinterpret_cast<uint32_t*>(b->ws + L.done);
     a.epoch = 1;
-    a.wait_ticks = 10000000ull;
     a.n_plan_dev = ba.n_plan_dev;
     a.lvl_dev = ba.lvl_dev;
+    a.n_lvl = A->depth;
+    a.lvl_claim = ba.lvl_dev + A->depth + 1;
+    a.lvl_done = a.lvl_claim + A->depth;
+    a.max_polls = kMaxIdlePolls;
     const uint32_t mode = t ? t->mode : 0;
-    if (mode == kModePersistent) {
-      rc = fail(ACE_E_ARG, "mode 2 is not available (the persistent kernel is disabled)");
-      break;
-    }
-    if (mode > 1 && mode != kModeOverlap) {
+    if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) {
       rc = fail(ACE_E_ARG, "unknown mode %u", mode);
       break;
     }
@@ -889,7 +919,10 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     for (uint32_t l = A->depth; e == hipSuccess && l-- > 1;)
       e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
     if (e == hipSuccess) e = launch_batch_compact(ba, s);
-    if (e == hipSuccess && overlap) {
+    if (e == hipSuccess && mode == kModePersistent) {
+      e = launch_fill_u32(a.lvl_claim, 0u, 2ull * A->depth, s);
+      if (e == hipSuccess) e = launch_persistent(a, t ? t->grid_wgs : 0, s);
+    } else if (e == hipSuccess && overlap) {
       const size_t split = level_split(A->all_levels);
       const uint32_t nl = A->depth;
       e = hipEventRecord(b->ev[0], s);

@@ -15,7 +15,6 @@
 namespace ace {
 namespace {
 
-constexpr uint32_t kWave = 64;
 
 // Device memory seen through the global address space.  Loads and stores
 // through these pointers are global instructions, which count only against
@@ -389,7 +388,8 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
 // [O_k, O_k + min(M_k, d_k)), which lies before the match.  Each span is
 // resolved to one address in memory whenever it can be:
 //   * inside one earlier block: that block's location (the block's
-//     dependency list and locations are cached in LDS once per block);
+//     dependency list is cached in LDS once per block; the location is
+//     computed in a whole-archive decode, else read from the location table);
 //   * inside an earlier tile of this block: the output itself;
 //   * inside this tile: pointer jumping over sequences.  A span inside a
 //     literal run resolves to the literal stream; a span inside one period
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPoison = 1u, kSlow = 2u, kPend = 4u, kExt = 8u;
 constexpr uint32_t kUnres = kPoison | kSlow | kPend;  // flags of a span without an address
-constexpr uint32_t kDepCache = 256;  // dependency locations cached in LDS per block
+constexpr uint32_t kDepCache = 896;  // dependency lists cached in LDS per block (longer: read from HBM)
 constexpr uint32_t kMaxJumps = 12;   // pointer-doubling rounds (chains up to 4096)
 
 template <uint32_t kThreads>
@@ -425,7 +425,6 @@ struct ExpandSmem {
   uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
   uint32_t deps[kDepCache];
-  uint64_t dloc[kDepCache];  // location of each cached dependency's first byte
   uint32_t scan[32];
 };
 
@@ -533,20 +532,18 @@ struct BlockCtx {
   bool ext_ok;
 };
 
-// Location of the first byte of earlier block blk (a listed dependency, so
-// usually in the LDS cache).
-template <uint32_t kThreads>
-__device__ __forceinline__ uint64_t dep_loc(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
-                                            uint32_t dep_cnt, uint64_t blk) {
-  const int di = dep_cnt <= kDepCache ? dep_index(sm.deps, dep_cnt, (uint32_t)blk) : -1;
-  return di >= 0 ? sm.dloc[di] : *gp(a.loc + blk);
+// Location of the first byte of earlier block blk: computed in a
+// whole-archive decode (blocks back to back in the output), else read from
+// the location table.
+__device__ __forceinline__ uint64_t blk_loc(const DecodeArgs& a, uint64_t blk) {
+  return a.loc_linear ? a.dst_base + blk * a.B : *gp(a.loc + blk);
 }
 
 // Slow path: the address of the byte at block-relative p, following sources
 // back to a literal, a resolved span, an earlier tile of this block or an
 // earlier block; null when the byte is to be written as zero (a failed
-// format rule, or an earlier block that was never published).  Reads only
-// LDS (and the location table for a dependency beyond the cache).
+// format rule, or an earlier block that was never published).  Reads LDS,
+// the offset stream and (outside whole-archive decodes) the location table.
 template <uint32_t kThreads>
 __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
                                        const BlockCtx& c, uint32_t p, uint32_t& n_ext) {
@@ -569,7 +566,7 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
       if (!c.ext_ok) return nullptr;
       n_ext++;
       const uint64_t blk = blk_of(a, src);
-      return reinterpret_cast<const uint8_t*>(dep_loc<kThreads>(a, sm, c.dep_cnt, blk)) + (src - blk * a.B);
+      return reinterpret_cast<const uint8_t*>(blk_loc(a, blk)) + (src - blk * a.B);
     }
     const uint32_t q = (uint32_t)(src - c.bs);
     if (q < c.d0) return c.out + q;
@@ -807,13 +804,9 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       }
     }
     if (t0 == 0) {
-      // the block's dependencies and their locations, once, in LDS (issued
-      // after the first tile's token loads, so the latencies overlap)
-      for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) {
-        const uint32_t d = deps[j];
-        sm.deps[j] = d;
-        sm.dloc[j] = !ext_ok ? 0 : a.loc_linear ? a.dst_base + (uint64_t)d * a.B : *gp(a.loc + d);
-      }
+      // the block's dependency list, once, in LDS (issued after the first
+      // tile's token loads, so the latencies overlap)
+      for (uint32_t j = tid; j < (cached ? dep_cnt : 0u); j += kThreads) sm.deps[j] = deps[j];
     }
     // positions in sequence order: slots 0..kThreads-1 first, then the rest
     uint32_t sv[4] = {L[0] + M[0], L[0], L[1] + M[1], L[1]}, st[4];
@@ -858,7 +851,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
                   break;
                 }
                 if (contiguous) {
-                  const uint64_t lb = cached ? sm.dloc[di] : *gp(a.loc + blk);
+                  const uint64_t lb = blk_loc(a, blk);
                   if (blk == b0) loc0 = lb;
                   else contiguous = lb == loc0 + (blk - b0) * a.B;
                 }
@@ -1238,74 +1231,181 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 // ---------------------------------------------------------------------------
-// Kernel (c): persistent, dependency-ordered decode.  Each single-wave
-// workgroup repeatedly takes the next plan entry (the plan lists blocks by
-// increasing dependency level), entropy-decodes its three streams, waits
-// until every block its matches read from has published completion, expands
-// it, and publishes its own completion.  A wave only ever waits for blocks
-// taken earlier, and those are held by running waves, so the wait always
-// ends; it is bounded anyway and flags a timeout instead of hanging.
-// Cross-XCD visibility: completion is a release store at agent scope (it
-// writes back this XCD's L2), the wait an acquire load at agent scope.
+// Kernel (c): one persistent launch decodes a whole plan, level by level,
+// driven by counters in device memory: for each dependency level, how many
+// of its blocks have been claimed for expansion and how many are finished;
+// one counter of entropy decodes claimed (in plan order, so lower levels
+// first) and one completion flag per plan entry.
+//
+// A workgroup expands blocks of the lowest level it has not yet seen
+// finish, and moves on to the next level once that level's finished count
+// reaches its size.  A block's dependencies all sit at lower levels, so
+// every block it expands finds the blocks it copies from complete.  When no
+// block of its level is left to claim, it entropy-decodes the next plan
+// entry instead, so the entropy layer of later levels runs under the
+// expansion of earlier ones (and an expansion whose streams are not decoded
+// yet decodes queued entries until they are).  Work is only ever claimed by
+// running workgroups and nothing claimed waits on anything claimed later, so
+// the launch needs no co-residency and no workgroup count.
+//
+// Cross-workgroup visibility: a finished item is published by every wave
+// issuing an agent-scope release fence (its own stores done, this XCD's L2
+// written back), then a barrier, then one atomic increment or store; the
+// consumer polls counters and flags with agent-scope atomic loads and issues
+// an agent-scope acquire fence in every wave before it reads the published
+// bytes.
+//
+// Every wait is bounded by a count of consecutive idle polls (not by a
+// clock).  An expired wait flags kErrTimeout and the workgroup stops waiting
+// from then on, as does every workgroup that sees that flag: levels are
+// skipped when not finished and expansions no longer read earlier blocks,
+// so the launch always drains (its output is then not valid, and ace_check
+// reports the timeout).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void decode_stream(const DecodeArgs& a, const PlanEntry& pe, uint32_t i,
-                                              uint32_t t, RansGroup<64>& sm, uint32_t lane) {
-  const uint8_t* d = a.arch + pe.pay + kSDesc * t;
-  const uint32_t mode = d[0], n = ld32(d + 4), clen = ld32(d + 8), off = ld32(d + 12);
-  const uint64_t pay = pe.pay;
-  uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
-               : t == 1 ? a.lens + 4ull * pe.seq_base
-                        : a.offs + (uint64_t)a.ow * pe.seq_base;
-  const uint8_t* src = a.arch + pay + off;
-  if (mode == 0) {
-    for (uint32_t j = lane; j < n; j += kWave) dst[j] = src[j];
-  } else if (rans_decode_group<64>(src, clen, n, a.W, dst, sm, lane, 0, true) && lane == 0) {
-    flag(a.err, kErrCorrupt);
+constexpr uint32_t kPersistThreads = 128;
+
+union PersistSmem {
+  ExpandSmem<kPersistThreads> e;
+  RansGroup<64> r[kPersistThreads / 64];
+};
+
+// A counter or flag shared across workgroups, read at agent scope.
+__device__ __forceinline__ uint32_t coherent_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Every wave of the workgroup: its earlier stores complete and visible at
+// agent scope; then all waves meet.
+__device__ __forceinline__ void publish_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+}
+__device__ __forceinline__ void acquire_all() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Entropy decode of plan entry i's rANS-coded streams (raw streams are read
+// in place by the expansion): wave 0 decodes LIT, wave 1 LEN then OFF.  Also
+// records where the block's bytes will live.
+__device__ void persist_entropy(const DecodeArgs& a, uint32_t i, PersistSmem& sm) {
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const PlanEntry* pp = a.plan + i;
+  const uint32_t blk = pp->block, seq_base = pp->seq_base;
+  const uint64_t pdst = pp->dst, pay = pp->pay;
+  if (threadIdx.x == 0) a.loc[blk] = a.dst_base + pdst;
+  const uint32_t t_lo = w == 0 ? 0u : 1u, t_hi = w == 0 ? 1u : 3u;
+  for (uint32_t t = t_lo; t < t_hi; t++) {
+    if (pp->raw[t] != kCoded) continue;  // wave-uniform
+    const uint8_t* d = a.arch + pay + kSDesc * t;
+    const uint32_t n = ld32(d + 4), clen = ld32(d + 8), off = ld32(d + 12);
+    uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
+                 : t == 1 ? a.lens + 4ull * seq_base
+                          : a.offs + (uint64_t)a.ow * seq_base;
+    const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
+    if (rans_decode_group<64>(a.arch + pay + off, clen, n, a.W, dst, sm.r[w], lane, 0, true) && lane == 0)
+      flag(a.err, kErrCorrupt);
+    if (a.trace && lane == 0) {
+      a.trace[8ull * i + 2 + 2 * t] = c0;
+      a.trace[8ull * i + 3 + 2 * t] = (unsigned long long)wall_clock64();
+    }
   }
 }
 
-__global__ __launch_bounds__(64) void k_persist(DecodeArgs a) {
-  __shared__ RansGroup<64> rs;
-  __shared__ ExpandSmem<64> es;
-  const uint32_t lane = threadIdx.x;
+__global__ __launch_bounds__(kPersistThreads) void k_persist(DecodeArgs a) {
+  __shared__ PersistSmem sm;
+  __shared__ uint32_t sh_kind, sh_item, sh_give_up;
+  enum : uint32_t { kExit, kExpand, kEntropy, kNextLevel, kIdle };
+  const uint32_t tid = threadIdx.x;
   const uint32_t n_plan = a.n_plan_dev ? *a.n_plan_dev : a.n_plan;
-  for (;;) {
-    uint32_t i = 0;
-    if (lane == 0) i = atomicAdd(a.queue, 1u);
-    i = __shfl(i, 0, 64);
-    if (i >= n_plan) break;
-    const PlanEntry pe = a.plan[i];
-    if (lane == 0) a.loc[pe.block] = a.dst_base + pe.dst;
-    decode_stream(a, pe, i, 1, rs, lane);
-    decode_stream(a, pe, i, 2, rs, lane);
-    decode_stream(a, pe, i, 0, rs, lane);
-    // dependencies: every listed earlier block must have published
-    const uint32_t dep_off = pe.dep_off, dep_cnt = pe.dep_cnt;
-    const uint32_t* deps = reinterpret_cast<const uint32_t*>(a.arch + kHdr + (uint64_t)kBlk * a.n_blocks) + dep_off;
-    // Poll with relaxed loads (no cache invalidation per poll), then acquire
-    // once.  The wait is bounded in time (the 100 MHz constant clock), and
-    // once any wave has given up every other wait gives up at once, so the
-    // kernel always drains.
-    bool timeout = false;
-    const uint64_t t_start = wall_clock64();
-    for (uint32_t j = lane; j < dep_cnt; j += kWave) {
-      const uint32_t* f = a.done + deps[j];
-      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
-        if (wall_clock64() - t_start > a.wait_ticks ||
-            (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)) {
-          timeout = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(8);
-      }
+  uint32_t lvl = 0, idle = 0;  // thread 0's view
+  bool give_up = false;
+  if (tid == 0) sh_give_up = 0;
+  // thread 0 decides the next step for the whole workgroup; entropy items
+  // are taken from the shared queue in plan order
+  auto take_entropy = [&](uint32_t& k) -> bool {
+    if (__hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n_plan) return false;
+    k = atomicAdd(a.queue, 1u);
+    return k < n_plan;
+  };
+  auto idle_poll = [&]() {
+    // back off while idle (the counters polled are shared by every workgroup)
+    if (idle < 16) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(16);
+    if (++idle > a.max_polls || (coherent_u32(a.err) & kErrTimeout)) {
+      if (!give_up) flag(a.err, kErrTimeout);
+      give_up = true;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const bool late = __ballot(timeout) != 0;
-    if (late && lane == 0) flag(a.err, kErrTimeout);
-    __syncthreads();  // streams of this block written, dependencies visible to all lanes
-    expand_block<64>(a, i, es, !late);
+  };
+  auto run_entropy = [&](uint32_t k) {
+    persist_entropy(a, k, sm);
+    publish_barrier();
+    if (tid == 0) __hip_atomic_store(a.done + k, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  for (;;) {
+    if (tid == 0) {
+      uint32_t kind = kIdle, item = 0;
+      if (lvl >= a.n_lvl) {
+        kind = kExit;
+      } else {
+        const uint32_t lo = a.lvl_dev[lvl], hi = a.lvl_dev[lvl + 1], size = hi - lo;
+        if (__hip_atomic_load(a.lvl_claim + lvl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < size) {
+          const uint32_t j = atomicAdd(a.lvl_claim + lvl, 1u);
+          if (j < size) {
+            kind = kExpand;
+            item = lo + j;
+          }
+        }
+        if (kind == kIdle) {
+          if (give_up || coherent_u32(a.lvl_done + lvl) >= size) kind = kNextLevel;
+          else if (take_entropy(item)) kind = kEntropy;
+        }
+      }
+      if (kind == kIdle) idle_poll();
+      else idle = 0;
+      sh_kind = kind;
+      sh_item = item;
+      sh_give_up = give_up ? 1u : 0u;
+    }
     __syncthreads();
-    if (lane == 0) __hip_atomic_store(a.done + pe.block, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t kind = sh_kind, item = sh_item;
+    const bool stop_waiting = sh_give_up != 0;
+    __syncthreads();
+    if (kind == kExit) break;
+    if (kind == kNextLevel) {
+      acquire_all();
+      if (tid == 0) lvl++;
+      continue;
+    }
+    if (kind == kEntropy) {
+      run_entropy(item);
+      continue;
+    }
+    if (kind != kExpand) continue;
+    // the entry's streams must be decoded: decode queued entries (plan order
+    // reaches this one) until its flag is set
+    for (;;) {
+      if (tid == 0) {
+        uint32_t st = kIdle, k = 0;
+        if (give_up || coherent_u32(a.done + item) == a.epoch) st = kExpand;
+        else if (take_entropy(k)) st = kEntropy;
+        if (st == kIdle) idle_poll();
+        else idle = 0;
+        sh_kind = st;
+        sh_item = k;
+        sh_give_up = give_up ? 1u : 0u;
+      }
+      __syncthreads();
+      const uint32_t st = sh_kind, k = sh_item;
+      __syncthreads();
+      if (st == kExpand) break;
+      if (st == kEntropy) run_entropy(k);
+    }
+    acquire_all();
+    const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
+    expand_block<kPersistThreads>(a, item, sm.e, !(stop_waiting || sh_give_up));
+    if (a.trace && tid == 0) {
+      a.trace[8ull * item] = c0;
+      a.trace[8ull * item + 1] = (unsigned long long)wall_clock64();
+    }
+    publish_barrier();
+    if (tid == 0) atomicAdd(a.lvl_done + lvl, 1u);
   }
 }
 
@@ -1543,19 +1643,24 @@ hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStrea
 hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s) {
   if (a.n_plan == 0) return hipSuccess;
   if (grid == 0) {
-    static int cached = 0;
-    if (cached == 0) {
-      int dev = 0, cus = 0, per_cu = 0;
-      if (hipGetDevice(&dev) != hipSuccess ||
-          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist, 64, 0) != hipSuccess)
+    static std::atomic<uint32_t> cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidValue;
+    grid = cache[dev].load(std::memory_order_relaxed);
+    if (grid == 0) {
+      int cus = 0, per_cu = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist, kPersistThreads, 0) != hipSuccess ||
+          cus <= 0)
         return hipErrorUnknown;
-      cached = cus * (per_cu > 0 ? per_cu : 1);
+      grid = (uint32_t)cus * (uint32_t)(per_cu > 0 ? per_cu : 1);
+      cache[dev].store(grid, std::memory_order_relaxed);
     }
-    grid = (uint32_t)cached;
   }
   if (grid > a.n_plan) grid = a.n_plan;
-  hipLaunchKernelGGL(k_persist, dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_persist, dim3(grid), dim3(kPersistThreads), 0, s, a);
   return hipGetLastError();
 }
 

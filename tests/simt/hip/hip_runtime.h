@@ -27,6 +27,8 @@
 #define __forceinline__ inline __attribute__((always_inline))
 #define __launch_bounds__(...)
 #define __shared__ static thread_local
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) ((const void*)&(x))
 // occupancy hints name GPU register budgets; on the host they mean nothing
 #define amdgpu_waves_per_eu(...) unused
 
@@ -194,6 +196,10 @@ template <typename K>
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) {
   *n = 1;
   return hipSuccess;
+}
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
+  return 0;
 }
 hipError_t hipGetLastError();
 hipError_t hipPeekAtLastError();

@@ -8,16 +8,12 @@ import gen
 
 pytestmark = pytest.mark.gpu
 
-# The persistent dependency-ordered kernel did not complete on the GPU in two
-# runs and its cause has not been found; the library refuses that mode.
-PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not complete on the "
-                                          "GPU, cause not yet found")
 torch = pytest.importorskip("torch")
 
 
 @pytest.mark.parametrize("tuning", [dict(mode=1), dict(mode=3),
                                     dict(mode=3, waves_per_block=8, blocks_per_wg=1),
-                                    pytest.param(dict(mode=2), marks=PERSISTENT_SKIP)],
+                                    dict(mode=2)],
                          ids=["levels", "overlap", "overlap-8waves-1stream", "persistent"])
 def test_graph_batch_replays(orc, tuning):
     if not torch.cuda.is_available():

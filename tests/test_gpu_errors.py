@@ -13,10 +13,6 @@ from harness import block_entry, stream_desc
 
 pytestmark = pytest.mark.gpu
 
-# The persistent dependency-ordered kernel did not complete on the GPU in two
-# runs and its cause has not been found; the library refuses that mode.
-PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not complete on the "
-                                          "GPU, cause not yet found")
 torch = pytest.importorskip("torch")
 
 
@@ -43,7 +39,7 @@ def _expect_corrupt(ace, a, mode):
     arc.check()  # the sticky word was cleared by the read
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+@pytest.mark.parametrize("mode", [2, 1, 3],
                          ids=["persistent", "levels", "overlap"])
 def test_damaged_rans_state(ace, orc, mode):
     x = gen.genome(1 << 18, 6)
@@ -55,7 +51,7 @@ def test_damaged_rans_state(ace, orc, mode):
     _expect_corrupt(ace, bad, mode)
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+@pytest.mark.parametrize("mode", [2, 1, 3],
                          ids=["persistent", "levels", "overlap"])
 def test_offset_not_before_destination(ace, orc, mode):
     x = gen.genome(1 << 18, 7)
@@ -79,7 +75,7 @@ def test_offset_not_before_destination(ace, orc, mode):
         _expect_corrupt(ace, _patch(a, offs["data_at"] + 4 * k, "<I", free[0] * 4096), mode)
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+@pytest.mark.parametrize("mode", [2, 1, 3],
                          ids=["persistent", "levels", "overlap"])
 def test_lengths_that_miss_the_block(ace, orc, mode):
     x = gen.text(1 << 18, 8)

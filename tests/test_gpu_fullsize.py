@@ -11,10 +11,6 @@ import gen
 
 pytestmark = pytest.mark.gpu
 
-# The persistent dependency-ordered kernel did not complete on the GPU in two
-# runs and its cause has not been found; the library refuses that mode.
-PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not complete on the "
-                                          "GPU, cause not yet found")
 torch = pytest.importorskip("torch")
 
 
@@ -29,7 +25,7 @@ def big():
     return x, a, Archive(a, device="cuda:0")
 
 
-@pytest.mark.parametrize("mode", [pytest.param(2, marks=PERSISTENT_SKIP), 1, 3],
+@pytest.mark.parametrize("mode", [2, 1, 3],
                          ids=["persistent", "levels", "overlap"])
 def test_full_decode_equals_original(big, mode):
     x, a, arc = big

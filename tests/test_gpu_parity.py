@@ -11,14 +11,10 @@ from harness import three_phase
 
 pytestmark = pytest.mark.gpu
 
-# The persistent dependency-ordered kernel did not complete on the GPU in two
-# runs and its cause has not been found; the library refuses that mode.
-PERSISTENT_SKIP = pytest.mark.skip(reason="persistent kernel disabled: did not complete on the "
-                                          "GPU, cause not yet found")
 
 torch = pytest.importorskip("torch")
 
-MODES = [pytest.param(dict(mode=2), marks=PERSISTENT_SKIP), dict(mode=1), dict(mode=3)]
+MODES = [dict(mode=2), dict(mode=1), dict(mode=3)]
 MODE_IDS = ["persistent", "levels", "overlap"]
 
 

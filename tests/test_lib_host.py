@@ -150,9 +150,6 @@ def test_argument_errors_before_device_work(lib):
     ws = C.c_uint64()
     assert L.ace_workspace_bytes(h, None, 0, C.byref(ws)) == 0
     assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value - 1, None, None) == lib.E_NOSPACE
-    t = lib.Tuning(0, 0, 0, 0, 2)
-    assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(t), None) == lib.E_ARG
-    assert b"disabled" in L.ace_last_error()
     for bad_t in [lib.Tuning(3, 0, 0, 0, 1), lib.Tuning(0, 3, 0, 0, 1), lib.Tuning(0, 0, 1, 0, 1),
                   lib.Tuning(0, 0, 0, 0, 4)]:
         assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(bad_t), None) == lib.E_ARG
