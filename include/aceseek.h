@@ -16,7 +16,9 @@
  *    error, leaves a description for ace_last_error() (per thread).
  *  - Pointers named d_* are device (HBM) pointers, h_* are host pointers.
  *    The caller owns every buffer; the library never allocates or frees
- *    device memory.  An ace_archive owns only a host copy of the index.
+ *    device memory (the one exception is the fixed scratch of
+ *    ace_seek_static, a static device array of the loaded library).  An
+ *    ace_archive owns only a host copy of the index.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
  *    asynchronous on it; host-side validation errors are returned at once,
  *    device-side ones (corrupt token streams) are sticky in the workspace
@@ -153,6 +155,26 @@ int ace_decode_all(const ace_archive* a, uint8_t* d_out, uint64_t out_cap, void*
  * An empty range returns ACE_OK without launching. */
 int ace_seek(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
              uint64_t ws_cap, const ace_tuning* t, void* stream);
+
+/* Allocation-free seek, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as ace_seek, with the workspace taken from a
+ * fixed device scratch inside the library (ACE_STATIC_SCRATCH_BYTES, one copy
+ * per device, held until the process ends) instead of a caller buffer.  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library call.
+ * d_status (caller-owned device memory, 4 bytes) receives the device error
+ * word of this seek once it completes on `stream` (0 = ok; bit 0 = a token
+ * stream broke a format rule, bit 1 = a bounded dependency wait expired).
+ * Runs the per-level path: t may be NULL or ask for mode 0 or 1, and phase
+ * timing must be off (ACE_E_ARG otherwise).  A seek whose workspace would
+ * exceed the scratch fails with ACE_E_NOSPACE (the needed size is in the
+ * message).  Every call on one device shares that device's scratch and the
+ * scratch keeps the last call's contents: calls that overlap on one device
+ * (two host threads, or two streams not ordered by the caller) race and may
+ * return wrong bytes; order them on one stream. */
+#define ACE_STATIC_SCRATCH_BYTES (64ull << 20)
+int ace_seek_static(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, uint32_t* d_status,
+                    const ace_tuning* t, void* stream);
 
 /* Batched seek: many seeks of Section 5 served together (Section 7: range
  * decode of many blocks at once).  Request i writes [lo_i, hi_i) at d_out +

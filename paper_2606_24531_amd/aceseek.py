@@ -22,7 +22,7 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
            "ace_batch_pin",
            "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan",
-           "ace_set_block_trace"]
+           "ace_set_block_trace", "ace_seek_static"]
 
 
 class AceError(RuntimeError):
@@ -72,6 +72,7 @@ def lib():
         L.ace_workspace_bytes.argtypes = [vp, vp, u32, u64p]
         L.ace_decode_all.argtypes = [vp, vp, u64, vp, u64, C.POINTER(Tuning), vp]
         L.ace_seek.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
+        L.ace_seek_static.argtypes = [vp, u64, u64, vp, vp, C.POINTER(Tuning), vp]
         L.ace_seek_batch.argtypes = [vp, vp, u32, vp, vp, vp, u64, C.POINTER(Tuning), vp]
         L.ace_check.argtypes = [vp, vp]
         L.ace_read_counters.argtypes = [vp, vp, u64p]
@@ -303,6 +304,15 @@ class Archive:
         _check(lib().ace_seek(self._h, lo, hi, C.c_void_p(out.data_ptr()),
                               C.c_void_p(ws.data_ptr()), ws.numel(), self._tuning(tuning),
                               _stream_ptr(stream)))
+        return out
+
+    def seek_static(self, lo: int, hi: int, out, status, tuning=None, stream=None):
+        """ace_seek_static: the seek with the library's fixed device scratch as
+        its workspace (allocates nothing); status (a device int32/uint8 tensor
+        of at least 4 bytes) receives the device error word."""
+        _check(lib().ace_seek_static(self._h, lo, hi, C.c_void_p(out.data_ptr()),
+                                     C.c_void_p(status.data_ptr()), self._tuning(tuning),
+                                     _stream_ptr(stream)))
         return out
 
     def seek_batch(self, ranges, out=None, out_offsets=None, ws=None, tuning=None, stream=None):

@@ -107,6 +107,10 @@ hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+// The fixed device scratch of the allocation-free seek (kStaticScratchBytes,
+// one copy per device): this device's address of it.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+hipError_t static_scratch(void** ptr);
 // batch planning and gather (device-side counts; grids sized for capacity)
 hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s);

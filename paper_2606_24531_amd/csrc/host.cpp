@@ -648,6 +648,30 @@ extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t*
   return seek_impl(A, lo, hi, d_out, d_ws, ws_cap, t, stream, nullptr);
 }
 
+static_assert(kStaticScratchBytes == ACE_STATIC_SCRATCH_BYTES, "the fixed scratch size the header states");
+
+extern "C" int ace_seek_static(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out,
+                               uint32_t* d_status, const ace_tuning* t, void* stream) {
+  if (!A || !d_status) return fail(ACE_E_ARG, "null argument");
+  if (t && t->mode != 0 && t->mode != 1)
+    return fail(ACE_E_ARG, "the allocation-free seek runs the per-level path (mode 0 or 1), not mode %u", t->mode);
+  if (g_timer.on) return fail(ACE_E_ARG, "phase timing creates events; turn it off for the allocation-free seek");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  HIP_TRY(static_scratch(&ws));
+  // the error word and the counters start at zero (a fill kernel: no memset
+  // node if the caller captures this call)
+  HIP_TRY(launch_fill_u32(static_cast<uint32_t*>(ws), 0u, kWsHeader / 4, s));
+  uint64_t need = 0;
+  int rc = seek_impl(A, lo, hi, d_out, ws, kStaticScratchBytes, t, stream, &need);
+  if (rc == ACE_E_NOSPACE)
+    return fail(ACE_E_NOSPACE, "the seek needs %llu bytes of scratch; the fixed scratch holds %llu",
+                (unsigned long long)need, (unsigned long long)kStaticScratchBytes);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(d_status, ws, 4, hipMemcpyDeviceToDevice, s));
+  return ACE_OK;
+}
+
 extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t n, uint8_t* d_out,
                               const uint64_t* out_off, void* d_ws, uint64_t ws_cap,
                               const ace_tuning* t, void* stream) {

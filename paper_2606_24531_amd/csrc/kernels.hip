@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -1675,6 +1676,33 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   uint64_t g = (n + 255) / 256;
   hipLaunchKernelGGL(k_fill_u32, dim3(g < 4096 ? g : 4096), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free seek entry point: one copy per
+// device, held from the library's load until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): it takes this device's address of the
+// array once, with the device current, and uses that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace ace

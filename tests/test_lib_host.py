@@ -150,6 +150,11 @@ def test_argument_errors_before_device_work(lib):
     ws = C.c_uint64()
     assert L.ace_workspace_bytes(h, None, 0, C.byref(ws)) == 0
     assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value - 1, None, None) == lib.E_NOSPACE
+    # the allocation-free seek refuses a null status word and the modes that
+    # create streams or events, before any device work
+    assert L.ace_seek_static(h, 0, 10, dummy, None, None, None) == lib.E_ARG
+    t3 = lib.Tuning(0, 0, 0, 0, 3)
+    assert L.ace_seek_static(h, 0, 10, dummy, dummy, C.byref(t3), None) == lib.E_ARG
     for bad_t in [lib.Tuning(3, 0, 0, 0, 1), lib.Tuning(0, 3, 0, 0, 1), lib.Tuning(0, 0, 1, 0, 1),
                   lib.Tuning(0, 0, 0, 0, 4)]:
         assert L.ace_decode_all(h, dummy, len(x), dummy, ws.value, C.byref(bad_t), None) == lib.E_ARG
