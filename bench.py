@@ -81,6 +81,29 @@ def cpu_facts() -> dict:
     return {"cpu_model": model or platform.processor(), "host_threads": os.cpu_count(), "compiler": cc}
 
 
+def cached_bytes(args, key, make):
+    """make(), kept in args.cache_dir (when given) under key."""
+    if not args.cache_dir:
+        return make()
+    path = os.path.join(args.cache_dir, key + ".bin")
+    if os.path.exists(path):
+        with open(path, "rb") as f:
+            return f.read()
+    b = make()
+    os.makedirs(args.cache_dir, exist_ok=True)
+    with open(path + ".tmp", "wb") as f:
+        f.write(b)
+    os.replace(path + ".tmp", path)
+    return b
+
+
+def cached_archive(args, x, block, cap, enc):
+    from paper_2606_24531_amd import encode
+    key = "archive-%s-%d-%d-B%d-cap%d-W%d-mm%d" % (args.profile, args.size, args.seed, block, cap,
+                                                   enc["interleave"], enc["min_match"])
+    return cached_bytes(args, key, lambda: encode(x, block_size=block, max_level=cap, **enc))
+
+
 def _time_steps(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -136,10 +159,13 @@ def main():
                          "autotuner on a 32 MiB sample of the workload")
     ap.add_argument("--min-match", type=int, default=16)
     ap.add_argument("--max-level", type=int, default=16)
-    ap.add_argument("--mode", type=int, default=1,
-                    help="1: entropy decode of all blocks, then one expansion launch per level, "
-                         "one stream; 3: entropy decode per level on a second stream beside the "
-                         "per-level expansion")
+    ap.add_argument("--mode", type=int, default=0,
+                    help="0: the autotuner's choice (1 when W is given); 1: entropy decode of all "
+                         "blocks, then one expansion launch per level; 2: entropy decode, then one "
+                         "persistent expansion launch for every level; 3: entropy decode per level "
+                         "group on a second stream beside the per-level expansion")
+    ap.add_argument("--grid", type=int, default=-1,
+                    help="mode 2: persistent workgroups (0 = all the device holds; -1 = tuned or 0)")
     ap.add_argument("--waves-per-block", type=int, default=0,
                     help="wavefronts per block in the match expansion (1, 2, 4, 8; 0 = chosen per launch by its size)")
     ap.add_argument("--per-wave", type=int, default=0,
@@ -165,6 +191,9 @@ def main():
                     help="instead of the headline decode, run the other workloads and print one "
                          "JSON line each: genome1m (1 MiB genome, decode + every block sought with "
                          "the three-phase check), fastq256 (256 MiB FASTQ, 16 KiB blocks, cap 16)")
+    ap.add_argument("--cache-dir", default="",
+                    help="keep the generated input and the encoded archives in this folder and "
+                         "reuse them when the same workload is asked for again (profiling runs)")
     ap.add_argument("--calib", action="store_true",
                     help="also run the byte-counter calibration kernels (a 256 MiB fill: known "
                          "bytes written; a 256 MiB sum: known bytes read) after the decode")
@@ -189,7 +218,8 @@ def main():
         return suite_main(args)
     os.environ.setdefault("ACESEEK_ENCODE_PROGRESS", "0")
     t0 = time.time()
-    x = gen.by_name(args.profile, args.size, args.seed)
+    x = cached_bytes(args, "input-%s-%d-%d" % (args.profile, args.size, args.seed),
+                     lambda: gen.by_name(args.profile, args.size, args.seed))
     _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
     x_dev = torch.from_numpy(np.frombuffer(x, dtype=np.uint8).copy()).to(dev)
     tuned = None
@@ -199,19 +229,28 @@ def main():
         tuned = tune(x[:min(len(x), 32 << 20)], args.profile, block_size=args.block,
                      min_match=args.min_match, max_level=args.max_level, log=_log)
         args.interleave = tuned["interleave"]
+        if not args.mode:
+            args.mode = tuned["mode"]
+            if args.grid < 0:
+                args.grid = tuned["grid_wgs"]
         if not args.waves_per_block:
             args.waves_per_block = tuned["waves_per_block"]
         if not args.per_wave:
             args.per_wave = tuned["blocks_per_wg"]
-        _log("autotune (%.1fs): W=%d, %s waves per block, %d streams per wave" % (
-            time.time() - t0, args.interleave, args.waves_per_block or "auto", args.per_wave))
+        _log("autotune (%.1fs): W=%d, mode %d, %s waves per block, %d streams per wave, grid %s" % (
+            time.time() - t0, args.interleave, args.mode, args.waves_per_block or "auto", args.per_wave,
+            args.grid if args.grid > 0 else "full"))
+    if not args.mode:
+        args.mode = 1
+    args.grid = max(args.grid, 0)
     enc = dict(interleave=args.interleave, min_match=args.min_match, hash_len=args.min_match, max_chain=32)
     t0 = time.time()
-    a = encode(x, block_size=args.block, max_level=args.max_level, **enc)
+    a = cached_archive(args, x, args.block, args.max_level, enc)
     enc_s = time.time() - t0
     _log("encoded to %d bytes (ratio %.3f) in %.1fs" % (len(a), len(x) / len(a), enc_s))
     arc = Archive(a, device=dev)
-    tuning = dict(mode=args.mode, waves_per_block=args.waves_per_block, blocks_per_wg=args.per_wave)
+    tuning = dict(mode=args.mode, waves_per_block=args.waves_per_block, blocks_per_wg=args.per_wave,
+                  grid_wgs=args.grid)
     stream = torch.cuda.current_stream()
     d = decode_entry(arc, a, x_dev, tuning, args.steps, args.warmup, "headline")
     ms, ext = d["ms"], d["ext"]
@@ -242,11 +281,12 @@ def main():
     share_exp = len(x) + ext + d["raw_in_place"]
     share_ent = d["coded"]
     phase = {
-        "entropy": {"kernel": "k_rans", "launches_per_step": arc.depth if args.mode == 3 else 1,
+        "entropy": {"kernel": "k_rans", "launches_per_step": 2 if args.mode == 3 else 1,
                     "ms": round(ms_ent, 4), "alg_bytes": share_ent,
                     "achieved_GBs": round(share_ent / (ms_ent * 1e-3) / 1e9, 2),
                     "overhead_bytes_written": d["rans_decoded"]},
-        "match": {"kernel": "k_expand", "launches_per_step": arc.depth, "ms": round(ms_mat, 4),
+        "match": {"kernel": "k_persist" if args.mode == 2 else "k_expand",
+                  "launches_per_step": 1 if args.mode == 2 else arc.depth, "ms": round(ms_mat, 4),
                   "alg_bytes": share_exp,
                   "achieved_GBs": round(share_exp / (ms_mat * 1e-3) / 1e9, 2),
                   "overhead_bytes_read": d["rans_decoded"]},
@@ -288,7 +328,9 @@ def main():
             "autotuned": tuned is not None, "encode_s": round(enc_s, 1),
             "dag": _dag_facts(a),
             "mode": {1: "entropy launch, then one expansion launch per level, one stream",
+                     2: "entropy launch, then one persistent expansion launch for every level",
                      3: "per-level launches, entropy overlapped on a second stream"}[args.mode],
+            "grid_wgs": args.grid if args.mode == 2 else None,
         },
         "roofline": {
             "bound": "hbm", "kernel": dk["kernel"],
@@ -323,7 +365,7 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
         for key, B, cap, steps in (("blocks_64k", 65536, args.max_level, args.steps),
                                    ("uncapped", args.block, 0, 3)):
             t0 = time.time()
-            ax = encode(x, block_size=B, max_level=cap, **enc)
+            ax = cached_archive(args, x, B, cap, enc)
             enc_s = time.time() - t0
             arcx = Archive(ax, device=dev)
             e = decode_entry(arcx, ax, x_dev, tuning, steps, 1, key)
@@ -593,7 +635,8 @@ def suite_main(args):
                    max_chain=32, max_level=16)
         arc = Archive(a, device=dev)
         xd = torch.from_numpy(np.frombuffer(x, dtype=np.uint8).copy()).to(dev)
-        shape = dict(mode=1, waves_per_block=tuned["waves_per_block"], blocks_per_wg=tuned["blocks_per_wg"])
+        shape = dict(mode=tuned["mode"], waves_per_block=tuned["waves_per_block"],
+                     blocks_per_wg=tuned["blocks_per_wg"], grid_wgs=tuned["grid_wgs"])
         ms, ok = _time_decode(arc, xd, shape, 20)
         _log("fastq256: ratio %.3f, depth %d, decode %.3f ms (%.1f GB/s), parity %s" % (
             len(x) / len(a), arc.depth, ms, len(x) / ms / 1e6, ok))

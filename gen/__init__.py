@@ -12,6 +12,8 @@ streams obtained by ``SeedSequence.spawn``.
 """
 from __future__ import annotations
 
+import bisect
+
 import numpy as np
 
 __all__ = [
@@ -175,21 +177,40 @@ def text(n: int, seed: int) -> bytes:
         c = np.concatenate([[0], np.cumsum(tl)])
         d = c[1:] + np.arange(m)  # D[k] = C[k+1] + k
         sep = np.full(m, ord(" "), dtype=np.uint8)
-        a = 0
+        # One target length per line, drawn in order; a batch draw yields the
+        # same values as one draw at a time, and the generator is then moved
+        # on by exactly the number of draws used.
+        state = r_line.bit_generator.state
+        targets = r_line.integers(60, 101, size=m + 1).tolist()
+        dl, cl = d.tolist(), c.tolist()
+        a = used = 0
         while a < m:
-            t = int(r_line.integers(60, 101))
-            k = int(np.searchsorted(d, c[a] + a + t, side="left"))
+            t = targets[used]
+            used += 1
+            k = bisect.bisect_left(dl, cl[a] + a + t)
             if k >= m:
                 break
             sep[k] = 10
             a = k + 1
+        r_line.bit_generator.state = state
+        r_line.integers(60, 101, size=used)
         tot_len = tl + 1
         starts = np.concatenate([[0], np.cumsum(tot_len)[:-1]])
         buf = np.empty(int(tot_len.sum()), dtype=np.uint8)
         wl = wlen[ids]
-        rep_start = np.repeat(starts, wl)
-        within = np.arange(int(wl.sum())) - np.repeat(np.cumsum(wl) - wl, wl)
-        buf[rep_start + within] = chars[np.repeat(wstart[ids], wl) + within]
+        # letter j of the chunk: source index into `chars` and destination
+        # index into `buf`, both consecutive within a word and jumping to the
+        # next word's start between words (built as running sums of steps)
+        first = np.cumsum(wl) - wl
+        src = np.ones(int(wl.sum()), dtype=np.int64)
+        dst = np.ones(src.size, dtype=np.int64)
+        ws = wstart[ids]
+        src[0], dst[0] = ws[0], starts[0]
+        src[first[1:]] = ws[1:] - (ws[:-1] + wl[:-1] - 1)
+        dst[first[1:]] = starts[1:] - (starts[:-1] + wl[:-1] - 1)
+        np.cumsum(src, out=src)
+        np.cumsum(dst, out=dst)
+        buf[dst] = chars[src]
         pend = starts + wl
         buf[pend[has_p]] = pch[has_p]
         buf[starts + tl] = sep

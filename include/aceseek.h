@@ -84,12 +84,17 @@ typedef struct {
  *                   (0 = 2 when possible)
  *  lut_variant      entropy table layout in LDS: 0 = 4096-byte slot->symbol
  *                   map plus one (f-1, cum) word per symbol (the only one)
- *  grid_wgs         workgroups of the persistent decoder (0 = fill the GPU)
+ *  grid_wgs         workgroups of the persistent expansion (0 = as many as
+ *                   the device holds at once; never more than the planned
+ *                   blocks)
  *  mode             0 and 1: one entropy launch for every planned block,
  *                   then one match-expansion launch per dependency level,
- *                   all on the caller's stream; 2: the persistent
- *                   dependency-ordered kernel, which is disabled in this
- *                   build (ACE_E_ARG); 3: the levels split in an early
+ *                   all on the caller's stream; 2: one entropy launch,
+ *                   then one persistent launch that expands every level in
+ *                   turn, synchronised by counters in the workspace (every
+ *                   wait bounded by a count of idle polls: an expired wait
+ *                   makes ace_check report ACE_E_TIMEOUT, and the launch
+ *                   still ends); 3: the levels split in an early
  *                   group (at most a quarter of the planned blocks, at
  *                   least level 0) and a late group; the late group's
  *                   entropy decode runs as one launch on a second stream of

@@ -224,6 +224,7 @@ class Archive:
         n, B, nb, depth = C.c_uint64(0), C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
         _check(lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)))
         self.n_total, self.block_size, self.n_blocks, self.depth = n.value, B.value, nb.value, depth.value
+        self.interleave = int(host[12]) | (int(host[13]) << 8) if self.nbytes >= 64 else 0
         self._ws = None
         # the whole-archive decode plan, resident next to the archive (else
         # it is copied from the host on every whole-archive decode)

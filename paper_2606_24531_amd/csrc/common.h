@@ -56,12 +56,11 @@ struct DecodeArgs {
   uint32_t* err;   // sticky error word
   unsigned long long* ext_bytes;  // counter: match bytes read from earlier blocks
   // persistent-kernel state
-  uint32_t* queue;      // entropy decodes claimed (plan entries, in plan order)
-  uint32_t* done;       // per plan entry: == epoch once its streams are decoded
-  uint32_t epoch;
   uint32_t n_lvl;       // dependency levels of the plan (bounds in lvl_dev)
-  uint32_t* lvl_claim;  // per level: expansions claimed
-  uint32_t* lvl_done;   // per level: expansions finished
+  uint32_t* lvl_done;   // per level: expansions finished and published
+  uint32_t* lvl_claim;  // per slice and level: expansions claimed (slice-major rows)
+  uint32_t lvl_row;     // words per slice row of lvl_claim
+  uint32_t* lvl_seen;   // levels finished, in copies one 128-byte line apart
   uint32_t max_polls;   // consecutive idle polls before a wait gives up
   // plan length (device-planned batches; null for host-planned calls) and
   // level boundaries in device memory (device-planned batches and the
@@ -101,8 +100,24 @@ struct BatchArgs {
 hipError_t launch_rans(const DecodeArgs& a, uint32_t lo, uint32_t hi, uint32_t per_wave, hipStream_t s);
 hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t plan_hi, uint32_t waves,
                                hipStream_t s);
-// the persistent level-by-level decode (kernel (c)); grid 0 = as many
-// workgroups as the device holds at once
+// the persistent level-by-level expansion (kernel (c)); grid 0 = as many
+// workgroups as the device holds at once.  Its counters (persist_sync_words
+// words from lvl_done, laid out by persist_sync) start at zero.
+constexpr uint32_t kPersistSlices = 8, kPersistReplicas = 64, kPersistLine = 32;
+inline uint64_t persist_row(uint32_t n_lvl) { return (n_lvl + kPersistLine - 1ull) / kPersistLine * kPersistLine; }
+inline uint64_t persist_sync_words(uint32_t n_lvl) {
+  return (1 + kPersistSlices) * persist_row(n_lvl) + (uint64_t)kPersistReplicas * kPersistLine;
+}
+// Points the kernel's counters into `words` (128-byte aligned, at least
+// persist_sync_words(a.n_lvl) words): finished counts, one row per level;
+// claim counts, one row per slice; the finished-level copies.
+inline void persist_sync(DecodeArgs& a, uint32_t* words) {
+  const uint64_t row = persist_row(a.n_lvl);
+  a.lvl_done = words;
+  a.lvl_claim = words + row;
+  a.lvl_row = (uint32_t)row;
+  a.lvl_seen = words + (1 + kPersistSlices) * row;
+}
 hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,
                        hipStream_t s);

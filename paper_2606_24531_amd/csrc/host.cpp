@@ -301,8 +301,8 @@ int check_tuning(const ace_archive* A, const ace_tuning* t) {
   return ACE_OK;
 }
 
-// workspace header: error word (0), work counter (4), 16 counters of match
-// bytes read from earlier blocks (16..144, one per block id mod 16)
+// workspace header: error word (0), 16 counters of match bytes read from
+// earlier blocks (16..144, one per block id mod 16)
 constexpr uint64_t kWsHeader = 256, kWsCounters = 16;
 
 uint32_t shift_of(uint32_t B) {
@@ -331,20 +331,19 @@ constexpr uint32_t kModePersistent = 2, kModeOverlap = 3;  // 0 and 1: per level
 constexpr uint32_t kMaxIdlePolls = 1u << 21;
 
 struct Layout {
-  uint64_t plan, lv, loc, done, lit, lens, offs, slots, items, total;
+  uint64_t plan, lv, loc, lit, lens, offs, slots, items, total;
 };
 
 // Workspace of one host-planned decode.  lv: per dependency level of the
 // archive, the plan's level boundaries (depth + 1), then the persistent
-// kernel's claimed and finished counts (depth each).
+// kernel's finished counts (depth) and its finished-level copies.
 Layout layout(const ace_archive* A, uint64_t n_plan, uint64_t n_seq, uint64_t n_slots,
               uint64_t n_items) {
   Layout L;
   uint64_t o = kWsHeader;
   L.plan = o;  o = align_up(o + sizeof(PlanEntry) * n_plan, 256);
-  L.lv = o;    o = align_up(o + 4ull * (3ull * A->depth + 1), 256);
+  L.lv = o;    o = align_up(o + 4ull * (persist_row(A->depth + 1) + persist_sync_words(A->depth)), 256);
   L.loc = o;   o = align_up(o + 8ull * A->nb, 256);
-  L.done = o;  o = align_up(o + 4ull * A->nb, 256);
   L.lit = o;   o = align_up(o + (uint64_t)A->B * n_plan + 64, 256);  // +64: aligned over-read slack
   L.lens = o;  o = align_up(o + 4ull * n_seq, 256);
   L.offs = o;  o = align_up(o + (uint64_t)A->ow * n_seq, 256);
@@ -432,13 +431,9 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
   a.offs = ws + L.offs;
   a.err = reinterpret_cast<uint32_t*>(ws);
   a.ext_bytes = reinterpret_cast<unsigned long long*>(ws + kWsCounters);
-  a.queue = reinterpret_cast<uint32_t*>(ws + 4);
-  a.done = reinterpret_cast<uint32_t*>(ws + L.done);
-  a.epoch = 1;
   a.n_lvl = (uint32_t)(lstart.size() - 1);
   a.lvl_dev = reinterpret_cast<const uint32_t*>(ws + L.lv);
-  a.lvl_claim = reinterpret_cast<uint32_t*>(ws + L.lv) + a.n_lvl + 1;
-  a.lvl_done = a.lvl_claim + a.n_lvl;
+  persist_sync(a, reinterpret_cast<uint32_t*>(ws + L.lv) + persist_row(a.n_lvl + 1));
   a.max_polls = kMaxIdlePolls;
   if (g_trace) {
     if (g_trace_entries < n_plan)
@@ -479,12 +474,11 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
       return r;
     };
     if (mode == kModePersistent) {
-      // one launch: level boundaries uploaded, counters and flags cleared
-      // (fill kernels), then the persistent level-by-level decode
+      // the entropy launch, then one persistent launch for every level:
+      // level boundaries uploaded, counters cleared by a fill kernel
       HIP_TRY(hipMemcpyAsync(ws + L.lv, lstart.data(), 4ull * lstart.size(), hipMemcpyHostToDevice, s));
-      HIP_TRY(launch_fill_u32(a.lvl_claim, 0u, 2ull * a.n_lvl, s));
-      HIP_TRY(launch_fill_u32(a.done, 0u, n_plan, s));
-      HIP_TRY(launch_fill_u32(a.queue, 0u, 1, s));
+      HIP_TRY(launch_fill_u32(a.lvl_done, 0u, persist_sync_words(a.n_lvl), s));
+      HIP_TRY(entropy(0, (uint32_t)n_plan, s));
       if (timed) {
         HIP_TRY(timer_pair(T.mat, T.n_mat));
         HIP_TRY(hipEventRecord(T.mat[2 * T.n_mat], s));
@@ -763,7 +757,7 @@ struct ace_batch {
 
 namespace {
 struct BatchLayout {
-  uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, done, lit, lens, offs, slots, desc, pin, pinbase,
+  uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, lit, lens, offs, slots, desc, pin, pinbase,
       total;
 };
 
@@ -781,9 +775,8 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   L.pre = take(4ull * A->nb);
   L.plan = take(sizeof(PlanEntry) * A->nb);
   L.nplan = take(4);
-  L.lvl = take(4ull * (3ull * A->depth + 1));  // plan boundaries, then the persistent kernel's counts
+  L.lvl = take(4ull * (persist_row(A->depth + 1) + persist_sync_words(A->depth)));  // plan boundaries, then the persistent kernel's counters
   L.loc = take(8ull * A->nb);
-  L.done = take(4ull * A->nb);
   L.lit = take((uint64_t)A->B * A->nb + 64);
   L.lens = take(4ull * A->all_seq);
   L.offs = take((uint64_t)A->ow * A->all_seq);
@@ -894,14 +887,10 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     a.offs = b->ws + L.offs;
     a.err = reinterpret_cast<uint32_t*>(b->ws);
     a.ext_bytes = reinterpret_cast<unsigned long long*>(b->ws + kWsCounters);
-    a.queue = reinterpret_cast<uint32_t*>(b->ws + 4);
-    a.done = reinterpret_cast<uint32_t*>(b->ws + L.done);
-    a.epoch = 1;
     a.n_plan_dev = ba.n_plan_dev;
     a.lvl_dev = ba.lvl_dev;
     a.n_lvl = A->depth;
-    a.lvl_claim = ba.lvl_dev + A->depth + 1;
-    a.lvl_done = a.lvl_claim + A->depth;
+    persist_sync(a, ba.lvl_dev + persist_row(A->depth + 1));
     a.max_polls = kMaxIdlePolls;
     const uint32_t mode = t ? t->mode : 0;
     if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) {
@@ -937,14 +926,13 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
       break;
     }
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ba.need), 0u, align_up(A->nb, 4) / 4, s);
-    if (e == hipSuccess) e = launch_fill_u32(a.done, 0u, A->nb, s);
-    if (e == hipSuccess) e = launch_fill_u32(a.queue, 0u, 1, s);
     if (e == hipSuccess) e = launch_batch_mark(ba, s);
     for (uint32_t l = A->depth; e == hipSuccess && l-- > 1;)
       e = launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s);
     if (e == hipSuccess) e = launch_batch_compact(ba, s);
     if (e == hipSuccess && mode == kModePersistent) {
-      e = launch_fill_u32(a.lvl_claim, 0u, 2ull * A->depth, s);
+      e = launch_fill_u32(a.lvl_done, 0u, persist_sync_words(A->depth), s);
+      if (e == hipSuccess) e = launch_rans_dev(a, A->nb, per_wave, s);
       if (e == hipSuccess) e = launch_persistent(a, t ? t->grid_wgs : 0, s);
     } else if (e == hipSuccess && overlap) {
       const size_t split = level_split(A->all_levels);

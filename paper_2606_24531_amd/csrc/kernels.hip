@@ -42,14 +42,6 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint8_t ld8(const uint8_t* p) { return *gp(p); }
 __device__ __forceinline__ void st8(uint8_t* p, uint8_t v) { *gp(p) = v; }
-__device__ __forceinline__ void st16(uint8_t* p, uint4 v) {  // 16-aligned p
-  u32x4 w;
-  w.x = v.x;
-  w.y = v.y;
-  w.z = v.z;
-  w.w = v.w;
-  *gp(reinterpret_cast<u32x4*>(p)) = w;
-}
 
 __device__ __forceinline__ uint32_t ld16(const uint8_t* p) {
   return (uint32_t)ld8(p) | ((uint32_t)ld8(p + 1) << 8);
@@ -330,20 +322,10 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
 // to lens + 4 * seq_base and OFF to offs + ow * seq_base; raw streams are
 // left in place (the expansion reads them there).  Also records where each
 // block's bytes will live.
+// Stream t of plan entry i (on: the group has an entry), one group of G lanes.
 template <uint32_t G>
-__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
-                                             int lv_hi) {
-  __shared__ RansGroup<G> sm[64 / G];
-  const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
-  if (lv_lo >= 0) {  // the plan range of levels [lv_lo, lv_hi), from device memory
-    plan_lo = a.lvl_dev[lv_lo];
-    plan_hi = a.lvl_dev[lv_hi];
-  } else if (a.n_plan_dev) {
-    plan_hi = *a.n_plan_dev;
-  }
-  const uint32_t i = plan_lo + blockIdx.x * (64 / G) + h;
-  bool on = i < plan_hi;
-  if (!__ballot(on)) return;
+__device__ __forceinline__ void rans_entry(const DecodeArgs& a, uint32_t i, bool on, uint32_t t,
+                                           RansGroup<G>& sm, uint32_t g, uint32_t h) {
   // only the fields this kernel needs (no whole-entry copy: raw[t] is
   // indexed by the grid's y coordinate)
   const PlanEntry* pp = a.plan + (on ? i : 0);
@@ -371,10 +353,36 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
                         : a.offs + (uint64_t)a.ow * seq_base;
   const uint8_t* src = a.arch + pay + off;
   const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
-  if (rans_decode_group<G>(src, clen, n, a.W, dst, sm[h], g, h, on) && g == 0) flag(a.err, kErrCorrupt);
+  if (rans_decode_group<G>(src, clen, n, a.W, dst, sm, g, h, on) && g == 0) flag(a.err, kErrCorrupt);
   if (a.trace && on && g == 0) {
     a.trace[8ull * i + 2 + 2 * t] = c0;
     a.trace[8ull * i + 3 + 2 * t] = (unsigned long long)wall_clock64();
+  }
+}
+
+// Kernel (a): grid (x, 3); wavefront x decodes stream y of the 64/G plan
+// entries plan_lo + (x + k * gridDim.x) * 64/G + ..., k = 0, 1, ... (one
+// pass when the grid covers the plan; a plan whose length is read from
+// device memory is covered by striding).  LIT goes to lit + plan_index * B,
+// LEN to lens + 4 * seq_base and OFF to offs + ow * seq_base; raw streams
+// are left in place (the expansion reads them there).  Also records where
+// each block's bytes will live.
+template <uint32_t G>
+__global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uint32_t plan_hi, int lv_lo,
+                                             int lv_hi) {
+  __shared__ RansGroup<G> sm[64 / G];
+  const uint32_t lane = threadIdx.x, h = lane / G, g = lane % G, t = blockIdx.y;
+  if (lv_lo >= 0) {  // the plan range of levels [lv_lo, lv_hi), from device memory
+    plan_lo = a.lvl_dev[lv_lo];
+    plan_hi = a.lvl_dev[lv_hi];
+  } else if (a.n_plan_dev) {
+    plan_hi = *a.n_plan_dev;
+  }
+  for (uint32_t bx = blockIdx.x;; bx += gridDim.x) {
+    const uint32_t i = plan_lo + bx * (64 / G) + h;
+    const bool on = i < plan_hi;
+    if (!__ballot(on)) return;
+    rans_entry<G>(a, i, on, t, sm[h], g, h);
   }
 }
 
@@ -397,13 +405,19 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
 //     of another match's bytes points at that match's span, and pointers are
 //     doubled (a pointer to a pointer becomes one) until each reaches a
 //     resolved span, so a chain of n such matches takes log2(n) rounds.
-// Output is then produced in 16-byte chunks: a chunk of one literal run or
-// of one resolved, non-wrapping match is one 16-byte load (global loads take
-// any byte alignment on this target) and one store; the
-// others are assembled byte by byte, every byte's address first and then the
-// loads together.  Spans that straddle sequences or blocks take the slow
-// path: follow the source back until it reaches a literal, a resolved span,
-// an earlier tile or an earlier block; each step moves strictly backwards.
+// Output is then produced in pieces: each literal run and each resolved
+// match is cut into 16-byte pieces from its own first byte (the last piece
+// shorter).  A piece is one 16-byte load at any byte alignment (global
+// loads and stores take any alignment on this target; a load is moved back
+// when the bytes after the piece are not known readable), or two when a
+// periodic match wraps inside it, and one store of exactly its bytes; a
+// match whose period is shorter than 16 bytes, or whose readable window is
+// too small, is read byte by byte.  Pieces write disjoint bytes, so every
+// thread takes four of them per round with all loads in flight before any
+// store, whatever sequences they belong to.  Spans that straddle sequences
+// or blocks take the slow path: follow the source back until it reaches a
+// literal, a resolved span, an earlier tile or an earlier block (each step
+// moves strictly backwards), one byte per thread.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPoison = 1u, kSlow = 2u, kPend = 4u, kExt = 8u;
 constexpr uint32_t kUnres = kPoison | kSlow | kPend;  // flags of a span without an address
@@ -413,11 +427,9 @@ constexpr uint32_t kMaxJumps = 12;   // pointer-doubling rounds (chains up to 40
 template <uint32_t kThreads>
 struct ExpandSmem {
   static constexpr uint32_t kSeq = 2 * kThreads;    // sequences per tile (two per thread)
-  static constexpr uint32_t kRound = 4 * kThreads;  // 16-byte chunks sorted per round
-  static constexpr uint32_t kSeqBits = kThreads <= 64 ? 7 : kThreads <= 128 ? 8 : kThreads <= 256 ? 9 : 10;
-  uint32_t list[kRound];  // per-byte chunks: chunk << kSeqBits | sequence
-  uint32_t cseq[kRound];  // marks: the last sequence starting in each chunk (0 = none)
-  uint32_t nbyte;
+  static constexpr uint32_t kRound = 4 * kThreads;  // output pieces per round (four per thread)
+  uint32_t cseq[kRound];  // marks: the sequence whose first piece is each piece of the round (0 = none)
+  uint32_t pfx[kSeq];     // index of the sequence's first output piece in the tile
   uint32_t dst[kSeq];     // block-relative start of the sequence
   uint32_t lm[kSeq];      // L | M << 16
   uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
@@ -604,6 +616,63 @@ __device__ __forceinline__ void st16u(uint8_t* p, uint4 v) {  // any byte alignm
   *reinterpret_cast<ACE_GLOBAL u32x4_a1*>(gp(p)) = w;
 }
 
+// The 16 bytes x moved down by s bytes (byte s becomes byte 0; zeros come
+// in at the top), 0 <= s < 16; and moved up by n bytes (byte 0 becomes byte
+// n), 0 <= n < 16.  Branch-free: dword selects, then a funnel shift.
+__device__ __forceinline__ uint32_t pick4(const uint32_t (&y)[8], uint32_t i, uint32_t q) {
+  return q == 0 ? y[i] : q == 1 ? y[i + 1] : q == 2 ? y[i + 2] : y[i + 3];
+}
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t b) {  // b in 0..24 step 8
+  return b ? (lo >> b) | (hi << (32 - b)) : lo;
+}
+__device__ __forceinline__ void shift_down16(uint32_t (&x)[4], uint32_t s) {
+  const uint32_t q = s >> 2, b = 8 * (s & 3);
+  const uint32_t y[8] = {x[0], x[1], x[2], x[3], 0u, 0u, 0u, 0u};
+  uint32_t z[5];
+#pragma unroll
+  for (uint32_t i = 0; i < 5; i++) z[i] = pick4(y, i < 4 ? i : 4, q);
+#pragma unroll
+  for (uint32_t i = 0; i < 4; i++) x[i] = funnel(z[i + 1], z[i], b);
+}
+__device__ __forceinline__ void shift_up16(uint32_t (&x)[4], uint32_t n) {
+  const uint32_t q = n >> 2, b = 8 * (n & 3);
+  const uint32_t y[8] = {0u, 0u, 0u, 0u, x[0], x[1], x[2], x[3]};  // y[4 + k] = x[k]
+#pragma unroll
+  for (uint32_t i = 0; i < 4; i++) {
+    const uint32_t hi = pick4(y, 1 + i, 3 - q), lo = pick4(y, i, 3 - q);  // x[i - q], x[i - q - 1]
+    x[i] = b ? (hi << b) | (lo >> (32 - b)) : hi;
+  }
+}
+
+typedef uint64_t u64_a1 __attribute__((aligned(1)));
+typedef uint32_t u32_a1 __attribute__((aligned(1)));
+typedef uint16_t u16_a1 __attribute__((aligned(1)));
+// Writes bytes [0, len) of w (len <= 16) at any byte address, nothing else.
+__device__ __forceinline__ void store_bytes(uint8_t* p, const uint32_t (&w)[4], uint32_t len) {
+  if (len == 16) {
+    st16u(p, make_uint4(w[0], w[1], w[2], w[3]));
+    return;
+  }
+  uint32_t x0 = w[0], x1 = w[1], x2 = w[2], x3 = w[3], o = 0;
+  if (len & 8) {
+    *reinterpret_cast<ACE_GLOBAL u64_a1*>(gp(p)) = (uint64_t)x0 | ((uint64_t)x1 << 32);
+    x0 = x2;
+    x1 = x3;
+    o = 8;
+  }
+  if (len & 4) {
+    *reinterpret_cast<ACE_GLOBAL u32_a1*>(gp(p + o)) = x0;
+    x0 = x1;
+    o += 4;
+  }
+  if (len & 2) {
+    *reinterpret_cast<ACE_GLOBAL u16_a1*>(gp(p + o)) = (uint16_t)x0;
+    x0 >>= 16;
+    o += 2;
+  }
+  if (len & 1) st8(p + o, (uint8_t)x0);
+}
+
 // Copies len bytes of the decoded data from absolute position lo to dst.
 // Each thread takes four 16-byte chunks per step (a blockDim.x * 16 stride
 // apart, so every load and store instruction is coalesced), issues the loads
@@ -666,102 +735,12 @@ __device__ __forceinline__ uint32_t dword_mask(uint32_t j, uint32_t lo, uint32_t
   return m;
 }
 
-// Segment path for a 16-byte output chunk [cb, cb+16) inside the tile: the
-// chunk is cut at literal/match and sequence boundaries into at most four
-// segments over at most two sequences.  Each segment's source, shifted so
-// that its byte j lines up with output byte j, is one 16-byte load (all
-// issued before any is used), merged by byte mask.  Bytes of slow spans are left as placeholders (the
-// slow pass writes them), bytes of poisoned sequences as zeros.  Returns
-// false (the caller takes the per-byte path) for a period wrap inside a
-// segment, a third sequence, or a source window that is not known readable.
-template <uint32_t kThreads>
-__device__ __forceinline__ bool seg_chunk(const ExpandSmem<kThreads>& sm, const BlockCtx& c, uint32_t cb,
-                                          uint32_t s, uint32_t d1, uint32_t (&out)[4]) {
-  constexpr uint32_t kC = 4;  // candidate segments: (literal, match) x 2 sequences
-  uint64_t V[kC];
-  uint32_t lo[kC], hi[kC];
-  bool load[kC];
-  uint32_t x = cb;
-  bool ok = true;
-  // the two candidate sequences' fields, read at once (indices clamped into
-  // the tile arrays; values past c.cnt are never used)
-  constexpr uint32_t kSeq = ExpandSmem<kThreads>::kSeq;
-  const uint32_t s1 = s + 1 < kSeq ? s + 1 : s, s2 = s + 2 < kSeq ? s + 2 : s;
-  const uint32_t dst_q[3] = {sm.dst[s], sm.dst[s1], sm.dst[s2]};
-  const uint32_t lm_q[2] = {sm.lm[s], sm.lm[s1]}, dfl_q[2] = {sm.dfl[s], sm.dfl[s1]};
-  const uint32_t lit_q[2] = {sm.lit[s], sm.lit[s1]}, win_q[2] = {sm.win[s], sm.win[s1]};
-  const uint64_t src_q[2] = {sm.src0[s], sm.src0[s1]};
-#pragma unroll
-  for (uint32_t q = 0; q < 2; q++) {
-    load[2 * q] = load[2 * q + 1] = false;
-    lo[2 * q] = hi[2 * q] = lo[2 * q + 1] = hi[2 * q + 1] = 0;
-    V[2 * q] = V[2 * q + 1] = 0;
-    const uint32_t sq = s + q;
-    if (x < cb + 16 && sq < c.cnt) {
-      const uint32_t sd = dst_q[q];
-      const uint32_t se = sq + 1 < c.cnt ? dst_q[q + 1] : d1;
-      const uint32_t L = lm_q[q] & 0xFFFFu;
-      const uint32_t dfl = dfl_q[q], f = dfl >> 24, d = dfl & 0xFFFFFFu;
-      const uint32_t end = se < cb + 16 ? se : cb + 16;
-      if (f & kPoison) {
-        lo[2 * q] = x - cb;  // zeros: a segment with no load
-        hi[2 * q] = end - cb;
-        x = end;
-      } else {
-        if (x < sd + L) {  // literal run
-          const uint32_t h = sd + L < end ? sd + L : end;
-          const uint8_t* A = c.lit + lit_q[q] + (x - sd);
-          V[2 * q] = (uint64_t)(uintptr_t)A - (x - cb);
-          lo[2 * q] = x - cb;
-          hi[2 * q] = h - cb;
-          load[2 * q] = true;  // literal streams are readable 31 bytes before and 16 after
-          x = h;
-        }
-        if (x < end) {  // match part
-          const uint32_t ii0 = x - (sd + L);
-          lo[2 * q + 1] = x - cb;
-          hi[2 * q + 1] = end - cb;
-          if (!(f & kUnres)) {
-            const uint64_t A = src_q[q] + ii0;
-            const uint64_t v = A - (x - cb);
-            const uint32_t wn = win_q[q], back = (wn & 31u) + ii0, fwd = (wn >> 5) - ii0;
-            const uint32_t need_back = x - cb;  // bytes read before the segment's source
-            ok = ok && ii0 + (end - x) <= d && need_back <= back && 16 - need_back <= fwd;
-            V[2 * q + 1] = v;
-            load[2 * q + 1] = true;
-          }
-          x = end;
-        }
-      }
-    }
-  }
-  if (!ok || x < cb + 16) return false;
-  uint4 wv[kC];
-#pragma unroll
-  for (uint32_t k = 0; k < kC; k++)
-    wv[k] = load[k] ? ld16u(reinterpret_cast<const uint8_t*>(V[k])) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-  for (uint32_t j = 0; j < 4; j++) out[j] = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < kC; k++) {
-    const uint32_t v4[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
-#pragma unroll
-    for (uint32_t j = 0; j < 4; j++) {
-      const uint32_t m = dword_mask(j, lo[k], hi[k]);
-      out[j] = (out[j] & ~m) | (v4[j] & m);
-    }
-  }
-  return true;
-}
-
 // Expands plan entry i with kThreads threads.  Sources in earlier blocks must
 // be complete and visible (unless ext_ok is false, after a timed-out wait).
 template <uint32_t kThreads>
 __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, ExpandSmem<kThreads>& sm,
                                              bool ext_ok = true) {
   constexpr uint32_t kSeq = ExpandSmem<kThreads>::kSeq, kRound = ExpandSmem<kThreads>::kRound;
-  constexpr uint32_t kSB = ExpandSmem<kThreads>::kSeqBits, kSM = (1u << kSB) - 1;
-  static_assert(kSeq <= (1u << kSB), "sequence index must fit its field");
   const uint32_t tid = threadIdx.x;
   const PlanEntry pe = a.plan[i];
   const uint32_t b = pe.block;
@@ -780,16 +759,14 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   const uint8_t* offs = pe.raw[2] != kCoded ? a.arch + pe.raw[2] : a.offs + (uint64_t)a.ow * pe.seq_base;
   c.offs = offs;
   c.ow = a.ow;
-  const bool aligned = (((uintptr_t)c.out) & 15) == 0;
   const bool cached = dep_cnt <= kDepCache;
   uint32_t carry_pos = 0, carry_lit = 0, n_ext = 0;
   bool bad = false;
-  // the chunk marks start cleared (each thread clears the entries it later
+  // the piece marks start cleared (each thread clears the entries it later
   // reads, right after reading them), ordered before the first marks by the
   // barriers of the token phase
 #pragma unroll
   for (uint32_t j = 0; j < 4; j++) sm.cseq[tid + j * kThreads] = 0;
-  if (tid == 0) sm.nbyte = 0;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kSeq) {
     // ---- two sequences per thread: tokens, scans, first classification
     uint32_t L[2] = {0, 0}, M[2] = {0, 0};
@@ -965,41 +942,56 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         fl_h[h] = nfl[h];
       }
     }
-    // slow sequences' match bytes, numbered: slot k's end in sm.ptr (the
-    // pointers are no longer needed)
-    uint32_t n_slow = 0;
+    const uint64_t d1w = (uint64_t)carry_pos + tp;
+    const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
+    // Output pieces: every sequence's literal run and its match (unless the
+    // match is slow) are cut into pieces of 16 bytes from their own start,
+    // the last one shorter; a poisoned sequence's bytes (clipped to the
+    // tile) are pieces of zeros.  Pieces write disjoint bytes, so they are
+    // spread over the threads in any order.  Slow sequences' match bytes
+    // are numbered for the slow pass: slot k's slow bytes end at sm.ptr[k]
+    // (the pointers are no longer needed), its pieces start at sm.pfx[k].
+    uint32_t n_slow = 0, n_piece = 0;
     {
-      uint32_t cv[4] = {(fl_h[0] & kSlow) ? M[0] : 0u, 0u, (fl_h[1] & kSlow) ? M[1] : 0u, 0u}, ct[4];
+      uint32_t np[2];
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        const uint32_t slot = tid + h * kThreads;
+        uint32_t n = 0;
+        if (slot < c.cnt) {
+          if (fl_h[h] & kPoison) {
+            const uint32_t ds = pos_h[h];
+            const uint64_t e = (uint64_t)ds + L[h] + M[h];
+            n = ds < d1 ? ((e < d1 ? (uint32_t)e : d1) - ds + 15) >> 4 : 0u;
+          } else {
+            n = ((L[h] + 15) >> 4) + ((fl_h[h] & kSlow) ? 0u : (M[h] + 15) >> 4);
+          }
+        }
+        np[h] = n;
+      }
+      uint32_t cv[4] = {(fl_h[0] & kSlow) ? M[0] : 0u, np[0], (fl_h[1] & kSlow) ? M[1] : 0u, np[1]}, ct[4];
       wg_scan4<kThreads>(cv, ct, sm.scan);
       sm.ptr[tid] = cv[0];
       sm.ptr[tid + kThreads] = ct[0] + cv[2];
+      sm.pfx[tid] = cv[1] - np[0];
+      sm.pfx[tid + kThreads] = ct[1] + cv[3] - np[1];
       n_slow = ct[0] + ct[2];
+      n_piece = ct[1] + ct[3];
       __syncthreads();
     }
-    const uint64_t d1w = (uint64_t)carry_pos + tp;
-    const uint32_t d1 = d1w < c.blen ? (uint32_t)d1w : c.blen;
-    // ---- output in 16-byte chunks, four per thread per round: copy chunks
-    // (one literal run, or one resolved match with no period wrap) are
-    // copied where they are
-    // classified; per-byte chunks are gathered in a list and spread over
-    // the threads, so a wavefront does not pay for both kinds of work
-    const uint32_t base = d0 & ~15u;
-    const uint32_t nch = d1 > base ? (d1 - base + 15) / 16 : 0;
+    // ---- pieces, four per thread per round: thread t takes pieces
+    // t + j * kThreads of the round.  Each sequence marks its first piece;
+    // a running maximum over the round's pieces gives every piece its
+    // sequence.  All four pieces' loads are issued before any is stored.
     uint32_t carry = 0;  // the last sequence marked in earlier rounds
-    for (uint32_t k0 = 0; k0 < nch; k0 += kRound) {
-      const uint32_t kn = nch - k0 < kRound ? nch - k0 : kRound;
-      // the sequence holding each chunk's first byte: every sequence marks
-      // the first chunk whose first byte is at or after its start, then a
-      // running maximum over the chunks fills the rest.  Thread t reads
-      // (and clears) the marks of chunks t + j * kThreads, the chunks it
-      // classifies, so the scan leaves each thread exactly its own values.
+    for (uint32_t p0 = 0; p0 < n_piece; p0 += kRound) {
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
         const uint32_t slot = tid + h * kThreads;
         if (slot < c.cnt) {
-          const uint32_t ds = sm.dst[slot];
-          const uint32_t cm = ds <= d0 ? 0u : (ds - base + 15) / 16;
-          if (cm >= k0 && cm < k0 + kn) atomicMax(&sm.cseq[cm - k0], slot);
+          const uint32_t f = sm.pfx[slot];
+          const uint32_t nxt = slot + 1 < c.cnt ? sm.pfx[slot + 1] : n_piece;
+          if (nxt > f && f >= p0 && f < p0 + kRound) sm.cseq[f - p0] = slot;
         }
       }
       __syncthreads();
@@ -1009,191 +1001,113 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         sqv[j] = sm.cseq[tid + j * kThreads];
         sm.cseq[tid + j * kThreads] = 0;
       }
-      // every thread read the previous round's count before the barrier
-      // above; this round's additions come after the scan's barrier
-      if (tid == 0) sm.nbyte = 0;
       carry = wg_max_scan_strided4<kThreads>(sqv, carry, sm.scan);
-      // Phase A (LDS only): classify this thread's four chunks (a copy chunk
-      // records its source; the others are appended to a list, one LDS
-      // atomic per wavefront) and, in the tile's last round, follow this
-      // thread's slow byte back to its source (a slow byte's source is never
-      // in this tile's output, so it can be read before the tile is done).
-      const bool fold = k0 + kRound >= nch;  // last round: slow bytes written here
-      // a copy chunk's 16 source bytes are loaded as soon as it is classified
-      // (one load at any byte alignment; other chunks read 16 bytes at c.lit,
-      // which is always readable), so the loads are in flight during the
-      // rest of the classification, the list barrier and the segment path
-      uint4 w[4];
-      uint32_t cbv[4];
+      uint4 v1[4], v2[4];
+      uint32_t dsto[4], len[4], sh1[4], n1[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
-        const uint32_t k = k0 + tid + j * kThreads;
-        const bool here = k < k0 + kn;
-        const uint32_t cb = base + 16 * k;
-        // branch-free: every LDS field the decision needs is read at once
-        // (sq is a valid slot even for chunks past the tile's end)
+        const uint32_t p = p0 + tid + j * kThreads;
+        const bool on = p < n_piece;
         const uint32_t sq = sqv[j] < c.cnt ? sqv[j] : c.cnt - 1;
-        const uint32_t dfl = sm.dfl[sq], sd = sm.dst[sq], lmv = sm.lm[sq], litv = sm.lit[sq];
-        const uint32_t sn = sm.dst[sq + 1 < kSeq ? sq + 1 : sq];
+        const uint32_t pf = sm.pfx[sq], ds = sm.dst[sq], lmv = sm.lm[sq], litv = sm.lit[sq];
+        const uint32_t dfl = sm.dfl[sq], wn = sm.win[sq];
         const uint64_t s0 = sm.src0[sq];
-        const uint32_t fl = dfl >> 24, Ls = lmv & 0xFFFFu;
-        const uint32_t end_s = sq + 1 < c.cnt ? sn : d1;
-        const uint32_t r0 = cb - sd, ii0 = r0 - Ls;  // used only when the chunk is whole
-        const bool whole = here && aligned && cb >= d0 && cb + 16 <= d1 && cb + 16 <= end_s && !(fl & kPoison);
-        // all literals (stream data has readable slack), or a resolved match
-        // with no period wrap inside the chunk (its 16 source bytes lie in
-        // the resolved span, which is readable)
-        const bool lit_ok = r0 + 16 <= Ls;
-        const bool mat_ok = r0 >= Ls && !(fl & kUnres) && ii0 + 16 <= (dfl & 0xFFFFFFu);
-        const bool vec = whole && (lit_ok || mat_ok);
-        const uint8_t* src = lit_ok ? c.lit + litv + r0 : reinterpret_cast<const uint8_t*>(s0 + ii0);
-        cbv[j] = vec ? cb : 0xFFFFFFFFu;
-        w[j] = ld16u(vec ? src : c.lit);  // c.lit is always readable
-        const bool byte = here && !vec;
-        const uint64_t mb = __builtin_amdgcn_ballot_w64(byte);
-        const uint32_t lane = tid & 63;
-        const uint32_t leader_b = mb ? (uint32_t)__builtin_ctzll(mb) : 64u;
-        uint32_t bb = 0;
-        if (lane == leader_b) bb = atomicAdd(&sm.nbyte, (uint32_t)__popcll(mb));
-        bb = (uint32_t)__builtin_amdgcn_readlane((int)bb, (int)(leader_b & 63));
-        const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-        if (byte) sm.list[bb + below_b] = (k << kSB) | sq;
-      }
-      uint32_t slow_p = 0xFFFFFFFFu;
-      const uint8_t* slow_a = nullptr;
-      if (fold && tid < n_slow) {
-        slow_p = slow_pos<kThreads>(sm, c, tid);
-        slow_a = resolve_addr<kThreads>(a, sm, c, slow_p, n_ext);
-      }
-      const uint32_t slow_v = slow_a ? (uint32_t)ld8(slow_a) : 0u;
-      __syncthreads();
-      const uint32_t nby = sm.nbyte;
-      // Phase B: the segment path's loads for this thread's first listed
-      // chunk, then the stores.
-      bool seg_done = false;
-      uint32_t seg_cb = 0, o4[4] = {0, 0, 0, 0};
-      if (tid < nby) {
-        const uint32_t e = sm.list[tid], k = e >> kSB;
-        seg_cb = base + 16 * k;
-        const uint32_t p0 = seg_cb < d0 ? d0 : seg_cb;
-        const uint32_t pe1 = seg_cb + 16 < d1 ? seg_cb + 16 : d1;
-        if (aligned && p0 == seg_cb && pe1 == seg_cb + 16)
-          seg_done = seg_chunk<kThreads>(sm, c, seg_cb, e & kSM, d1, o4);
-      }
-#pragma unroll
-      for (uint32_t j = 0; j < 4; j++)
-        if (cbv[j] != 0xFFFFFFFFu) st16(c.out + cbv[j], w[j]);
-      if (seg_done) st16(c.out + seg_cb, make_uint4(o4[0], o4[1], o4[2], o4[3]));
-      // per-byte path: listed chunks the segment path declined or that lie
-      // beyond the first kThreads entries.  Every byte's source address
-      // first, then the 16 loads back to back.  The current sequence's
-      // fields stay in registers (LDS is read only when the walk enters the
-      // next sequence), and match bytes step their source offset by one,
-      // wrapping at the period.  Bytes of slow sequences get a placeholder
-      // here; the slow bytes are written after the barrier below.
-      for (uint32_t ei = tid; ei < nby; ei += kThreads) {
-        if (ei == tid && seg_done) continue;
-        const uint32_t e = sm.list[ei], k = e >> kSB;
-        const uint32_t cb = base + 16 * k;
-        const uint32_t p0 = cb < d0 ? d0 : cb;
-        const uint32_t pe1 = cb + 16 < d1 ? cb + 16 : d1;
-        uint32_t s = e & kSM;
-        if (ei != tid && aligned && p0 == cb && pe1 == cb + 16) {
-          uint32_t q4[4];
-          if (seg_chunk<kThreads>(sm, c, cb, s, d1, q4)) {
-            st16(c.out + cb, make_uint4(q4[0], q4[1], q4[2], q4[3]));
-            continue;
-          }
-        }
-        uint32_t sd = 0, se = 0, sL = 0, sf = 0, sdist = 1, im = 0;
-        const uint8_t* litp = c.lit;
-        uint64_t src0 = 0;
-        bool started = false;
-        auto view = [&]() {
-          sd = sm.dst[s];
-          se = s + 1 < c.cnt ? sm.dst[s + 1] : d1;
-          sL = sm.lm[s] & 0xFFFFu;
-          sf = sm.dfl[s] >> 24;
-          sdist = sm.dfl[s] & 0xFFFFFFu;
-          litp = c.lit + sm.lit[s];
-          src0 = sm.src0[s];
-          started = false;
-        };
-        view();
-        // two halves of eight bytes (this path is rare; halves keep its
-        // registers below those of the main path)
-        uint32_t acc[4] = {0, 0, 0, 0};
-#pragma unroll 1
-        for (uint32_t hf = 0; hf < 2; hf++) {
-          const uint8_t* ad[8];
-          uint32_t zero = 0;
-#pragma unroll
-          for (uint32_t j = 0; j < 8; j++) {
-            const uint32_t p = cb + 8 * hf + j;
-            const uint8_t* q = nullptr;
-            if (p >= p0 && p < pe1) {
-              while (p >= se) {
-                s++;
-                view();
-              }
-              const uint32_t r = p - sd;
-              if (sf & kPoison) {
-                q = nullptr;  // a format rule failed: write zeros, read nothing
-              } else if (r < sL) {
-                q = litp + r;
-              } else if (!(sf & kUnres)) {
-                if (!started) {
-                  const uint32_t ii = r - sL;
-                  im = ii < sdist ? ii : ii % sdist;
-                  started = true;
-                } else if (++im == sdist) {
-                  im = 0;
-                }
-                q = reinterpret_cast<const uint8_t*>(src0 + im);
-              }
-            }
-            zero |= (q == nullptr ? 1u : 0u) << j;
-            ad[j] = q == nullptr ? c.lit : q;  // c.lit is always readable
-          }
-          uint32_t lo4 = 0, hi4 = 0;
-#pragma unroll
-          for (uint32_t j = 0; j < 8; j++) {
-            const uint32_t v = (zero >> j) & 1u ? 0u : (uint32_t)ld8(ad[j]);
-            if (j < 4) lo4 |= v << (8 * j);
-            else hi4 |= v << (8 * (j - 4));
-          }
-          acc[2 * hf] = lo4;
-          acc[2 * hf + 1] = hi4;
-        }
-        if (aligned && p0 == cb && pe1 == cb + 16) {
-          st16(c.out + cb, make_uint4(acc[0], acc[1], acc[2], acc[3]));
+        const uint32_t Ls = lmv & 0xFFFFu, Ms = lmv >> 16, fl = dfl >> 24, dist = dfl & 0xFFFFFFu;
+        const uint32_t k = on ? p - pf : 0u;
+        const uint32_t pl = (Ls + 15) >> 4;
+        // the piece: output offset, length, and where its bytes come from
+        const uint8_t* A1 = c.lit;  // readable: the literal stream has slack around it
+        const uint8_t* A2 = c.lit;
+        uint32_t off, r, s1 = 0, m1 = 16;
+        bool zero = !on || (fl & kPoison);
+        if ((fl & kPoison) || k < pl) {
+          off = 16 * k;
+          const uint32_t tot = (fl & kPoison) ? (d1 - ds < Ls + Ms ? d1 - ds : Ls + Ms) : Ls;
+          r = tot - off < 16 ? tot - off : 16;
+          A1 = c.lit + litv + off;
+          dsto[j] = ds + off;
         } else {
-#pragma unroll
-          for (uint32_t j = 0; j < 16; j++)
-            if (cb + j >= p0 && cb + j < pe1) st8(c.out + cb + j, (uint8_t)(acc[j >> 2] >> (8 * (j & 3))));
+          off = 16 * (k - pl);
+          r = Ms - off < 16 ? Ms - off : 16;
+          dsto[j] = ds + Ls + off;
+          // match byte i reads span byte i mod d; a piece runs up to the
+          // period's end (m1 bytes) and the rest restarts at the span start
+          const bool wrap = Ms > dist;
+          const uint32_t at = wrap ? off % dist : off;
+          m1 = wrap && dist - at < r ? dist - at : r;
+          // readable bytes around the span start: back (<= 31), forward
+          const uint32_t back = wn & 31u, fwd = wn >> 5;
+          const uint32_t need = at + 16 > fwd ? at + 16 - fwd : 0u;  // shift the load back this far
+          s1 = need;
+          A1 = reinterpret_cast<const uint8_t*>(s0 + at - need);
+          A2 = reinterpret_cast<const uint8_t*>(s0);
+          if (need > back + at || (wrap && dist < 16) || (m1 < r && fwd < 16)) {
+            // a window too small for 16-byte loads, or a period shorter
+            // than a piece: this piece goes byte by byte below
+            s1 = 0xFFu;
+            A1 = c.lit;
+            A2 = c.lit;
+          }
+        }
+        len[j] = on ? r : 0u;
+        sh1[j] = zero ? 0u : s1;
+        n1[j] = m1;
+        v1[j] = ld16u(zero || s1 == 0xFFu ? c.lit : A1);
+        v2[j] = ld16u(zero || s1 == 0xFFu || m1 >= r ? c.lit : A2);
+        if (zero) sh1[j] = 0x100u;  // zeros
+        if (s1 == 0xFFu && !zero) {
+          // byte by byte (rare): span byte (at + i) mod d for each piece byte
+          const uint32_t at0 = Ms > dist ? off % dist : off;
+          uint32_t w[4] = {0, 0, 0, 0};
+          uint32_t ii = at0;
+          for (uint32_t b2 = 0; b2 < 16; b2++) {
+            if (b2 < r) w[b2 >> 2] |= (uint32_t)ld8(reinterpret_cast<const uint8_t*>(s0 + ii)) << (8 * (b2 & 3));
+            ii = (Ms > dist && ii + 1 == dist) ? 0u : ii + 1;
+          }
+          v1[j] = make_uint4(w[0], w[1], w[2], w[3]);
+          sh1[j] = 0;
+          n1[j] = 16;
         }
       }
-      // the slow bytes loaded above, after every chunk store of the tile
-      // (only its last round resolves them).  The list and the marks are
-      // next written after the next round's first barrier.
-      if (fold) {
-        __syncthreads();
-        if (slow_p != 0xFFFFFFFFu) st8(c.out + slow_p, (uint8_t)slow_v);
+      // assemble and store: bytes [0, n1) from the first load (shifted down
+      // by sh1), the rest from the second; exactly len bytes written
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        if (!len[j]) continue;
+        uint32_t w[4];
+        if (sh1[j] == 0x100u) {
+          w[0] = w[1] = w[2] = w[3] = 0u;
+        } else {
+          uint32_t x1[4] = {v1[j].x, v1[j].y, v1[j].z, v1[j].w};
+          shift_down16(x1, sh1[j]);
+          if (n1[j] < len[j]) {
+            uint32_t x2[4] = {v2[j].x, v2[j].y, v2[j].z, v2[j].w};
+            shift_up16(x2, n1[j]);
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+              const uint32_t m = dword_mask(q, 0, n1[j]);
+              x1[q] = (x1[q] & m) | (x2[q] & ~m);
+            }
+          }
+          w[0] = x1[0];
+          w[1] = x1[1];
+          w[2] = x1[2];
+          w[3] = x1[3];
+        }
+        store_bytes(c.out + dsto[j], w, len[j]);
       }
+      __syncthreads();  // the marks of the next round are written after every read of this one
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
     // sequences, tiles or non-adjacent blocks), one byte per thread, each
-    // followed back to its origin
-    const uint32_t slow_from = nch > 0 ? kThreads : 0u;  // the first ones went with the last round
-    if (n_slow > slow_from) {
-      __syncthreads();  // after every chunk store (placeholders included)
-      for (uint32_t u = slow_from + tid; u < n_slow; u += kThreads) {
-        const uint32_t p = slow_pos<kThreads>(sm, c, u);
-        const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
-        st8(c.out + p, q ? ld8(q) : (uint8_t)0);
-      }
-      __syncthreads();
+    // followed back to its origin (never to this tile's output)
+    for (uint32_t u = tid; u < n_slow; u += kThreads) {
+      const uint32_t p = slow_pos<kThreads>(sm, c, u);
+      const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
+      st8(c.out + p, q ? ld8(q) : (uint8_t)0);
     }
+    // the next tile reads this tile's output and rewrites the tables
+    if (t0 + kSeq < n_seq) __syncthreads();
     carry_pos = (uint32_t)(d1w > 0xFFFFFFFFull ? 0xFFFFFFFFu : d1w);
     carry_lit += tl;
     if ((uint64_t)carry_pos > c.blen) {
@@ -1218,195 +1132,149 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 template <uint32_t kThreads>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
   __shared__ ExpandSmem<kThreads> sm;
-  uint32_t i = plan_lo + blockIdx.x;
-  if (level >= 0) {
-    i = a.lvl_dev[level] + blockIdx.x;
-    if (i >= a.lvl_dev[level + 1]) return;
+  auto one = [&](uint32_t i) {
+    const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
+    expand_block<kThreads>(a, i, sm);
+    if (a.trace && threadIdx.x == 0) {
+      a.trace[8ull * i] = c0;
+      a.trace[8ull * i + 1] = (unsigned long long)wall_clock64();
+    }
+  };
+  if (level < 0) {  // host-planned: one block per workgroup
+    one(plan_lo + blockIdx.x);
+    return;
   }
-  const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
-  expand_block<kThreads>(a, i, sm);
-  if (a.trace && threadIdx.x == 0) {
-    a.trace[8ull * i] = c0;
-    a.trace[8ull * i + 1] = (unsigned long long)wall_clock64();
+  // device-planned: the level's plan range from device memory, strided
+  const uint32_t lo = a.lvl_dev[level], hi = a.lvl_dev[level + 1];
+  for (uint32_t i = lo + blockIdx.x; i < hi; i += gridDim.x) {
+    one(i);
+    __syncthreads();  // every thread done with this block's LDS tables
   }
 }
 
 // ---------------------------------------------------------------------------
-// Kernel (c): one persistent launch decodes a whole plan, level by level,
-// driven by counters in device memory: for each dependency level, how many
-// of its blocks have been claimed for expansion and how many are finished;
-// one counter of entropy decodes claimed (in plan order, so lower levels
-// first) and one completion flag per plan entry.
+// Kernel (c): one persistent launch expands a whole plan, level by level
+// (the entropy layer of every planned block is decoded by kernel (a) just
+// before it), with device-side counters.
 //
-// A workgroup expands blocks of the lowest level it has not yet seen
-// finish, and moves on to the next level once that level's finished count
-// reaches its size.  A block's dependencies all sit at lower levels, so
-// every block it expands finds the blocks it copies from complete.  When no
-// block of its level is left to claim, it entropy-decodes the next plan
-// entry instead, so the entropy layer of later levels runs under the
-// expansion of earlier ones (and an expansion whose streams are not decoded
-// yet decodes queued entries until they are).  Work is only ever claimed by
-// running workgroups and nothing claimed waits on anything claimed later, so
-// the launch needs no co-residency and no workgroup count.
+// A level's blocks are dealt into kPersistSlices slices (block j of the level
+// to slice j mod kPersistSlices), each with its own claim counter on its own
+// cache line.  Workgroup w claims from slice w mod kPersistSlices (its home:
+// with workgroups dealt round-robin over the XCDs, one slice per XCD), and
+// once that is empty from the others in turn, so no single address takes
+// every claim.  The next claim on the home slice is issued before the claimed
+// block's expansion and its result used after it, which hides the atomic's
+// round trip.  When no slice has blocks left, the workgroup adds the count it
+// expanded to the level's finished count (one atomic per workgroup and
+// level); the workgroup whose add completes the level raises the count of
+// finished levels held in kPersistReplicas copies, one per 128-byte line, and
+// each workgroup polls the copy w mod kPersistReplicas until it passes the
+// level, so idle polling is spread over many lines.  Empty levels are
+// skipped.  A block's dependencies all sit at lower levels, so every block
+// expanded finds its sources complete.  A workgroup waits only after every
+// block of the level is claimed, i.e. held by a running workgroup: the launch
+// needs no co-residency, and drains when it shares the device.
 //
-// Cross-workgroup visibility: a finished item is published by every wave
-// issuing an agent-scope release fence (its own stores done, this XCD's L2
-// written back), then a barrier, then one atomic increment or store; the
-// consumer polls counters and flags with agent-scope atomic loads and issues
-// an agent-scope acquire fence in every wave before it reads the published
-// bytes.
+// Visibility across workgroups: every wave of a workgroup issues an
+// agent-scope release fence (its stores complete, this XCD's L2 written
+// back) before the barrier that precedes the workgroup's finished-count add;
+// the copies are raised by atomic max after that add.  A waiting workgroup
+// polls with agent-scope atomic loads, then every wave issues an agent-scope
+// acquire fence before it reads lower levels' bytes.
 //
-// Every wait is bounded by a count of consecutive idle polls (not by a
-// clock).  An expired wait flags kErrTimeout and the workgroup stops waiting
-// from then on, as does every workgroup that sees that flag: levels are
-// skipped when not finished and expansions no longer read earlier blocks,
-// so the launch always drains (its output is then not valid, and ace_check
-// reports the timeout).
+// Every wait is bounded by a count of idle polls (not by a clock).  An
+// expired wait flags kErrTimeout and the workgroup stops waiting from then
+// on, as does every workgroup that sees that flag (checked every 256 idle
+// polls); expansions then no longer read earlier blocks, so the launch always
+// drains (its output is then not valid, and ace_check reports the timeout).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPersistThreads = 128;
+constexpr uint32_t kNoItem = 0xffffffffu;
 
-union PersistSmem {
-  ExpandSmem<kPersistThreads> e;
-  RansGroup<64> r[kPersistThreads / 64];
-};
-
-// A counter or flag shared across workgroups, read at agent scope.
+// A counter shared across workgroups, read at agent scope.
 __device__ __forceinline__ uint32_t coherent_u32(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Every wave of the workgroup: its earlier stores complete and visible at
-// agent scope; then all waves meet.
-__device__ __forceinline__ void publish_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-}
-__device__ __forceinline__ void acquire_all() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// Entropy decode of plan entry i's rANS-coded streams (raw streams are read
-// in place by the expansion): wave 0 decodes LIT, wave 1 LEN then OFF.  Also
-// records where the block's bytes will live.
-__device__ void persist_entropy(const DecodeArgs& a, uint32_t i, PersistSmem& sm) {
-  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const PlanEntry* pp = a.plan + i;
-  const uint32_t blk = pp->block, seq_base = pp->seq_base;
-  const uint64_t pdst = pp->dst, pay = pp->pay;
-  if (threadIdx.x == 0) a.loc[blk] = a.dst_base + pdst;
-  const uint32_t t_lo = w == 0 ? 0u : 1u, t_hi = w == 0 ? 1u : 3u;
-  for (uint32_t t = t_lo; t < t_hi; t++) {
-    if (pp->raw[t] != kCoded) continue;  // wave-uniform
-    const uint8_t* d = a.arch + pay + kSDesc * t;
-    const uint32_t n = ld32(d + 4), clen = ld32(d + 8), off = ld32(d + 12);
-    uint8_t* dst = t == 0 ? a.lit + (uint64_t)i * a.B
-                 : t == 1 ? a.lens + 4ull * seq_base
-                          : a.offs + (uint64_t)a.ow * seq_base;
-    const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
-    if (rans_decode_group<64>(a.arch + pay + off, clen, n, a.W, dst, sm.r[w], lane, 0, true) && lane == 0)
-      flag(a.err, kErrCorrupt);
-    if (a.trace && lane == 0) {
-      a.trace[8ull * i + 2 + 2 * t] = c0;
-      a.trace[8ull * i + 3 + 2 * t] = (unsigned long long)wall_clock64();
-    }
+// Blocks of a level of `size` blocks in slice r.
+__device__ __forceinline__ uint32_t slice_size(uint32_t size, uint32_t r) {
+  return size > r ? (size - 1 - r) / kPersistSlices + 1 : 0u;
+}
+
+// A claim from any slice with blocks left, starting at slice `first`
+// (thread 0 only): the plan entry, or kNoItem when every slice is empty.
+__device__ uint32_t claim_any(const DecodeArgs& a, uint32_t lvl, uint32_t lo, uint32_t size, uint32_t first) {
+  for (uint32_t k = 0; k < kPersistSlices; k++) {
+    const uint32_t r = (first + k) % kPersistSlices, n_r = slice_size(size, r);
+    uint32_t* c = a.lvl_claim + (uint64_t)r * a.lvl_row + lvl;
+    if (coherent_u32(c) >= n_r) continue;
+    const uint32_t t = atomicAdd(c, 1u);
+    if (t < n_r) return lo + r + t * kPersistSlices;
   }
+  return kNoItem;
 }
 
-__global__ __launch_bounds__(kPersistThreads) void k_persist(DecodeArgs a) {
-  __shared__ PersistSmem sm;
-  __shared__ uint32_t sh_kind, sh_item, sh_give_up;
-  enum : uint32_t { kExit, kExpand, kEntropy, kNextLevel, kIdle };
-  const uint32_t tid = threadIdx.x;
-  const uint32_t n_plan = a.n_plan_dev ? *a.n_plan_dev : a.n_plan;
-  uint32_t lvl = 0, idle = 0;  // thread 0's view
-  bool give_up = false;
-  if (tid == 0) sh_give_up = 0;
-  // thread 0 decides the next step for the whole workgroup; entropy items
-  // are taken from the shared queue in plan order
-  auto take_entropy = [&](uint32_t& k) -> bool {
-    if (__hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n_plan) return false;
-    k = atomicAdd(a.queue, 1u);
-    return k < n_plan;
-  };
-  auto idle_poll = [&]() {
-    // back off while idle (the counters polled are shared by every workgroup)
-    if (idle < 16) __builtin_amdgcn_s_sleep(2);
-    else __builtin_amdgcn_s_sleep(16);
-    if (++idle > a.max_polls || (coherent_u32(a.err) & kErrTimeout)) {
-      if (!give_up) flag(a.err, kErrTimeout);
-      give_up = true;
+__global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_persist(DecodeArgs a) {
+  __shared__ ExpandSmem<kPersistThreads> sm;
+  __shared__ uint32_t sh_item[2], sh_give_up;
+  const uint32_t tid = threadIdx.x, home = blockIdx.x % kPersistSlices;
+  uint32_t* seen = a.lvl_seen + (blockIdx.x % kPersistReplicas) * kPersistLine;
+  bool give_up = false;  // thread 0's view, broadcast after every wait
+  for (uint32_t lvl = 0; lvl < a.n_lvl; lvl++) {
+    const uint32_t lo = a.lvl_dev[lvl], size = a.lvl_dev[lvl + 1] - lo;
+    if (size == 0) continue;
+    const uint32_t n_home = slice_size(size, home);
+    uint32_t* home_claim = a.lvl_claim + (uint64_t)home * a.lvl_row + lvl;
+    if (tid == 0) sh_item[0] = claim_any(a, lvl, lo, size, home);
+    __syncthreads();
+    uint32_t item = sh_item[0], par = 0, mine = 0;
+    while (item != kNoItem) {
+      uint32_t next = kNoItem;
+      if (tid == 0) next = atomicAdd(home_claim, 1u);  // result used after the expansion
+      const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
+      expand_block<kPersistThreads>(a, item, sm, !give_up);
+      if (a.trace && tid == 0) {
+        a.trace[8ull * item] = c0;
+        a.trace[8ull * item + 1] = (unsigned long long)wall_clock64();
+      }
+      mine++;
+      if (tid == 0)
+        sh_item[par ^ 1] = next < n_home ? lo + home + next * kPersistSlices : claim_any(a, lvl, lo, size, home + 1);
+      __syncthreads();  // every thread done with this block's LDS tables; next item visible
+      par ^= 1;
+      item = sh_item[par];
     }
-  };
-  auto run_entropy = [&](uint32_t k) {
-    persist_entropy(a, k, sm);
-    publish_barrier();
-    if (tid == 0) __hip_atomic_store(a.done + k, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
-  for (;;) {
-    if (tid == 0) {
-      uint32_t kind = kIdle, item = 0;
-      if (lvl >= a.n_lvl) {
-        kind = kExit;
-      } else {
-        const uint32_t lo = a.lvl_dev[lvl], hi = a.lvl_dev[lvl + 1], size = hi - lo;
-        if (__hip_atomic_load(a.lvl_claim + lvl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < size) {
-          const uint32_t j = atomicAdd(a.lvl_claim + lvl, 1u);
-          if (j < size) {
-            kind = kExpand;
-            item = lo + j;
-          }
+    if (mine) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid < kPersistReplicas) {  // wave 0: lane r raises copy r
+        uint32_t prev = 0;
+        if (tid == 0) prev = atomicAdd(a.lvl_done + lvl, mine);
+        prev = __shfl(prev, 0);
+        if (prev + mine == size) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+          __hip_atomic_fetch_max(a.lvl_seen + tid * kPersistLine, lvl + 1, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (kind == kIdle) {
-          if (give_up || coherent_u32(a.lvl_done + lvl) >= size) kind = kNextLevel;
-          else if (take_entropy(item)) kind = kEntropy;
+        __builtin_amdgcn_wave_barrier();  // the wave's raises come before lane 0's wait
+      }
+    }
+    if (tid == 0) {
+      uint32_t idle = 0;
+      while (!give_up && coherent_u32(seen) <= lvl) {
+        if (idle < 16) __builtin_amdgcn_s_sleep(4);
+        else __builtin_amdgcn_s_sleep(32);
+        ++idle;
+        if (idle > a.max_polls || ((idle & 255u) == 0 && (coherent_u32(a.err) & kErrTimeout))) {
+          flag(a.err, kErrTimeout);
+          give_up = true;
         }
       }
-      if (kind == kIdle) idle_poll();
-      else idle = 0;
-      sh_kind = kind;
-      sh_item = item;
       sh_give_up = give_up ? 1u : 0u;
     }
     __syncthreads();
-    const uint32_t kind = sh_kind, item = sh_item;
-    const bool stop_waiting = sh_give_up != 0;
-    __syncthreads();
-    if (kind == kExit) break;
-    if (kind == kNextLevel) {
-      acquire_all();
-      if (tid == 0) lvl++;
-      continue;
-    }
-    if (kind == kEntropy) {
-      run_entropy(item);
-      continue;
-    }
-    if (kind != kExpand) continue;
-    // the entry's streams must be decoded: decode queued entries (plan order
-    // reaches this one) until its flag is set
-    for (;;) {
-      if (tid == 0) {
-        uint32_t st = kIdle, k = 0;
-        if (give_up || coherent_u32(a.done + item) == a.epoch) st = kExpand;
-        else if (take_entropy(k)) st = kEntropy;
-        if (st == kIdle) idle_poll();
-        else idle = 0;
-        sh_kind = st;
-        sh_item = k;
-        sh_give_up = give_up ? 1u : 0u;
-      }
-      __syncthreads();
-      const uint32_t st = sh_kind, k = sh_item;
-      __syncthreads();
-      if (st == kExpand) break;
-      if (st == kEntropy) run_entropy(k);
-    }
-    acquire_all();
-    const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
-    expand_block<kPersistThreads>(a, item, sm.e, !(stop_waiting || sh_give_up));
-    if (a.trace && tid == 0) {
-      a.trace[8ull * item] = c0;
-      a.trace[8ull * item + 1] = (unsigned long long)wall_clock64();
-    }
-    publish_barrier();
-    if (tid == 0) atomicAdd(a.lvl_done + lvl, 1u);
+    give_up = sh_give_up != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
 }
 
@@ -1536,6 +1404,9 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
 
 }  // namespace
 
+// Grid caps of launches whose plan length is read on the device.
+constexpr uint32_t kStrideGridRans = 4096, kStrideGridExpand = 2048;
+
 // Entropy launch over plan entries [lo, hi), or (lv_lo >= 0) over the plan
 // range of levels [lv_lo, lv_hi) read from device memory, with hi - lo
 // entries of capacity.
@@ -1544,10 +1415,16 @@ static hipError_t launch_rans_any(const DecodeArgs& a, uint32_t lo, uint32_t hi,
   if (hi <= lo) return hipSuccess;
   const uint32_t n = hi - lo;
   if (per_wave == 0) per_wave = a.W <= 32 ? 2 : 1;
-  if (per_wave == 2 && a.W <= 32)
-    hipLaunchKernelGGL(k_rans<32>, dim3((n + 1) / 2, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
+  const bool two = per_wave == 2 && a.W <= 32;
+  uint32_t grid = two ? (n + 1) / 2 : n;
+  // a plan whose length is read on the device is covered by striding over a
+  // grid the device holds at once, not by one wavefront per possible entry
+  const bool dev = lv_lo >= 0 || a.n_plan_dev;
+  if (dev && grid > kStrideGridRans) grid = kStrideGridRans;
+  if (two)
+    hipLaunchKernelGGL(k_rans<32>, dim3(grid, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
   else
-    hipLaunchKernelGGL(k_rans<64>, dim3(n, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
+    hipLaunchKernelGGL(k_rans<64>, dim3(grid, 3), dim3(64), 0, s, a, lo, hi, lv_lo, lv_hi);
   return hipGetLastError();
 }
 
@@ -1614,7 +1491,10 @@ hipError_t launch_rans_levels_dev(const DecodeArgs& a, uint32_t lv_lo, uint32_t 
 
 hipError_t launch_expand_level_dev(const DecodeArgs& a, uint32_t level, uint32_t width, uint32_t waves,
                                    hipStream_t s) {
-  return launch_expand(a, width, 0u, (int)level, waves, s);
+  // strided over at most as many workgroups as the device holds at once
+  const uint32_t r4 = expand4_resident();
+  const uint32_t cap = r4 ? 2 * r4 : kStrideGridExpand;
+  return launch_expand(a, width < cap ? width : cap, 0u, (int)level, waves, s);
 }
 
 hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s) {

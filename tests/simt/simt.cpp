@@ -446,3 +446,11 @@ hipError_t hipGraphDestroy(hipGraph_t g) {
   delete g;
   return hipSuccess;
 }
+
+// A stream for callers of the CPU build that need one of their own (graph
+// capture refuses the null stream).
+extern "C" void* simt_stream_create() {
+  hipStream_t s = nullptr;
+  hipStreamCreate(&s);
+  return s;
+}

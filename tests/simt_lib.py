@@ -40,6 +40,12 @@ def lib():
         L.ace_seek_batch.argtypes = [vp, vp, u32, vp, vp, vp, u64, C.POINTER(Tuning), vp]
         L.ace_check.argtypes = [vp, vp]
         L.ace_read_counters.argtypes = [vp, vp, u64p]
+        L.ace_batch_workspace_bytes.argtypes = [vp, u32, u64p]
+        L.ace_batch_create.argtypes = [vp, u32, vp, u64, C.POINTER(Tuning), vp, C.POINTER(vp)]
+        L.ace_batch_run.argtypes = [vp, vp, u32, vp, vp]
+        L.ace_batch_destroy.argtypes = [vp]
+        L.ace_batch_destroy.restype = None
+        L.simt_stream_create.restype = vp
         _lib = L
     return _lib
 
@@ -108,3 +114,27 @@ class Archive:
         _check(lib().ace_seek(self._h, lo, hi, _p(out), _p(ws), ws.size, t, None))
         _check(lib().ace_check(_p(ws), None))
         return out[:hi - lo].tobytes()
+
+
+def seek_batch_graph(arc, lo, hi, tuning=None):
+    """The requests [lo_i, hi_i) through a captured batch graph (ace_batch_*),
+    replayed twice; returns each request's bytes from the second replay."""
+    L = lib()
+    n = len(lo)
+    b = C.c_uint64(0)
+    _check(L.ace_batch_workspace_bytes(arc._h, n, C.byref(b)))
+    ws = np.zeros(b.value, dtype=np.uint8)
+    h = C.c_void_p()
+    t = C.byref(Tuning(**tuning)) if tuning else None
+    _check(L.ace_batch_create(arc._h, n, _p(ws), ws.size, t, C.c_void_p(L.simt_stream_create()), C.byref(h)))
+    r = np.empty(2 * n, dtype=np.uint64)
+    r[0::2], r[1::2] = lo, hi
+    ln = (np.asarray(hi, dtype=np.int64) - np.asarray(lo, dtype=np.int64))
+    offs = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
+    out = np.zeros(max(int(ln.sum()), 1), dtype=np.uint8)
+    for _ in range(2):
+        out[:] = 0
+        _check(L.ace_batch_run(h, _p(r), n, _p(out), _p(offs)))
+    _check(L.ace_check(_p(ws), None))
+    L.ace_batch_destroy(h)
+    return [out[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs, ln)]

@@ -44,6 +44,10 @@ lo, hi = n // 3, n // 3 + 2 * B + 17
 assert arc.seek(lo, hi, dict(mode=mode)) == x[lo:hi], "seek differs from the original"
 if n <= (4 << 20):
     assert oracle.decode(a) == x, "the oracle disagrees"
+    # a captured batch graph (device-side planning, strided launches), replayed
+    lo_r, hi_r = gen.seek_requests(n, 9, 3, max_len=3 * B)
+    got_b = simt_lib.seek_batch_graph(arc, lo_r, hi_r, dict(mode=mode if mode != 3 else 1))
+    assert all(g == x[int(l):int(h)] for g, l, h in zip(got_b, lo_r, hi_r)), "batch graph differs"
 print("OK", arc.n_blocks, arc.depth)
 """
 
