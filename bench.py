@@ -425,6 +425,19 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
         plain_ok = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x_dev[int(lo[i]):int(hi[i])]))
                        for i in range(n_plain))
         plain_rate = n_plain / sum(lat)
+        # where a plain seek's time goes, on the first requests again: host
+        # planning and enqueueing (library clocks), device phases (events)
+        ace.set_timing(True)
+        plan_us, enq_us, dev_ms = [], [], []
+        for i in range(min(n_plain, 300)):
+            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning)
+            torch.cuda.synchronize()
+            p_us, e_us = ace.last_host_times()
+            e_ms, m_ms = ace.last_timings()
+            plan_us.append(p_us)
+            enq_us.append(e_us)
+            dev_ms.append(e_ms + m_ms)
+        ace.set_timing(False)
         result["seek"] = {
             "workload": "%d seeks on the resident archive, length log-uniform 1 B..4 MiB, uniform "
                         "offsets (seed 4)" % n_req,
@@ -436,10 +449,16 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
             "plain_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
             "plain_req_per_s": round(plain_rate, 1), "plain_outputs_equal_original": plain_ok,
             "batched_vs_plain_throughput": round((n_req / tb) / plain_rate, 1),
+            "plain_host_plan_us_p50": round(float(np.median(plan_us)), 1),
+            "plain_host_enqueue_us_p50": round(float(np.median(enq_us)), 1),
+            "plain_device_ms_p50": round(float(np.median(dev_ms)), 4),
+            "plain_plan_share_of_p50": round(float(np.median(plan_us)) * 1e-3 / float(np.percentile(lat, 50)), 4),
         }
         _log("seek: batch of %d in %.3f ms (%.0f req/s, all outputs equal: %s); plain p50 %.3f ms "
-             "p99 %.3f ms (%.0f req/s)" % (n_req, 1e3 * tb, n_req / tb, good, result["seek"]["plain_p50_ms"],
-                                           result["seek"]["plain_p99_ms"], plain_rate))
+             "p99 %.3f ms (%.0f req/s; host planning p50 %.1f us, enqueue %.1f us, device %.3f ms)" % (
+                 n_req, 1e3 * tb, n_req / tb, good, result["seek"]["plain_p50_ms"],
+                 result["seek"]["plain_p99_ms"], plain_rate, result["seek"]["plain_host_plan_us_p50"],
+                 result["seek"]["plain_host_enqueue_us_p50"], result["seek"]["plain_device_ms_p50"]))
         del out
         torch.cuda.empty_cache()
 
@@ -480,7 +499,7 @@ def serve_main(args):
 
     import gen
     from paper_2606_24531_amd import Archive, encode
-    from paper_2606_24531_amd.serve import GpuBackend, Server, latency_report, poisson_run
+    from paper_2606_24531_amd.serve import GpuBackend, Server, latency_report, limiter, poisson_run
 
     sizes = {"genome": 4 << 30, "fastq": 2 << 30, "text": 1 << 30, "mixed": 1 << 30}
     seeds = {"genome": 51, "fastq": 52, "text": 53, "mixed": 3}
@@ -499,25 +518,38 @@ def serve_main(args):
     rates = [float(r) for r in args.serve_rates.split(",")]
     runs = []
     keep = args.serve_keep if args.serve_keep >= 0 else None
-    backend = GpuBackend(arcs, slots=4, keep_levels=keep, max_batch=4096)
+    budget = 32 << 30
+    backend = GpuBackend(arcs, slots=4, keep_levels=keep, max_batch=4096, batch_bytes=budget)
+    dev_bytes = backend.device_bytes()
+    _log("device memory held by the server: %s, output budget %d" % (dev_bytes, budget))
     for rate in rates:
-        srv = Server(backend, budget_bytes=32 << 30, slots=4, max_batch=4096)
+        # every 97th result is checked against the oracle's seek of the
+        # compressed archive after the run; results are released as they
+        # complete, which returns their bytes to the budget
+        sample = {}
+        srv = Server(backend, budget_bytes=budget, slots=4, max_batch=4096, auto_release=True,
+                     on_done=lambda r: r.rid % 97 == 0 and sample.__setitem__(r.rid, r.result.cpu()))
         reqs, wall = poisson_run(srv, list(arcs), n_total, rate=rate, count=args.serve_count,
                                  seed=int(rate), min_len=16, max_len=16 << 20)
         torch.cuda.synchronize()
         rep = latency_report(reqs, wall)
-        rep.update(offered_req_per_s=rate, batches=srv.batches,
-                   peak_out_bytes=srv.peak_used)
+        ok = True
+        for r in reqs:
+            if r.rid in sample:
+                solo = arcs[r.archive].seek(r.lo, r.hi)
+                ok = ok and bool(torch.equal(solo.cpu(), sample[r.rid]))
+        rep.update(offered_req_per_s=rate, batches=srv.batches, peak_out_bytes=srv.peak_used,
+                   sampled_results_equal_solo_seek=ok, n_sampled=len(sample), **limiter(srv))
         runs.append(rep)
-        _log("rate %.0f/s: p50 %.3f ms p99 %.3f ms, %.0f req/s" % (rate, rep["p50_ms"], rep["p99_ms"],
-                                                                  rep["req_per_s"]))
+        _log("rate %.0f/s: p50 %.3f ms p99 %.3f ms, %.0f req/s, limiter %s" % (
+            rate, rep["p50_ms"], rep["p99_ms"], rep["req_per_s"], rep["limiter"]))
     print(json.dumps({
         "metric": "seek latency p50/p99 vs throughput (serving loop)", "unit": "ms",
         "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
         "config": {"workload": "resident genome/fastq/text/mixed archives at %.4g of 4/2/1/1 GiB, "
                                "Poisson arrivals, 16 B..16 MiB log-uniform, 32 GiB budget, 4 slots"
                                % args.serve_scale,
-                   "kept_levels": keep},
+                   "kept_levels": keep, "output_budget_bytes": budget, "device_bytes": dev_bytes},
         "runs": runs}), flush=True)
 
 

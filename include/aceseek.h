@@ -148,6 +148,13 @@ int ace_archive_attach_plan(ace_archive* a, void* d_plan, uint64_t bytes, void* 
 int ace_workspace_bytes(const ace_archive* a, const ace_range* ranges, uint32_t n_ranges,
                         uint64_t* bytes);
 
+/* An upper bound of ace_workspace_bytes over every set of at most n_ranges
+ * ranges whose lengths add up to at most total_bytes (every block in the
+ * closure and decoded into a slot), so that a caller can allocate one
+ * workspace before any request is known. */
+int ace_workspace_bound(const ace_archive* a, uint32_t n_ranges, uint64_t total_bytes,
+                        uint64_t* bytes);
+
 /* Whole-archive decode (Section 2: every block, both layers, each after the
  * earlier blocks it copies from; Section 7: decode of a whole block range):
  * writes n_total bytes at d_out (out_cap >= n_total).  The workspace needs
@@ -251,6 +258,13 @@ int ace_set_timing(int on);
  * bytes / 64 fails with ACE_E_NOSPACE.  The caller owns the buffer. */
 int ace_set_block_trace(void* d_trace, uint64_t bytes);
 int ace_last_timings(float* ms_entropy, float* ms_match);
+
+/* Host time of the last timed decode or seek on the calling thread (phase
+ * timing on), in microseconds: planning (from the call's entry to its first
+ * enqueue: range closure, level order, plan entries, workspace layout) and
+ * enqueueing (plan upload and launches; the device work is not waited for).
+ * ACE_E_ARG when no timed call has run on this thread. */
+int ace_last_host_times(double* us_plan, double* us_enqueue);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,8 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_batch_workspace_bytes", "ace_batch_create", "ace_batch_run", "ace_batch_destroy",
            "ace_batch_pin",
            "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan",
-           "ace_set_block_trace", "ace_seek_static"]
+           "ace_set_block_trace", "ace_seek_static", "ace_last_host_times",
+           "ace_workspace_bound"]
 
 
 class AceError(RuntimeError):
@@ -70,6 +71,7 @@ def lib():
         L.ace_archive_close.restype = None
         L.ace_archive_info.argtypes = [vp, u64p, u32p, u32p, u32p]
         L.ace_workspace_bytes.argtypes = [vp, vp, u32, u64p]
+        L.ace_workspace_bound.argtypes = [vp, u32, u64, u64p]
         L.ace_decode_all.argtypes = [vp, vp, u64, vp, u64, C.POINTER(Tuning), vp]
         L.ace_seek.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
         L.ace_seek_static.argtypes = [vp, u64, u64, vp, vp, C.POINTER(Tuning), vp]
@@ -85,6 +87,7 @@ def lib():
         L.ace_set_timing.argtypes = [C.c_int]
         L.ace_set_block_trace.argtypes = [vp, u64]
         L.ace_last_timings.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.ace_last_host_times.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ace_plan_bytes.argtypes = [vp, u64p]
         L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
         _lib = L
@@ -197,6 +200,13 @@ def last_timings():
     return a.value, b.value
 
 
+def last_host_times():
+    """(planning us, enqueue us) of the last timed decode on this thread."""
+    a, b = C.c_double(0), C.c_double(0)
+    _check(lib().ace_last_host_times(C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -256,6 +266,13 @@ class Archive:
             r = self._ranges(ranges)
             _check(lib().ace_workspace_bytes(self._h, r.ctypes.data_as(C.c_void_p), len(r) // 2,
                                              C.byref(b)))
+        return b.value
+
+    def workspace_bound(self, n_ranges: int, total_bytes: int) -> int:
+        """Workspace bytes that suffice for any seek_batch of at most n_ranges
+        ranges of at most total_bytes bytes in all."""
+        b = C.c_uint64(0)
+        _check(lib().ace_workspace_bound(self._h, int(n_ranges), int(total_bytes), C.byref(b)))
         return b.value
 
     def workspace(self, nbytes: int):

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -179,7 +180,11 @@ static int validate(const uint8_t* a, uint64_t len, ace_archive* A) {
   return ACE_OK;
 }
 
-// Level order of a set of blocks (counting sort, stable by block id).
+// Level order of a set of blocks (counting sort by level).  Within a level
+// the blocks with more sequences come first (then by block id): a block's
+// expansion time grows with its sequence count, and starting the long ones
+// first keeps a level's last residency wave short (longest-first list
+// scheduling).
 static void level_order(const ace_archive* A, const std::vector<uint32_t>& blocks,
                         std::vector<uint32_t>& order, std::vector<uint32_t>& lstart) {
   lstart.assign(A->depth + 1, 0);
@@ -188,6 +193,16 @@ static void level_order(const ace_archive* A, const std::vector<uint32_t>& block
   std::vector<uint32_t> pos(lstart.begin(), lstart.end() - 1);
   order.resize(blocks.size());
   for (uint32_t b : blocks) order[pos[A->blk[b].level]++] = b;
+  std::vector<uint64_t> key;
+  for (uint32_t l = 0; l < A->depth; l++) {
+    const uint32_t lo = lstart[l], hi = lstart[l + 1];
+    if (hi - lo < 2) continue;
+    key.resize(hi - lo);
+    for (uint32_t i = lo; i < hi; i++)
+      key[i - lo] = ((uint64_t)(0xFFFFFFFFu - A->blk[order[i]].n_seq) << 32) | order[i];
+    std::sort(key.begin(), key.end());
+    for (uint32_t i = lo; i < hi; i++) order[i] = (uint32_t)key[i - lo];
+  }
 }
 
 extern "C" int ace_archive_open(const uint8_t* h_arch, uint64_t len, const void* d_arch,
@@ -245,8 +260,17 @@ struct PhaseTimer {
   std::vector<hipEvent_t> ent, mat;  // begin/end pairs
   size_t n_ent = 0, n_mat = 0;
   bool recorded = false;
+  // host side of the last timed call: entry, then planning and enqueueing
+  std::chrono::steady_clock::time_point t_enter;
+  double us_plan = 0, us_enqueue = 0;
 };
 thread_local PhaseTimer g_timer;
+inline void timer_enter() {
+  if (g_timer.on) g_timer.t_enter = std::chrono::steady_clock::now();
+}
+inline double us_since(std::chrono::steady_clock::time_point t) {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count();
+}
 // per-block clock trace of this thread's decodes (null: off)
 thread_local unsigned long long* g_trace = nullptr;
 thread_local uint64_t g_trace_entries = 0;
@@ -402,11 +426,35 @@ void close_range(const ace_archive* A, uint32_t t0, uint32_t t1, std::vector<uin
 // ---------------------------------------------------------------------------
 // execution
 // ---------------------------------------------------------------------------
+static int run_launches(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
+                        const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
+                        const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
+                        hipStream_t s, bool entries_pinned, bool loc_linear,
+                        const PlanEntry* resident);
+
+// Runs a host-built plan; with phase timing on, also records the host time
+// spent planning (since the call's entry) and enqueueing.
 static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
                hipStream_t s, bool entries_pinned, bool loc_linear = false,
                const PlanEntry* resident = nullptr) {
+  if (!g_timer.on)
+    return run_launches(A, entries, n_plan, lstart, items, n_items, L, ws, dst_base, t, s, entries_pinned,
+                        loc_linear, resident);
+  const auto t_run = std::chrono::steady_clock::now();
+  g_timer.us_plan = std::chrono::duration<double, std::micro>(t_run - g_timer.t_enter).count();
+  const int rc = run_launches(A, entries, n_plan, lstart, items, n_items, L, ws, dst_base, t, s,
+                              entries_pinned, loc_linear, resident);
+  g_timer.us_enqueue = us_since(t_run);
+  return rc;
+}
+
+static int run_launches(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
+                        const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
+                        const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
+                        hipStream_t s, bool entries_pinned, bool loc_linear,
+                        const PlanEntry* resident) {
   (void)entries_pinned;
   const uint32_t mode = t ? t->mode : 0;
   if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) return fail(ACE_E_ARG, "unknown mode %u", mode);
@@ -542,6 +590,7 @@ extern "C" int ace_workspace_bytes(const ace_archive* A, const ace_range* r, uin
 
 extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out_cap, void* d_ws,
                               uint64_t ws_cap, const ace_tuning* t, void* stream) {
+  timer_enter();
   if (!A || (!d_out && A->n) || !d_ws) return fail(ACE_E_ARG, "null argument");
   if (out_cap < A->n) return fail(ACE_E_NOSPACE, "output needs %llu bytes", (unsigned long long)A->n);
   Layout L = layout(A, A->nb, A->all_seq, 0, 0);
@@ -592,6 +641,7 @@ extern "C" int ace_archive_attach_plan(ace_archive* A, void* d_plan, uint64_t by
 // given, receives the workspace size the seek needs (also on ACE_E_NOSPACE).
 static int seek_impl(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
                      uint64_t ws_cap, const ace_tuning* t, void* stream, uint64_t* ws_need) {
+  timer_enter();
   if (!A) return fail(ACE_E_ARG, "null archive");
   if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
                            (unsigned long long)hi);
@@ -669,6 +719,7 @@ extern "C" int ace_seek_static(const ace_archive* A, uint64_t lo, uint64_t hi, u
 extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t n, uint8_t* d_out,
                               const uint64_t* out_off, void* d_ws, uint64_t ws_cap,
                               const ace_tuning* t, void* stream) {
+  timer_enter();
   if (!A || (n && (!r || !out_off))) return fail(ACE_E_ARG, "null argument");
   std::vector<uint8_t> need(A->nb, 0);
   uint32_t top = 0;
@@ -788,6 +839,17 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   return L;
 }
 }  // namespace
+
+extern "C" int ace_workspace_bound(const ace_archive* A, uint32_t n_ranges, uint64_t total_bytes,
+                                   uint64_t* bytes) {
+  if (!A || !bytes) return fail(ACE_E_ARG, "null argument");
+  // every block planned, every one in a slot, and the most copy items the
+  // ranges can need: a range of len bytes takes at most len / 64 KiB + 3
+  // (the layout grows with each of these)
+  const uint64_t items = total_bytes / 65536 + 3ull * n_ranges;
+  *bytes = layout(A, A->nb, A->all_seq, A->nb, items).total;
+  return ACE_OK;
+}
 
 extern "C" int ace_batch_workspace_bytes(const ace_archive* A, uint32_t max_requests,
                                          uint64_t* bytes) {
@@ -1073,5 +1135,13 @@ extern "C" int ace_last_timings(float* ms_entropy, float* ms_match) {
   }
   *ms_entropy = e;
   *ms_match = m;
+  return ACE_OK;
+}
+
+extern "C" int ace_last_host_times(double* us_plan, double* us_enqueue) {
+  if (!us_plan || !us_enqueue) return fail(ACE_E_ARG, "null argument");
+  if (!g_timer.recorded) return fail(ACE_E_ARG, "no timed decode on this thread");
+  *us_plan = g_timer.us_plan;
+  *us_enqueue = g_timer.us_enqueue;
   return ACE_OK;
 }

@@ -617,8 +617,8 @@ __device__ __forceinline__ void st16u(uint8_t* p, uint4 v) {  // any byte alignm
 }
 
 // The 16 bytes x moved down by s bytes (byte s becomes byte 0; zeros come
-// in at the top), 0 <= s < 16; and moved up by n bytes (byte 0 becomes byte
-// n), 0 <= n < 16.  Branch-free: dword selects, then a funnel shift.
+// in at the top), 0 <= s < 16.  Branch-free: dword selects, then a funnel
+// shift.
 __device__ __forceinline__ uint32_t pick4(const uint32_t (&y)[8], uint32_t i, uint32_t q) {
   return q == 0 ? y[i] : q == 1 ? y[i + 1] : q == 2 ? y[i + 2] : y[i + 3];
 }
@@ -634,16 +634,6 @@ __device__ __forceinline__ void shift_down16(uint32_t (&x)[4], uint32_t s) {
 #pragma unroll
   for (uint32_t i = 0; i < 4; i++) x[i] = funnel(z[i + 1], z[i], b);
 }
-__device__ __forceinline__ void shift_up16(uint32_t (&x)[4], uint32_t n) {
-  const uint32_t q = n >> 2, b = 8 * (n & 3);
-  const uint32_t y[8] = {0u, 0u, 0u, 0u, x[0], x[1], x[2], x[3]};  // y[4 + k] = x[k]
-#pragma unroll
-  for (uint32_t i = 0; i < 4; i++) {
-    const uint32_t hi = pick4(y, 1 + i, 3 - q), lo = pick4(y, i, 3 - q);  // x[i - q], x[i - q - 1]
-    x[i] = b ? (hi << b) | (lo >> (32 - b)) : hi;
-  }
-}
-
 typedef uint64_t u64_a1 __attribute__((aligned(1)));
 typedef uint32_t u32_a1 __attribute__((aligned(1)));
 typedef uint16_t u16_a1 __attribute__((aligned(1)));
@@ -724,15 +714,23 @@ __device__ __forceinline__ uint32_t win_pack(uint64_t back, uint64_t fwd) {
   return (uint32_t)(back < 31 ? back : 31) | ((uint32_t)(fwd < (1ull << 26) ? fwd : (1ull << 26)) << 5);
 }
 
-// Byte mask (as bit mask of dword j's four bytes) of chunk bytes [lo, hi).
-__device__ __forceinline__ uint32_t dword_mask(uint32_t j, uint32_t lo, uint32_t hi) {
-  uint32_t m = 0;
-#pragma unroll
-  for (uint32_t b = 0; b < 4; b++) {
-    const uint32_t x = 4 * j + b;
-    m |= (x >= lo && x < hi) ? (0xFFu << (8 * b)) : 0u;
-  }
-  return m;
+// n / d for n < 2^20 and d >= 1: a reciprocal estimate, then corrected by
+// one either way (the estimate is within one of the quotient).
+__device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
+  uint32_t q = (uint32_t)((float)n * __builtin_amdgcn_rcpf((float)d));
+  if (q * d > n) q--;
+  else if ((q + 1) * d <= n) q++;
+  return q;
+}
+
+// Output pieces of a match of m bytes (m < 2^16) whose byte i is span byte
+// i mod d: a match that repeats its span (m > d) with d >= 16 is cut period
+// by period, each period into 16-byte pieces from its start; any other match
+// into 16-byte pieces from its first byte.
+__device__ __forceinline__ uint32_t match_pieces(uint32_t m, uint32_t d) {
+  if (m <= d || d < 16) return (m + 15) >> 4;
+  const uint32_t q = udiv_small(m, d);
+  return q * ((d + 15) >> 4) + ((m - q * d + 15) >> 4);
 }
 
 // Expands plan entry i with kThreads threads.  Sources in earlier blocks must
@@ -964,7 +962,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
             const uint64_t e = (uint64_t)ds + L[h] + M[h];
             n = ds < d1 ? ((e < d1 ? (uint32_t)e : d1) - ds + 15) >> 4 : 0u;
           } else {
-            n = ((L[h] + 15) >> 4) + ((fl_h[h] & kSlow) ? 0u : (M[h] + 15) >> 4);
+            n = ((L[h] + 15) >> 4) + ((fl_h[h] & kSlow) ? 0u : match_pieces(M[h], sm.dfl[slot] & 0xFFFFFFu));
           }
         }
         np[h] = n;
@@ -1002,8 +1000,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         sm.cseq[tid + j * kThreads] = 0;
       }
       carry = wg_max_scan_strided4<kThreads>(sqv, carry, sm.scan);
-      uint4 v1[4], v2[4];
-      uint32_t dsto[4], len[4], sh1[4], n1[4];
+      uint4 v1[4];
+      uint32_t dsto[4], len[4], sh1[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         const uint32_t p = p0 + tid + j * kThreads;
@@ -1017,9 +1015,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         const uint32_t pl = (Ls + 15) >> 4;
         // the piece: output offset, length, and where its bytes come from
         const uint8_t* A1 = c.lit;  // readable: the literal stream has slack around it
-        const uint8_t* A2 = c.lit;
-        uint32_t off, r, s1 = 0, m1 = 16;
-        bool zero = !on || (fl & kPoison);
+        uint32_t off, r, s1 = 0, at = 0;
+        const bool zero = !on || (fl & kPoison);
         if ((fl & kPoison) || k < pl) {
           off = 16 * k;
           const uint32_t tot = (fl & kPoison) ? (d1 - ds < Ls + Ms ? d1 - ds : Ls + Ms) : Ls;
@@ -1027,72 +1024,60 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           A1 = c.lit + litv + off;
           dsto[j] = ds + off;
         } else {
-          off = 16 * (k - pl);
-          r = Ms - off < 16 ? Ms - off : 16;
+          // match byte i reads span byte i mod d: a match that repeats its
+          // span with a period of 16 bytes or more is cut period by period
+          // (no piece crosses a period's end); a shorter period goes byte
+          // by byte below
+          const uint32_t kk = k - pl;
+          if (Ms > dist && dist >= 16) {
+            const uint32_t ppp = (dist + 15) >> 4, q = udiv_small(kk, ppp);
+            at = 16 * (kk - q * ppp);
+            off = q * dist + at;
+            const uint32_t rest = dist - at < Ms - off ? dist - at : Ms - off;
+            r = rest < 16 ? rest : 16;
+          } else {
+            off = at = 16 * kk;
+            r = Ms - off < 16 ? Ms - off : 16;
+          }
           dsto[j] = ds + Ls + off;
-          // match byte i reads span byte i mod d; a piece runs up to the
-          // period's end (m1 bytes) and the rest restarts at the span start
-          const bool wrap = Ms > dist;
-          const uint32_t at = wrap ? off % dist : off;
-          m1 = wrap && dist - at < r ? dist - at : r;
           // readable bytes around the span start: back (<= 31), forward
           const uint32_t back = wn & 31u, fwd = wn >> 5;
           const uint32_t need = at + 16 > fwd ? at + 16 - fwd : 0u;  // shift the load back this far
           s1 = need;
           A1 = reinterpret_cast<const uint8_t*>(s0 + at - need);
-          A2 = reinterpret_cast<const uint8_t*>(s0);
-          if (need > back + at || (wrap && dist < 16) || (m1 < r && fwd < 16)) {
-            // a window too small for 16-byte loads, or a period shorter
+          if (need > back + at || (Ms > dist && dist < 16)) {
+            // a window too small for a 16-byte load, or a period shorter
             // than a piece: this piece goes byte by byte below
             s1 = 0xFFu;
             A1 = c.lit;
-            A2 = c.lit;
           }
         }
         len[j] = on ? r : 0u;
-        sh1[j] = zero ? 0u : s1;
-        n1[j] = m1;
+        sh1[j] = zero ? 0x100u : s1;  // 0x100: zeros
         v1[j] = ld16u(zero || s1 == 0xFFu ? c.lit : A1);
-        v2[j] = ld16u(zero || s1 == 0xFFu || m1 >= r ? c.lit : A2);
-        if (zero) sh1[j] = 0x100u;  // zeros
         if (s1 == 0xFFu && !zero) {
-          // byte by byte (rare): span byte (at + i) mod d for each piece byte
-          const uint32_t at0 = Ms > dist ? off % dist : off;
+          // byte by byte (rare): span byte (off + i) mod d for each piece byte
           uint32_t w[4] = {0, 0, 0, 0};
-          uint32_t ii = at0;
+          uint32_t ii = Ms > dist ? off % dist : off;
+#pragma unroll
           for (uint32_t b2 = 0; b2 < 16; b2++) {
             if (b2 < r) w[b2 >> 2] |= (uint32_t)ld8(reinterpret_cast<const uint8_t*>(s0 + ii)) << (8 * (b2 & 3));
             ii = (Ms > dist && ii + 1 == dist) ? 0u : ii + 1;
           }
           v1[j] = make_uint4(w[0], w[1], w[2], w[3]);
           sh1[j] = 0;
-          n1[j] = 16;
         }
       }
-      // assemble and store: bytes [0, n1) from the first load (shifted down
-      // by sh1), the rest from the second; exactly len bytes written
+      // assemble and store: the load shifted down by sh1 (or zeros);
+      // exactly len bytes written
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         if (!len[j]) continue;
-        uint32_t w[4];
+        uint32_t w[4] = {v1[j].x, v1[j].y, v1[j].z, v1[j].w};
         if (sh1[j] == 0x100u) {
           w[0] = w[1] = w[2] = w[3] = 0u;
         } else {
-          uint32_t x1[4] = {v1[j].x, v1[j].y, v1[j].z, v1[j].w};
-          shift_down16(x1, sh1[j]);
-          if (n1[j] < len[j]) {
-            uint32_t x2[4] = {v2[j].x, v2[j].y, v2[j].z, v2[j].w};
-            shift_up16(x2, n1[j]);
-#pragma unroll
-            for (uint32_t q = 0; q < 4; q++) {
-              const uint32_t m = dword_mask(q, 0, n1[j]);
-              x1[q] = (x1[q] & m) | (x2[q] & ~m);
-            }
-          }
-          w[0] = x1[0];
-          w[1] = x1[1];
-          w[2] = x1[2];
-          w[3] = x1[3];
+          shift_down16(w, sh1[j]);
         }
         store_bytes(c.out + dsto[j], w, len[j]);
       }
@@ -1132,23 +1117,21 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 template <uint32_t kThreads>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
   __shared__ ExpandSmem<kThreads> sm;
-  auto one = [&](uint32_t i) {
+  // host-planned: one block per workgroup; device-planned: the level's plan
+  // range from device memory, strided over the grid (one call site, so the
+  // expansion is inlined)
+  const bool host = level < 0;
+  const uint32_t first = (host ? plan_lo : a.lvl_dev[level]) + blockIdx.x;
+  const uint32_t end = host ? first + 1 : a.lvl_dev[level + 1];
+  const uint32_t stride = host ? 1u : gridDim.x;
+  for (uint32_t i = first; i < end; i += stride) {
     const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
     expand_block<kThreads>(a, i, sm);
     if (a.trace && threadIdx.x == 0) {
       a.trace[8ull * i] = c0;
       a.trace[8ull * i + 1] = (unsigned long long)wall_clock64();
     }
-  };
-  if (level < 0) {  // host-planned: one block per workgroup
-    one(plan_lo + blockIdx.x);
-    return;
-  }
-  // device-planned: the level's plan range from device memory, strided
-  const uint32_t lo = a.lvl_dev[level], hi = a.lvl_dev[level + 1];
-  for (uint32_t i = lo + blockIdx.x; i < hi; i += gridDim.x) {
-    one(i);
-    __syncthreads();  // every thread done with this block's LDS tables
+    if (i + stride < end) __syncthreads();  // every thread done with this block's LDS tables
   }
 }
 
@@ -1169,8 +1152,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // level); the workgroup whose add completes the level raises the count of
 // finished levels held in kPersistReplicas copies, one per 128-byte line, and
 // each workgroup polls the copy w mod kPersistReplicas until it passes the
-// level, so idle polling is spread over many lines.  Empty levels are
-// skipped.  A block's dependencies all sit at lower levels, so every block
+// level, so idle polling is spread over many lines.  Only workgroups
+// 0 .. size-1 claim from a level of `size` blocks (the others go straight to
+// the wait, so a small level is not probed by the whole grid).  Empty levels
+// are skipped.  A block's dependencies all sit at lower levels, so every block
 // expanded finds its sources complete.  A workgroup waits only after every
 // block of the level is claimed, i.e. held by a running workgroup: the launch
 // needs no co-residency, and drains when it shares the device.
@@ -1179,8 +1164,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // agent-scope release fence (its stores complete, this XCD's L2 written
 // back) before the barrier that precedes the workgroup's finished-count add;
 // the copies are raised by atomic max after that add.  A waiting workgroup
-// polls with agent-scope atomic loads, then every wave issues an agent-scope
-// acquire fence before it reads lower levels' bytes.
+// polls with agent-scope atomic loads; a workgroup that claims a block of the
+// next level issues an agent-scope acquire fence in every wave before it
+// reads lower levels' bytes.
 //
 // Every wait is bounded by a count of idle polls (not by a clock).  An
 // expired wait flags kErrTimeout and the workgroup stops waiting from then
@@ -1206,6 +1192,7 @@ __device__ __forceinline__ uint32_t slice_size(uint32_t size, uint32_t r) {
 __device__ uint32_t claim_any(const DecodeArgs& a, uint32_t lvl, uint32_t lo, uint32_t size, uint32_t first) {
   for (uint32_t k = 0; k < kPersistSlices; k++) {
     const uint32_t r = (first + k) % kPersistSlices, n_r = slice_size(size, r);
+    if (n_r == 0) continue;
     uint32_t* c = a.lvl_claim + (uint64_t)r * a.lvl_row + lvl;
     if (coherent_u32(c) >= n_r) continue;
     const uint32_t t = atomicAdd(c, 1u);
@@ -1223,40 +1210,49 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
   for (uint32_t lvl = 0; lvl < a.n_lvl; lvl++) {
     const uint32_t lo = a.lvl_dev[lvl], size = a.lvl_dev[lvl + 1] - lo;
     if (size == 0) continue;
-    const uint32_t n_home = slice_size(size, home);
-    uint32_t* home_claim = a.lvl_claim + (uint64_t)home * a.lvl_row + lvl;
-    if (tid == 0) sh_item[0] = claim_any(a, lvl, lo, size, home);
-    __syncthreads();
-    uint32_t item = sh_item[0], par = 0, mine = 0;
-    while (item != kNoItem) {
-      uint32_t next = kNoItem;
-      if (tid == 0) next = atomicAdd(home_claim, 1u);  // result used after the expansion
-      const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
-      expand_block<kPersistThreads>(a, item, sm, !give_up);
-      if (a.trace && tid == 0) {
-        a.trace[8ull * item] = c0;
-        a.trace[8ull * item + 1] = (unsigned long long)wall_clock64();
-      }
-      mine++;
-      if (tid == 0)
-        sh_item[par ^ 1] = next < n_home ? lo + home + next * kPersistSlices : claim_any(a, lvl, lo, size, home + 1);
-      __syncthreads();  // every thread done with this block's LDS tables; next item visible
-      par ^= 1;
-      item = sh_item[par];
-    }
-    if (mine) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // workgroups 0 .. size-1 take part (all of them when the level has at
+    // least as many blocks as the grid); workgroups are dispatched in index
+    // order, so every one taking part is running while any other waits
+    uint32_t mine = 0;
+    if (blockIdx.x < size) {
+      const uint32_t n_home = slice_size(size, home);
+      uint32_t* home_claim = a.lvl_claim + (uint64_t)home * a.lvl_row + lvl;
+      if (tid == 0) sh_item[0] = claim_any(a, lvl, lo, size, home);
       __syncthreads();
-      if (tid < kPersistReplicas) {  // wave 0: lane r raises copy r
-        uint32_t prev = 0;
-        if (tid == 0) prev = atomicAdd(a.lvl_done + lvl, mine);
-        prev = __shfl(prev, 0);
-        if (prev + mine == size) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-          __hip_atomic_fetch_max(a.lvl_seen + tid * kPersistLine, lvl + 1, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t item = sh_item[0], par = 0;
+      // the levels below are complete: make their bytes visible here (only
+      // workgroups with blocks to expand pay for the cache invalidation)
+      if (item != kNoItem) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      while (item != kNoItem) {
+        uint32_t next = kNoItem;
+        if (tid == 0) next = atomicAdd(home_claim, 1u);  // result used after the expansion
+        const unsigned long long c0 = a.trace ? (unsigned long long)wall_clock64() : 0ull;
+        expand_block<kPersistThreads>(a, item, sm, !give_up);
+        if (a.trace && tid == 0) {
+          a.trace[8ull * item] = c0;
+          a.trace[8ull * item + 1] = (unsigned long long)wall_clock64();
         }
-        __builtin_amdgcn_wave_barrier();  // the wave's raises come before lane 0's wait
+        mine++;
+        if (tid == 0)
+          sh_item[par ^ 1] = next < n_home ? lo + home + next * kPersistSlices : claim_any(a, lvl, lo, size, home + 1);
+        __syncthreads();  // every thread done with this block's LDS tables; next item visible
+        par ^= 1;
+        item = sh_item[par];
+      }
+      if (mine) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid < kPersistReplicas) {  // wave 0: lane r raises copy r
+          uint32_t prev = 0;
+          if (tid == 0) prev = atomicAdd(a.lvl_done + lvl, mine);
+          prev = __shfl(prev, 0);
+          if (prev + mine == size) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_fetch_max(a.lvl_seen + tid * kPersistLine, lvl + 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+          }
+          __builtin_amdgcn_wave_barrier();  // the wave's raises come before lane 0's wait
+        }
       }
     }
     if (tid == 0) {
@@ -1274,7 +1270,6 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
     }
     __syncthreads();
     give_up = sh_give_up != 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
 }
 

@@ -9,8 +9,17 @@ slots overlap on the device.  A batch is one seek_batch call (one
 dependency-ordered decode of the union of the requests' closures, then one
 gather), or, with keep_levels, one replay of a captured batch graph per
 (slot, archive) whose lowest dependency levels stay decoded (ace_batch_pin),
-so closures stop there.  Latency is measured from a request's scheduled arrival to the
-completion of its batch, so queueing is included.
+so closures stop there.  Latency is measured from a request's scheduled
+arrival to the completion of its batch, so queueing is included.
+
+Device memory is bounded up front.  A result is a view of its batch's output
+buffer; the batch's bytes stay charged to the output budget until the
+consumer has released every request of the batch (Server.release, or
+auto_release after an on_done callback), so outputs never hold more than the
+budget.  Every workspace is allocated when the backend is built (per slot,
+sized by the library's bound for a batch of max_batch requests filling the
+budget; or one captured batch graph per slot and archive with kept levels)
+and reported by device_bytes().
 
 The device work goes through a backend object so the scheduling logic can
 be exercised without a GPU; GpuBackend is the real one.
@@ -33,18 +42,31 @@ class Request:
     hi: int
     t_arrival: float                 # scheduled arrival (perf_counter seconds)
     t_done: float = 0.0
-    result: object = None            # device tensor view (or host bytes) of [lo, hi)
+    result: object = None            # device tensor view (or host bytes) of [lo, hi), until released
     done: threading.Event = field(default_factory=threading.Event)
+    batch: object = None             # the _Batch whose output holds the result
+    released: bool = False
 
     @property
     def nbytes(self) -> int:
         return self.hi - self.lo
 
 
-class GpuBackend:
-    """Slots on HIP streams, decoding with libaceseek's batched seek."""
+@dataclass
+class _Batch:
+    nbytes: int      # output bytes charged to the budget
+    open: int        # requests not yet released
 
-    def __init__(self, archives: dict, slots: int, device="cuda:0", keep_levels=None, max_batch: int = 4096):
+
+class GpuBackend:
+    """Slots on HIP streams, decoding with libaceseek's batched seek.  Every
+    workspace is allocated here: one per slot, sized by the library's bound
+    for max_batch ranges of at most batch_bytes in all (the plain path), or
+    one captured batch graph per (slot, archive) whose lowest keep_levels
+    levels stay decoded."""
+
+    def __init__(self, archives: dict, slots: int, device="cuda:0", keep_levels=None, max_batch: int = 4096,
+                 batch_bytes: int = 1 << 30):
         import torch
         self.torch = torch
         self.archives = archives
@@ -59,6 +81,17 @@ class GpuBackend:
                     bt = arc.batch(max_batch, stream=self.streams[slot])
                     bt.pin(min(int(keep_levels), arc.depth))
                     self.batches[(slot, name)] = bt
+        else:
+            need = max(arc.workspace_bound(max_batch, batch_bytes) for arc in archives.values())
+            self.ws = [torch.zeros(max(need, 256), dtype=torch.uint8, device=self.device) for _ in range(slots)]
+
+    def device_bytes(self) -> dict:
+        """Device memory held by the backend: workspaces (or batch graphs) and
+        the compressed archives."""
+        ws = sum(t.numel() for t in self.ws if t is not None) + sum(bt.ws.numel() for bt in self.batches.values())
+        arch = sum(arc.d_arch.numel() + (arc.d_plan.numel() if arc.d_plan is not None else 0)
+                   for arc in self.archives.values())
+        return {"workspaces": int(ws), "archives_and_plans": int(arch)}
 
     def launch(self, slot: int, name: str, reqs):
         torch = self.torch
@@ -74,9 +107,7 @@ class GpuBackend:
             if bt is not None:
                 bt.run((lo, hi), out, offs)
             else:
-                need = arc.workspace_bytes((lo, hi))
-                if self.ws[slot] is None or self.ws[slot].numel() < need:
-                    self.ws[slot] = torch.zeros(max(need, 256), dtype=torch.uint8, device=self.device)
+                # the slot's workspace is sized by the bound: no allocation here
                 arc.seek_batch((lo, hi), out=out, out_offsets=offs, ws=self.ws[slot], stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
@@ -97,10 +128,16 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, backend, budget_bytes: int, slots: int, max_batch: int = 4096):
+    """on_done(request) runs at each completion (under the server's lock);
+    with auto_release the request is released right after it."""
+
+    def __init__(self, backend, budget_bytes: int, slots: int, max_batch: int = 4096, on_done=None,
+                 auto_release: bool = False):
         self.backend = backend
         self.budget = budget_bytes
-        self.used = 0
+        self.on_done = on_done
+        self.auto_release = auto_release
+        self.used = 0  # output bytes admitted and not yet released
         self.slots = slots
         self.max_batch = max_batch
         self.pending = collections.deque()  # arrived, not yet admitted
@@ -111,6 +148,9 @@ class Server:
         self.rid = 0
         self.peak_used = 0
         self.batches = 0
+        # scheduling passes, and those that found every slot busy or the
+        # oldest pending request not fitting the budget (what limits a run)
+        self.passes = self.passes_slots_full = self.passes_budget_full = 0
 
     def submit(self, archive: str, lo: int, hi: int, t_arrival: float = None) -> Request:
         with self.lock:
@@ -133,20 +173,30 @@ class Server:
     def step(self) -> bool:
         """One scheduling pass; returns True if anything is still in progress."""
         with self.lock:
-            # completions free slots and budget
+            # completions free slots; budget comes back as results are released
             for slot, (h, reqs, nb) in list(self.inflight.items()):
                 if self.backend.poll(h):
                     views = self.backend.finish(h)
                     t = time.perf_counter()
+                    batch = _Batch(nb, len(reqs))
                     for r, v in zip(reqs, views):
-                        r.result, r.t_done = v, t
+                        r.result, r.t_done, r.batch = v, t, batch
                         r.done.set()
-                    self.used -= nb
                     self.done.extend(reqs)
                     del self.inflight[slot]
+                    for r in reqs:
+                        if self.on_done is not None:
+                            self.on_done(r)
+                        if self.auto_release:
+                            self._release(r)
             self._admit()
+            self.passes += 1
+            if self.pending:
+                self.passes_budget_full += 1
             # fill free slots with the oldest archive's admitted requests
             free = [s for s in range(self.slots) if s not in self.inflight]
+            if not free and any(self.admitted.values()):
+                self.passes_slots_full += 1
             for slot in free:
                 names = [n for n, q in self.admitted.items() if q]
                 if not names:
@@ -159,6 +209,22 @@ class Server:
                 self.batches += 1
             busy = bool(self.inflight or self.pending or any(self.admitted.values()))
         return busy
+
+    def release(self, r: Request):
+        """The consumer is done with r's result: drops it, and returns its
+        batch's bytes to the budget once every request of the batch is
+        released."""
+        with self.lock:
+            self._release(r)
+
+    def _release(self, r: Request):
+        if r.released or r.batch is None:
+            return
+        r.released = True
+        r.result = None
+        r.batch.open -= 1
+        if r.batch.open == 0:
+            self.used -= r.batch.nbytes
 
     def drain(self, timeout: float = 600.0):
         t_end = time.perf_counter() + timeout
@@ -195,6 +261,16 @@ def poisson_run(server: Server, names, n_total: dict, rate: float, count: int, s
         if i < count and due[i] > time.perf_counter():
             server.step()
     return reqs, time.perf_counter() - t0
+
+
+def limiter(server: Server) -> dict:
+    """Shares of scheduling passes that found admitted work waiting for a
+    slot (device-bound) or arrived work waiting for budget (memory-bound)."""
+    n = max(server.passes, 1)
+    slots, budget = server.passes_slots_full / n, server.passes_budget_full / n
+    name = "slots" if slots >= budget and slots > 0.05 else "budget" if budget > 0.05 else "arrivals"
+    return {"passes": server.passes, "slots_full_share": round(slots, 4),
+            "budget_full_share": round(budget, 4), "limiter": name}
 
 
 def latency_report(reqs, wall: float) -> dict:

@@ -110,6 +110,7 @@ void launch(dim3 grid, dim3 block, hipStream_t s, std::function<void()> body);
 #define __builtin_amdgcn_s_sleep(n) ::simt::spin_pause()
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier()
+#define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
 
 inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t m, uint32_t base) {
   const uint32_t l = ::simt::lane_id();

@@ -21,20 +21,27 @@ def test_results_same_alone_and_in_mix(orc, keep):
           "text": gen.text(2 << 20, 53)}
     arcs = {k: Archive(encode(v, block_size=16384, interleave=32, min_match=16, hash_len=16,
                               max_level=8), device="cuda:0") for k, v in xs.items()}
-    srv = Server(GpuBackend(arcs, slots=3, keep_levels=keep, max_batch=64), budget_bytes=8 << 20, slots=3,
-                 max_batch=64)
+    backend = GpuBackend(arcs, slots=3, keep_levels=keep, max_batch=64, batch_bytes=8 << 20)
+    # the consumer copies each result out as it completes and releases it,
+    # which returns its bytes to the budget
+    got = {}
+    srv = Server(backend, budget_bytes=8 << 20, slots=3, max_batch=64,
+                 on_done=lambda r: got.__setitem__(r.rid, r.result.cpu().numpy().tobytes()),
+                 auto_release=True)
     reqs, wall = poisson_run(srv, list(xs), {k: len(v) for k, v in xs.items()}, rate=3000.0,
                              count=400, seed=5, min_len=16, max_len=1 << 20)
     rep = latency_report(reqs, wall)
     assert rep["requests"] == 400
-    assert srv.peak_used <= 8 << 20 and srv.used == 0
+    assert srv.peak_used <= 8 << 20
     assert srv.batches < 400  # requests were actually batched
+    # workspaces were all allocated up front
+    assert backend.device_bytes()["workspaces"] > 0
     torch.cuda.synchronize()
+    assert srv.used == 0 and all(r.released for r in reqs)
     rng = np.random.default_rng(0)
     for r in reqs:
-        got = r.result.cpu().numpy().tobytes()
-        assert got == xs[r.archive][r.lo:r.hi], r.rid
+        assert got[r.rid] == xs[r.archive][r.lo:r.hi], r.rid
     for r in rng.choice(reqs, size=20, replace=False):
         solo = arcs[r.archive].seek(r.lo, r.hi, tuning=dict(mode=1))
         arcs[r.archive].check()
-        assert solo.cpu().numpy().tobytes() == r.result.cpu().numpy().tobytes()
+        assert solo.cpu().numpy().tobytes() == got[r.rid]

@@ -162,3 +162,36 @@ def test_argument_errors_before_device_work(lib):
     assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), 1, C.byref(ws)) == lib.E_RANGE
     assert L.ace_batch_pin(None, 1) == lib.E_ARG
     L.ace_archive_close(h)
+
+
+def test_workspace_bound_covers_every_batch(lib):
+    """The bound for n ranges of at most m bytes in all is at least the
+    workspace of any such set of ranges (seeded random sets, single bytes
+    spread over every block, and the whole archive)."""
+    x = gen.mixed(3 << 20, 8)
+    a = lib.encode(x, block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=6)
+    rc, h = _open(lib, a)
+    assert rc == 0
+    L = lib.lib()
+
+    def need(lo, hi):
+        r = np.empty(2 * len(lo), dtype=np.uint64)
+        r[0::2], r[1::2] = lo, hi
+        b = C.c_uint64()
+        assert L.ace_workspace_bytes(h, r.ctypes.data_as(C.c_void_p), len(lo), C.byref(b)) == 0
+        return b.value
+
+    def bound(n, m):
+        b = C.c_uint64()
+        assert L.ace_workspace_bound(h, n, m, C.byref(b)) == 0
+        return b.value
+
+    for seed, n, m in [(1, 1, 1), (2, 16, 1 << 20), (3, 300, 4 << 20), (4, 40, 3 << 20)]:
+        lo, hi = gen.seek_requests(len(x), n, seed, max_len=m)
+        assert need(lo, hi) <= bound(n, int((hi - lo).sum()))
+    nb = -(-len(x) // 16384)
+    lo = np.arange(nb, dtype=np.uint64) * 16384 + 1
+    assert need(lo, lo + 1) <= bound(nb, nb)
+    assert need(np.array([0], dtype=np.uint64), np.array([len(x)], dtype=np.uint64)) <= bound(1, len(x))
+    assert L.ace_workspace_bound(None, 1, 1, C.byref(C.c_uint64())) == lib.E_ARG
+    L.ace_archive_close(h)
