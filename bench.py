@@ -358,6 +358,7 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
 
     import gen
     from paper_2606_24531_amd import Archive, encode
+    from paper_2606_24531_amd import aceseek as ace
 
     dev = x_dev.device
     if not args.no_extras:
@@ -412,32 +413,48 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
         bt.close()
         tb = float(np.median(times))
         # plain: one seek call (its own plan and launches) per request, waited
-        # on; the first plain_requests requests of the same list
+        # on; the first plain_requests requests of the same list.  Planned on
+        # the device (the archive's plan resident, a workspace of
+        # seek_device_bytes) and, as before, on the host (closure walk).
         n_plain = min(args.plain_requests, n_req)
-        ws = torch.zeros(arc.workspace_bytes([0, len(x)]), dtype=torch.uint8, device=dev)
-        lat = []
-        for i in range(n_plain):
-            t = time.perf_counter()
-            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning)
-            torch.cuda.synchronize()
-            lat.append(time.perf_counter() - t)
-        arc.check(ws)
-        plain_ok = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x_dev[int(lo[i]):int(hi[i])]))
-                       for i in range(n_plain))
-        plain_rate = n_plain / sum(lat)
-        # where a plain seek's time goes, on the first requests again: host
-        # planning and enqueueing (library clocks), device phases (events)
-        ace.set_timing(True)
-        plan_us, enq_us, dev_ms = [], [], []
-        for i in range(min(n_plain, 300)):
-            arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning)
-            torch.cuda.synchronize()
-            p_us, e_us = ace.last_host_times()
-            e_ms, m_ms = ace.last_timings()
-            plan_us.append(p_us)
-            enq_us.append(e_us)
-            dev_ms.append(e_ms + m_ms)
-        ace.set_timing(False)
+        ws = torch.zeros(max(arc.seek_device_bytes(), arc.workspace_bytes([0, len(x)])), dtype=torch.uint8,
+                         device=dev)
+
+        def plain(planner):
+            lat = []
+            for i in range(n_plain):
+                t = time.perf_counter()
+                arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning, plan=planner)
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - t)
+            arc.check(ws)
+            ok = all(bool(torch.equal(out[int(offs[i]):int(offs[i]) + int(ln[i])], x_dev[int(lo[i]):int(hi[i])]))
+                     for i in range(n_plain))
+            # where the time goes, on the first requests again: host planning
+            # and enqueueing (library clocks), device phases (events)
+            ace.set_timing(True)
+            plan_us, enq_us, dev_ms = [], [], []
+            for i in range(min(n_plain, 300)):
+                arc.seek(int(lo[i]), int(hi[i]), out=out[int(offs[i]):], ws=ws, tuning=tuning, plan=planner)
+                torch.cuda.synchronize()
+                p_us, e_us = ace.last_host_times()
+                e_ms, m_ms = ace.last_timings()
+                plan_us.append(p_us)
+                enq_us.append(e_us)
+                dev_ms.append(e_ms + m_ms)
+            ace.set_timing(False)
+            p50 = float(np.percentile(lat, 50))
+            return {
+                "p50_ms": round(1e3 * p50, 4), "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+                "req_per_s": round(n_plain / sum(lat), 1), "outputs_equal_original": ok,
+                "host_plan_us_p50": round(float(np.median(plan_us)), 1),
+                "host_enqueue_us_p50": round(float(np.median(enq_us)), 1),
+                "device_decode_ms_p50": round(float(np.median(dev_ms)), 4),
+                "plan_share_of_p50": round(float(np.median(plan_us)) * 1e-6 / p50, 4),
+            }
+
+        pd = plain("device")
+        ph = plain("host")
         result["seek"] = {
             "workload": "%d seeks on the resident archive, length log-uniform 1 B..4 MiB, uniform "
                         "offsets (seed 4)" % n_req,
@@ -445,20 +462,17 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
             "batched_latency_ms": round(1e3 * tb, 4), "batched_req_per_s": round(n_req / tb, 1),
             "batched_out_GBs": round(total / tb / 1e9, 2), "batched_outputs_equal_original": good,
             "plain_requests_timed": n_plain,
-            "plain_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 4),
-            "plain_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
-            "plain_req_per_s": round(plain_rate, 1), "plain_outputs_equal_original": plain_ok,
-            "batched_vs_plain_throughput": round((n_req / tb) / plain_rate, 1),
-            "plain_host_plan_us_p50": round(float(np.median(plan_us)), 1),
-            "plain_host_enqueue_us_p50": round(float(np.median(enq_us)), 1),
-            "plain_device_ms_p50": round(float(np.median(dev_ms)), 4),
-            "plain_plan_share_of_p50": round(float(np.median(plan_us)) * 1e-3 / float(np.percentile(lat, 50)), 4),
+            "plain_p50_ms": pd["p50_ms"], "plain_p99_ms": pd["p99_ms"], "plain_req_per_s": pd["req_per_s"],
+            "batched_vs_plain_throughput": round((n_req / tb) / pd["req_per_s"], 1),
+            "plain_device_planned": pd, "plain_host_planned": ph,
         }
-        _log("seek: batch of %d in %.3f ms (%.0f req/s, all outputs equal: %s); plain p50 %.3f ms "
-             "p99 %.3f ms (%.0f req/s; host planning p50 %.1f us, enqueue %.1f us, device %.3f ms)" % (
-                 n_req, 1e3 * tb, n_req / tb, good, result["seek"]["plain_p50_ms"],
-                 result["seek"]["plain_p99_ms"], plain_rate, result["seek"]["plain_host_plan_us_p50"],
-                 result["seek"]["plain_host_enqueue_us_p50"], result["seek"]["plain_device_ms_p50"]))
+        _log("seek: batch of %d in %.3f ms (%.0f req/s, all outputs equal: %s)" % (n_req, 1e3 * tb, n_req / tb, good))
+        for name, r in (("device", pd), ("host", ph)):
+            _log("plain %s-planned: p50 %.3f ms p99 %.3f ms (%.0f req/s, equal %s); host planning p50 %.1f us "
+                 "(%.1f%% of p50), enqueue %.1f us, device decode %.3f ms" % (
+                     name, r["p50_ms"], r["p99_ms"], r["req_per_s"], r["outputs_equal_original"],
+                     r["host_plan_us_p50"], 100 * r["plan_share_of_p50"], r["host_enqueue_us_p50"],
+                     r["device_decode_ms_p50"]))
         del out
         torch.cuda.empty_cache()
 

@@ -131,12 +131,13 @@ int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_t* block_si
                      uint32_t* n_blocks, uint32_t* depth);
 
 /* Optional: the whole-archive decode plan (the blocks in dependency-level
- * order with the index fields the kernels need, 64 bytes per block) kept
- * resident on the device.  ace_plan_bytes gives its size; attach uploads it
- * once into d_plan (caller-owned device memory of at least that many bytes,
- * kept alive and unmodified while the handle is used; synchronous on
- * `stream`), and later ace_decode_all calls read it there instead of copying
- * it from the host on every call. */
+ * order with the index fields the kernels need, 64 bytes per block, then the
+ * block ids in that order and the level boundaries) kept resident on the
+ * device.  ace_plan_bytes gives its size; attach uploads it once into d_plan
+ * (caller-owned device memory of at least that many bytes, kept alive and
+ * unmodified while the handle is used; synchronous on `stream`).  Later
+ * ace_decode_all calls read it there instead of copying it from the host on
+ * every call, and ace_seek can plan on the device. */
 int ace_plan_bytes(const ace_archive* a, uint64_t* bytes);
 int ace_archive_attach_plan(ace_archive* a, void* d_plan, uint64_t bytes, void* stream);
 
@@ -164,7 +165,13 @@ int ace_decode_all(const ace_archive* a, uint8_t* d_out, uint64_t out_cap, void*
 
 /* Seek (Section 5): writes exactly hi - lo bytes at d_out and nothing else in
  * d_out.  Blocks that only supply sources are decoded into the workspace.
- * An empty range returns ACE_OK without launching. */
+ * An empty range returns ACE_OK without launching.  Planning: when the
+ * archive's plan is attached (ace_archive_attach_plan) and ws_cap is at
+ * least ace_batch_workspace_bytes(a, 1), the range's dependency closure is
+ * found on the device (the batch planner's kernels for one request) and the
+ * host only enqueues; otherwise the host walks the closure, and the
+ * workspace needs ace_workspace_bytes for the range.  Both give the same
+ * bytes. */
 int ace_seek(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
              uint64_t ws_cap, const ace_tuning* t, void* stream);
 

@@ -313,14 +313,37 @@ class Archive:
                                     _stream_ptr(stream)))
         return out
 
-    def seek(self, lo: int, hi: int, out=None, ws=None, tuning=None, stream=None):
+    def seek_device_bytes(self) -> int:
+        """Workspace bytes with which ace_seek plans on the device (the
+        archive's plan is attached by default)."""
+        b = C.c_uint64(0)
+        _check(lib().ace_batch_workspace_bytes(self._h, 1, C.byref(b)))
+        return b.value
+
+    def seek(self, lo: int, hi: int, out=None, ws=None, tuning=None, stream=None, plan: str = "auto"):
+        """[lo, hi) as a device tensor.  plan: "host" walks the closure on the
+        host (the workspace capacity passed is the host plan's need), "device"
+        plans on the device (needs the resident plan), "auto" lets the
+        library choose by the workspace's size."""
         torch = self._torch
         if out is None:
             out = torch.empty(max(hi - lo, 0), dtype=torch.uint8, device=self.device)
+        host_need = self.workspace_bytes([lo, hi]) if hi > lo else 256
+        if plan == "device":
+            if self.d_plan is None:
+                raise AceError(E_ARG, "device planning needs the resident plan")
+            need = self.seek_device_bytes()
+        else:
+            need = host_need
         if ws is None:
-            ws = self.workspace(self.workspace_bytes([lo, hi]) if hi > lo else 256)
+            ws = self.workspace(need)
+        cap = ws.numel()
+        if plan == "host":
+            cap = min(cap, host_need)
+        elif plan == "device" and cap < need:
+            raise AceError(E_NOSPACE, "device planning needs a %d-byte workspace" % need)
         _check(lib().ace_seek(self._h, lo, hi, C.c_void_p(out.data_ptr()),
-                              C.c_void_p(ws.data_ptr()), ws.numel(), self._tuning(tuning),
+                              C.c_void_p(ws.data_ptr()), cap, self._tuning(tuning),
                               _stream_ptr(stream)))
         return out
 

@@ -7,9 +7,11 @@ Whole-archive decode (`tune`): searches, on a sample of the workload,
   * entropy streams per wavefront (1, or 2 when W <= 32),
   * wavefronts per block of the match expansion (0 = the library's choice per
     launch by the level's size, 2 or 4),
-  * the decode mode (1: one expansion launch per dependency level; 2: one
-    persistent launch for all levels) and, for mode 2, the grid (every
-    workgroup the device holds at once, or half of them).
+  * the decode mode (1: one expansion launch per dependency level; 3: the
+    same, with the later levels' entropy decode on a second stream beside
+    the first levels' expansion; 2: one persistent launch for all levels)
+    and, for mode 2, the grid (every workgroup the device holds at once, or
+    half of them).
 Batched seeks (`tune_batch`): the same launch-shape space for a replayed batch
 graph, timed on a sample batch of requests.
 
@@ -49,6 +51,7 @@ def candidates(W: int, grid_full: int):
     for p in per_wave:
         for w in (0, 2, 4):
             out.append(dict(mode=1, waves_per_block=w, blocks_per_wg=p, grid_wgs=0))
+        out.append(dict(mode=3, waves_per_block=0, blocks_per_wg=p, grid_wgs=0))
         out.append(dict(mode=2, waves_per_block=0, blocks_per_wg=p, grid_wgs=0))
         if grid_full:
             out.append(dict(mode=2, waves_per_block=0, blocks_per_wg=p, grid_wgs=grid_full // 2))

@@ -90,6 +90,8 @@ struct BatchArgs {
   uint64_t* loc;
   const uint8_t* pin;        // per block: 1 = decoded once and kept (its loc stays valid)
   const uint32_t* pin_base;  // slots taken by kept blocks; planned blocks go after them
+  uint32_t* chunk_cnt;       // compaction: per chunk of `order`, needed blocks (then their prefix)
+  uint32_t* chunk_seq;       // and their sequences; batch_compact_chunks + 1 entries each
 };
 
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
@@ -130,7 +132,11 @@ hipError_t static_scratch(void** ptr);
 hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s);
 hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s);
+uint32_t batch_compact_chunks(uint32_t n_blocks);
 hipError_t launch_batch_gather(const BatchArgs& b, const DecodeArgs& a, hipStream_t s);
+// a one-request descriptor (n = 1, d_out, then lo, hi at output offset 0)
+// written by a kernel from its arguments
+hipError_t launch_put_range(uint64_t* desc, uint64_t d_out, uint64_t lo, uint64_t hi, hipStream_t s);
 hipError_t launch_rans_dev(const DecodeArgs& a, uint32_t cap, uint32_t per_wave, hipStream_t s);
 // entropy decode of levels [lv_lo, lv_hi), whose plan range is read from
 // lvl_dev; width = the most entries those levels can hold

@@ -73,6 +73,8 @@ struct ace_archive {
   uint64_t all_seq = 0;
   PlanEntry* all_plan_pinned = nullptr;
   const PlanEntry* d_plan = nullptr;  // the whole-archive plan resident on the device, if attached
+  const uint32_t* d_order = nullptr;  // with it: all blocks by level, then the level boundaries
+  const uint32_t* d_lstart = nullptr;
   std::mutex pin_mu;
   ~ace_archive() {
     if (all_plan_pinned) (void)hipHostFree(all_plan_pinned);
@@ -618,29 +620,50 @@ extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out
              (uint64_t)(uintptr_t)d_out, t, static_cast<hipStream_t>(stream), true, true);
 }
 
+// The resident plan: the entries, then the blocks by level and the level
+// boundaries (the static data of device-side seek planning).
+static uint64_t plan_bytes(const ace_archive* A) {
+  return sizeof(PlanEntry) * (uint64_t)A->nb + 4ull * A->nb + 4ull * (A->depth + 1);
+}
+
 extern "C" int ace_plan_bytes(const ace_archive* A, uint64_t* bytes) {
   if (!A || !bytes) return fail(ACE_E_ARG, "null argument");
-  *bytes = sizeof(PlanEntry) * (uint64_t)A->nb;
+  *bytes = plan_bytes(A);
   return ACE_OK;
 }
 
 extern "C" int ace_archive_attach_plan(ace_archive* A, void* d_plan, uint64_t bytes, void* stream) {
   if (!A || (!d_plan && A->nb)) return fail(ACE_E_ARG, "null argument");
-  const uint64_t need = sizeof(PlanEntry) * (uint64_t)A->nb;
+  const uint64_t need = plan_bytes(A);
   if (bytes < need) return fail(ACE_E_NOSPACE, "the plan needs %llu bytes", (unsigned long long)need);
   if (A->nb == 0) return ACE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HIP_TRY(hipMemcpyAsync(d_plan, A->all_plan.data(), need, hipMemcpyHostToDevice, s));
+  std::vector<uint32_t> order(A->nb);
+  for (uint32_t i = 0; i < A->nb; i++) order[i] = A->all_plan[i].block;
+  uint8_t* d = static_cast<uint8_t*>(d_plan);
+  const uint64_t o_order = sizeof(PlanEntry) * (uint64_t)A->nb, o_lstart = o_order + 4ull * A->nb;
+  HIP_TRY(hipMemcpyAsync(d, A->all_plan.data(), o_order, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d + o_order, order.data(), 4ull * A->nb, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d + o_lstart, A->all_levels.data(), 4ull * (A->depth + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  A->d_plan = static_cast<const PlanEntry*>(d_plan);
+  A->d_plan = reinterpret_cast<const PlanEntry*>(d);
+  A->d_order = reinterpret_cast<const uint32_t*>(d + o_order);
+  A->d_lstart = reinterpret_cast<const uint32_t*>(d + o_lstart);
   return ACE_OK;
 }
 
-// One seek: plan the closure of [lo, hi) on the host and decode it into the
-// workspace ws (whole target blocks straight into d_out).  ws_need, when
-// given, receives the workspace size the seek needs (also on ACE_E_NOSPACE).
+static uint64_t seek_device_bytes(const ace_archive* A);
+static int seek_device(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, uint8_t* ws,
+                       const ace_tuning* t, hipStream_t s);
+
+// One seek into the workspace ws (whole target blocks straight into d_out
+// on the host-planned path).  Planned on the device when the archive's plan
+// is resident and ws holds seek_device_bytes (allow_device), else the
+// closure of [lo, hi) is planned on the host.  ws_need, when given, receives
+// the workspace size the host-planned seek needs (also on ACE_E_NOSPACE).
 static int seek_impl(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
-                     uint64_t ws_cap, const ace_tuning* t, void* stream, uint64_t* ws_need) {
+                     uint64_t ws_cap, const ace_tuning* t, void* stream, uint64_t* ws_need,
+                     bool allow_device = true) {
   timer_enter();
   if (!A) return fail(ACE_E_ARG, "null archive");
   if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
@@ -649,6 +672,10 @@ static int seek_impl(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_
                              (unsigned long long)A->n);
   if (lo == hi) return ACE_OK;
   if (!d_out || !d_ws) return fail(ACE_E_ARG, "null argument");
+  if (allow_device && A->d_order && ws_cap >= seek_device_bytes(A)) {
+    if (ws_need) *ws_need = seek_device_bytes(A);
+    return seek_device(A, lo, hi, d_out, static_cast<uint8_t*>(d_ws), t, static_cast<hipStream_t>(stream));
+  }
   const uint32_t t0 = (uint32_t)(lo / A->B), t1 = (uint32_t)((hi - 1) / A->B);
   std::vector<uint32_t> blocks, order, lstart;
   close_range(A, t0, t1, blocks);
@@ -707,7 +734,7 @@ extern "C" int ace_seek_static(const ace_archive* A, uint64_t lo, uint64_t hi, u
   // node if the caller captures this call)
   HIP_TRY(launch_fill_u32(static_cast<uint32_t*>(ws), 0u, kWsHeader / 4, s));
   uint64_t need = 0;
-  int rc = seek_impl(A, lo, hi, d_out, ws, kStaticScratchBytes, t, stream, &need);
+  int rc = seek_impl(A, lo, hi, d_out, ws, kStaticScratchBytes, t, stream, &need, false);
   if (rc == ACE_E_NOSPACE)
     return fail(ACE_E_NOSPACE, "the seek needs %llu bytes of scratch; the fixed scratch holds %llu",
                 (unsigned long long)need, (unsigned long long)kStaticScratchBytes);
@@ -809,7 +836,7 @@ struct ace_batch {
 namespace {
 struct BatchLayout {
   uint64_t order, lstart, need, pre, plan, nplan, lvl, loc, lit, lens, offs, slots, desc, pin, pinbase,
-      total;
+      chunks, total;
 };
 
 BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
@@ -835,10 +862,124 @@ BatchLayout batch_layout(const ace_archive* A, uint32_t cap) {
   L.desc = take(16 + 24ull * cap);
   L.pin = take(align_up(A->nb, 4));
   L.pinbase = take(4);
+  L.chunks = take(8ull * (batch_compact_chunks(A->nb) + 1));
   L.total = o;
   return L;
 }
 }  // namespace
+
+static uint64_t seek_device_bytes(const ace_archive* A) { return batch_layout(A, 1).total; }
+
+// A device-planned seek: the batch planner for one request (mark the target
+// blocks, close level by level, compact into a level-ordered plan), the
+// device-planned decode into workspace slots, then the copy of [lo, hi) to
+// d_out.  The host only enqueues: no closure walk.  The static planning data
+// (blocks by level, level boundaries) come from the resident plan.
+static int seek_device(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, uint8_t* ws,
+                       const ace_tuning* t, hipStream_t s) {
+  const uint32_t mode = t ? t->mode : 0;
+  if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) return fail(ACE_E_ARG, "unknown mode %u", mode);
+  int rc = check_tuning(A, t);
+  if (rc) return rc;
+  const BatchLayout L = batch_layout(A, 1);
+  BatchArgs ba{};
+  ba.arch = A->d_arch;
+  ba.B = A->B;
+  ba.n_blocks = A->nb;
+  ba.depth = A->depth;
+  ba.cap = 1;
+  ba.n_total = A->n;
+  ba.order = A->d_order;
+  ba.lstart = A->d_lstart;
+  ba.need = ws + L.need;
+  ba.pre = reinterpret_cast<uint32_t*>(ws + L.pre);
+  ba.desc = reinterpret_cast<const uint64_t*>(ws + L.desc);
+  ba.plan = reinterpret_cast<PlanEntry*>(ws + L.plan);
+  ba.n_plan_dev = reinterpret_cast<uint32_t*>(ws + L.nplan);
+  ba.lvl_dev = reinterpret_cast<uint32_t*>(ws + L.lvl);
+  ba.loc = reinterpret_cast<uint64_t*>(ws + L.loc);
+  ba.pin = ws + L.pin;
+  ba.pin_base = reinterpret_cast<const uint32_t*>(ws + L.pinbase);
+  ba.chunk_cnt = reinterpret_cast<uint32_t*>(ws + L.chunks);
+  ba.chunk_seq = ba.chunk_cnt + batch_compact_chunks(A->nb) + 1;
+  DecodeArgs a{};
+  a.arch = A->d_arch;
+  a.plan = ba.plan;
+  a.n_plan = A->nb;  // capacity: the real count is read on the device
+  a.B = A->B;
+  a.b_shift = shift_of(A->B);
+  a.W = A->W;
+  a.ow = A->ow;
+  a.n_blocks = A->nb;
+  a.n_total = A->n;
+  a.dst_base = (uint64_t)(uintptr_t)(ws + L.slots);
+  a.loc = ba.loc;
+  a.lit = ws + L.lit;
+  a.lens = ws + L.lens;
+  a.offs = ws + L.offs;
+  a.err = reinterpret_cast<uint32_t*>(ws);
+  a.ext_bytes = reinterpret_cast<unsigned long long*>(ws + kWsCounters);
+  a.n_plan_dev = ba.n_plan_dev;
+  a.lvl_dev = ba.lvl_dev;
+  a.n_lvl = A->depth;
+  persist_sync(a, ba.lvl_dev + persist_row(A->depth + 1));
+  a.max_polls = kMaxIdlePolls;
+  if (g_trace) {
+    if (g_trace_entries < A->nb)
+      return fail(ACE_E_NOSPACE, "the block trace holds %llu entries, a device-planned seek may plan %u",
+                  (unsigned long long)g_trace_entries, A->nb);
+    a.trace = g_trace;
+  }
+  const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
+  PhaseTimer& T = g_timer;
+  const bool timed = T.on;
+  std::chrono::steady_clock::time_point t_run;
+  if (timed) {
+    t_run = std::chrono::steady_clock::now();
+    T.us_plan = std::chrono::duration<double, std::micro>(t_run - T.t_enter).count();
+    T.n_ent = T.n_mat = 0;
+    T.recorded = false;
+    HIP_TRY(timer_pair(T.ent, 0));
+    HIP_TRY(timer_pair(T.mat, 0));
+  }
+  // request descriptor, marks and the (empty) kept-block table (the header's
+  // error word and counters accumulate as for every other call)
+  HIP_TRY(launch_put_range(reinterpret_cast<uint64_t*>(ws + L.desc), (uint64_t)(uintptr_t)d_out, lo, hi, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.need), 0u, align_up(A->nb, 4) / 4, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.pin), 0u, align_up(A->nb, 4) / 4, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.pinbase), 0u, 1, s));
+  HIP_TRY(launch_batch_mark(ba, s));
+  for (uint32_t l = A->depth; l-- > 1;)
+    HIP_TRY(launch_batch_close(ba, l, A->all_levels[l + 1] - A->all_levels[l], s));
+  HIP_TRY(launch_batch_compact(ba, s));
+  if (timed) HIP_TRY(hipEventRecord(T.ent[0], s));
+  if (mode == kModePersistent) {
+    HIP_TRY(launch_fill_u32(a.lvl_done, 0u, persist_sync_words(A->depth), s));
+    HIP_TRY(launch_rans_dev(a, A->nb, per_wave, s));
+    if (timed) {
+      HIP_TRY(hipEventRecord(T.ent[1], s));
+      HIP_TRY(hipEventRecord(T.mat[0], s));
+    }
+    HIP_TRY(launch_persistent(a, t ? t->grid_wgs : 0, s));
+  } else {
+    // modes 0, 1 and 3: one entropy launch, then one expansion per level
+    HIP_TRY(launch_rans_dev(a, A->nb, per_wave, s));
+    if (timed) {
+      HIP_TRY(hipEventRecord(T.ent[1], s));
+      HIP_TRY(hipEventRecord(T.mat[0], s));
+    }
+    for (uint32_t l = 0; l < A->depth; l++)
+      HIP_TRY(launch_expand_level_dev(a, l, A->all_levels[l + 1] - A->all_levels[l], waves, s));
+  }
+  if (timed) HIP_TRY(hipEventRecord(T.mat[1], s));
+  HIP_TRY(launch_batch_gather(ba, a, s));
+  if (timed) {
+    T.n_ent = T.n_mat = 1;
+    T.recorded = true;
+    T.us_enqueue = us_since(t_run);
+  }
+  return ACE_OK;
+}
 
 extern "C" int ace_workspace_bound(const ace_archive* A, uint32_t n_ranges, uint64_t total_bytes,
                                    uint64_t* bytes) {
@@ -922,6 +1063,8 @@ extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, 
     ba.loc = reinterpret_cast<uint64_t*>(b->ws + L.loc);
     ba.pin = b->ws + L.pin;
     ba.pin_base = reinterpret_cast<const uint32_t*>(b->ws + L.pinbase);
+    ba.chunk_cnt = reinterpret_cast<uint32_t*>(b->ws + L.chunks);
+    ba.chunk_seq = ba.chunk_cnt + batch_compact_chunks(A->nb) + 1;
     b->off_plan = L.plan;
     b->off_pin = L.pin;
     b->off_pinbase = L.pinbase;

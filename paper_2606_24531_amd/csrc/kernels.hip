@@ -434,12 +434,38 @@ struct ExpandSmem {
   uint32_t lm[kSeq];      // L | M << 16
   uint32_t lit[kSeq];     // index of the sequence's first literal in the literal stream
   uint32_t dfl[kSeq];     // min(d, 2^24 - 1) | flags << 24
-  uint32_t win[kSeq];     // readable bytes around src0: back (0..31) | forward << 5
+  uint32_t win[kSeq];     // readable bytes around src0: back (0..31) | forward << 5; unresolved: O - block start
   uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
   uint32_t deps[kDepCache];
   uint32_t scan[32];
 };
+
+// A workgroup barrier that orders LDS accesses only: global loads and stores
+// still in flight stay in flight (__syncthreads also waits for every one of
+// them).  The expansion's barriers guard its LDS tables; its global reads
+// never touch bytes written earlier in the same tile.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Whether p holds for any thread of the workgroup (every thread must call
+// it; an LDS barrier, with sh[0 .. kThreads/64) as scratch, which the caller
+// must not reuse before a later barrier).
+template <uint32_t kThreads>
+__device__ __forceinline__ bool wg_any(bool p, uint32_t* sh) {
+  constexpr uint32_t kW = kThreads / 64;
+  const bool w = __ballot(p) != 0;
+  if (kW == 1) return w;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w ? 1u : 0u;
+  lds_barrier();
+  uint32_t any = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kW; q++) any |= sh[q];
+  return any != 0;
+}
 
 // Inclusive scans of four values over the workgroup (kThreads threads):
 // v[j] becomes the sum of v[j] over threads 0..tid, t[j] the total.
@@ -454,12 +480,12 @@ __device__ __forceinline__ void wg_scan4(uint32_t (&v)[4], uint32_t (&t)[4], uin
     for (uint32_t j = 0; j < 4; j++) t[j] = lane63(v[j]);
     return;
   }
-  __syncthreads();
+  lds_barrier();
   if (lane == 63) {
 #pragma unroll
     for (uint32_t j = 0; j < 4; j++) sh[4 * w + j] = v[j];
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (uint32_t j = 0; j < 4; j++) {
     uint32_t o = 0, tot = 0;
@@ -498,7 +524,7 @@ __device__ __forceinline__ uint32_t wg_max_scan_strided4(uint32_t (&v)[4], uint3
 #pragma unroll
     for (uint32_t j = 0; j < 4; j++) sh[4 * w + j] = v[j];
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (uint32_t j = 0; j < 4; j++) {
     uint32_t before = run, tot = run;
@@ -552,6 +578,15 @@ __device__ __forceinline__ uint64_t blk_loc(const DecodeArgs& a, uint64_t blk) {
   return a.loc_linear ? a.dst_base + blk * a.B : *gp(a.loc + blk);
 }
 
+// Source offset of a sequence without a resolved address, relative to the
+// block start, as a signed 32-bit value (kOrelFar: too far back; then it is
+// read back from the offset stream).
+constexpr uint32_t kOrelFar = 0x80000000u;
+__device__ __forceinline__ uint32_t orel_pack(uint64_t o, uint64_t bs) {
+  const int64_t r = (int64_t)(o - bs);
+  return r > -(int64_t)0x7FFFFFFF && r < (int64_t)0x7FFFFFFF ? (uint32_t)(int32_t)r : kOrelFar;
+}
+
 // Slow path: the address of the byte at block-relative p, following sources
 // back to a literal, a resolved span, an earlier tile of this block or an
 // earlier block; null when the byte is to be written as zero (a failed
@@ -573,8 +608,13 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
       if (fl & kExt) n_ext++;
       return reinterpret_cast<const uint8_t*>(sm.src0[s] + im);
     }
-    const uint32_t k = c.t0 + s;  // O is read back from the token stream (rare path)
-    const uint64_t src = (c.ow == 4 ? (uint64_t)ld32(c.offs + 4ull * k) : ld64(c.offs + 8ull * k)) + im;
+    // the source offset, kept beside the sequence (read back from the token
+    // stream when too far back for 32 bits)
+    const uint32_t orel = sm.win[s];
+    const uint32_t k = c.t0 + s;
+    const uint64_t o = orel != kOrelFar ? c.bs + (uint64_t)(int64_t)(int32_t)orel
+                       : c.ow == 4 ? (uint64_t)ld32(c.offs + 4ull * k) : ld64(c.offs + 8ull * k);
+    const uint64_t src = o + im;
     if (src < c.bs) {
       if (!c.ext_ok) return nullptr;
       n_ext++;
@@ -863,10 +903,11 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       sm.lm[slot] = L[h] | (M[h] << 16);
       sm.lit[slot] = litk;
       sm.dfl[slot] = dist | (fl << 24);
-      sm.win[slot] = win;
+      // a span without an address keeps its source offset here instead
+      sm.win[slot] = (fl & (kSlow | kPend)) ? orel_pack(O[h], c.bs) : win;
       sm.src0[slot] = src0;
     }
-    __syncthreads();
+    lds_barrier();
     // ---- spans inside this tile: a literal run resolves at once; a span
     // inside one period of another match points at that match's span
 #pragma unroll
@@ -897,13 +938,13 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       sm.dfl[slot] = dist | (fl << 24);
       sm.ptr[slot] = ptr;
       sm.src0[slot] = src0;
-      sm.win[slot] = win;
+      sm.win[slot] = fl ? orel_pack(O[h], c.bs) : win;
       fl_h[h] = fl;
     }
     // ---- pointer doubling
     for (uint32_t round = 0;; round++) {
       const bool pend = (fl_h[0] | fl_h[1]) & kPend;
-      if (!__syncthreads_or(pend)) break;
+      if (!wg_any<kThreads>(pend, sm.scan)) break;
       uint32_t nfl[2] = {fl_h[0], fl_h[1]}, nptr[2] = {0, 0}, nwin[2] = {0, 0};
       uint64_t nsrc[2] = {0, 0};
 #pragma unroll
@@ -924,7 +965,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           nfl[h] = kSlow;
         }
       }
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (uint32_t h = 0; h < 2; h++) {
         if (!(fl_h[h] & kPend)) continue;
@@ -975,7 +1016,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       sm.pfx[tid + kThreads] = ct[1] + cv[3] - np[1];
       n_slow = ct[0] + ct[2];
       n_piece = ct[1] + ct[3];
-      __syncthreads();
+      lds_barrier();
     }
     // ---- pieces, four per thread per round: thread t takes pieces
     // t + j * kThreads of the round.  Each sequence marks its first piece;
@@ -992,7 +1033,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
           if (nxt > f && f >= p0 && f < p0 + kRound) sm.cseq[f - p0] = slot;
         }
       }
-      __syncthreads();
+      lds_barrier();
       uint32_t sqv[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
@@ -1081,15 +1122,32 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         }
         store_bytes(c.out + dsto[j], w, len[j]);
       }
-      __syncthreads();  // the marks of the next round are written after every read of this one
+      lds_barrier();  // the marks of the next round are written after every read of this one
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
     // sequences, tiles or non-adjacent blocks), one byte per thread, each
     // followed back to its origin (never to this tile's output)
-    for (uint32_t u = tid; u < n_slow; u += kThreads) {
-      const uint32_t p = slow_pos<kThreads>(sm, c, u);
-      const uint8_t* q = resolve_addr<kThreads>(a, sm, c, p, n_ext);
-      st8(c.out + p, q ? ld8(q) : (uint8_t)0);
+    // (four bytes per thread at a time: their addresses first, then the
+    // four loads in flight together, then the stores)
+    for (uint32_t u0 = tid; u0 < n_slow; u0 += 4 * kThreads) {
+      uint32_t pp[4];
+      const uint8_t* qq[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t u = u0 + j * kThreads;
+        pp[j] = 0;
+        qq[j] = nullptr;
+        if (u < n_slow) {
+          pp[j] = slow_pos<kThreads>(sm, c, u);
+          qq[j] = resolve_addr<kThreads>(a, sm, c, pp[j], n_ext);
+        }
+      }
+      uint8_t vv[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) vv[j] = qq[j] ? ld8(qq[j]) : (uint8_t)0;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (u0 + j * kThreads < n_slow) st8(c.out + pp[j], vv[j]);
     }
     // the next tile reads this tile's output and rewrites the tables
     if (t0 + kSeq < n_seq) __syncthreads();
@@ -1104,9 +1162,9 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   if (bad) flag(a.err, kErrCorrupt);
   // one counter update per block, spread over 16 counters
   n_ext = wave_total(n_ext);
-  __syncthreads();
+  lds_barrier();
   if ((tid & 63) == 0) sm.scan[tid >> 6] = n_ext;
-  __syncthreads();
+  lds_barrier();
   if (tid == 0) {
     uint32_t sum = 0;
     for (uint32_t w = 0; w < kThreads / 64; w++) sum += sm.scan[w];
@@ -1131,7 +1189,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       a.trace[8ull * i] = c0;
       a.trace[8ull * i + 1] = (unsigned long long)wall_clock64();
     }
-    if (i + stride < end) __syncthreads();  // every thread done with this block's LDS tables
+    if (i + stride < end) lds_barrier();  // every thread done with this block's LDS tables
   }
 }
 
@@ -1235,7 +1293,7 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
         mine++;
         if (tid == 0)
           sh_item[par ^ 1] = next < n_home ? lo + home + next * kPersistSlices : claim_any(a, lvl, lo, size, home + 1);
-        __syncthreads();  // every thread done with this block's LDS tables; next item visible
+        lds_barrier();  // every thread done with this block's LDS tables; next item visible
         par ^= 1;
         item = sh_item[par];
       }
@@ -1303,81 +1361,150 @@ __global__ void k_bmark(BatchArgs b) {
   }
 }
 
-__global__ void k_bclose(BatchArgs b, uint32_t level) {
+// One wavefront per block of the level (lanes over its dependency list).
+__global__ __launch_bounds__(256) void k_bclose(BatchArgs b, uint32_t level) {
+  const uint32_t lane = threadIdx.x & 63, wpg = blockDim.x >> 6;
   const uint32_t j0 = b.lstart[level], j1 = b.lstart[level + 1];
-  for (uint32_t j = j0 + blockIdx.x * blockDim.x + threadIdx.x; j < j1; j += gridDim.x * blockDim.x) {
+  for (uint32_t j = j0 + blockIdx.x * wpg + (threadIdx.x >> 6); j < j1; j += gridDim.x * wpg) {
     const uint32_t blk = b.order[j];
-    if (!b.need[blk]) continue;
+    if (!b.need[blk]) continue;  // uniform over the wavefront
     const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
     const uint32_t dep_off = ld32(be + 20), dep_cnt = ld32(be + 24);
     const uint32_t* deps = reinterpret_cast<const uint32_t*>(b.arch + kHdr + (uint64_t)kBlk * b.n_blocks) + dep_off;
-    for (uint32_t k = 0; k < dep_cnt; k++) {
+    for (uint32_t k = lane; k < dep_cnt; k += 64) {
       const uint32_t d = deps[k];
       if (!b.pin[d]) b.need[d] = 1;
     }
   }
 }
 
-// One workgroup of 1024 threads: running scans of "needed" and of n_seq.
-__global__ __launch_bounds__(1024) void k_bcompact(BatchArgs b) {
-  __shared__ uint32_t sh_cnt[16], sh_seq[16];
-  __shared__ uint32_t base_cnt, base_seq;
+// Compaction of the needed blocks, in level order, into the plan: chunks of
+// kCompactChunk positions of `order`.  (1) each workgroup counts its chunk's
+// needed blocks and their sequences; (2) one workgroup scans the chunk
+// totals; (3) each workgroup writes its chunk's plan entries at their scanned
+// positions, the level boundaries of the levels that start in it, and
+// (last chunk) the plan length.
+constexpr uint32_t kCompactChunk = 1024;
+
+__device__ __forceinline__ void need_fields(const BatchArgs& b, uint32_t j, uint32_t& blk, uint32_t& f,
+                                            uint32_t& ns) {
+  blk = 0;
+  f = 0;
+  ns = 0;
+  if (j < b.n_blocks) {
+    blk = b.order[j];
+    f = b.need[blk] ? 1u : 0u;
+    ns = f ? ld32(b.arch + kHdr + (uint64_t)kBlk * blk + 12) : 0u;
+  }
+}
+
+// Workgroup sums (kCompactChunk threads) of f and ns; exclusive prefixes of
+// both in oc / os for the calling thread.
+__device__ __forceinline__ void chunk_scan(uint32_t f, uint32_t ns, uint32_t& oc, uint32_t& os, uint32_t& tc,
+                                           uint32_t& ts) {
+  __shared__ uint32_t sh_cnt[kCompactChunk / 64], sh_seq[kCompactChunk / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) {
-    base_cnt = 0;
-    base_seq = 0;
+  const uint32_t ic = wave_incl_sum(f, lane), is = wave_incl_sum(ns, lane);
+  if (lane == 63) {
+    sh_cnt[w] = ic;
+    sh_seq[w] = is;
   }
   __syncthreads();
-  for (uint32_t j0 = 0; j0 < b.n_blocks; j0 += 1024) {
-    const uint32_t j = j0 + tid;
-    uint32_t blk = 0, f = 0, ns = 0;
-    if (j < b.n_blocks) {
-      blk = b.order[j];
-      f = b.need[blk] ? 1u : 0u;
-      ns = f ? ld32(b.arch + kHdr + (uint64_t)kBlk * blk + 12) : 0u;
+  oc = ic - f;
+  os = is - ns;
+  tc = ts = 0;
+  for (uint32_t k = 0; k < kCompactChunk / 64; k++) {
+    if (k < w) {
+      oc += sh_cnt[k];
+      os += sh_seq[k];
     }
-    const uint32_t ic = wave_incl_sum(f, lane), is = wave_incl_sum(ns, lane);
+    tc += sh_cnt[k];
+    ts += sh_seq[k];
+  }
+}
+
+__global__ __launch_bounds__(kCompactChunk) void k_bcount(BatchArgs b) {
+  uint32_t blk, f, ns, oc, os, tc, ts;
+  need_fields(b, blockIdx.x * kCompactChunk + threadIdx.x, blk, f, ns);
+  chunk_scan(f, ns, oc, os, tc, ts);
+  if (threadIdx.x == 0) {
+    b.chunk_cnt[blockIdx.x] = tc;
+    b.chunk_seq[blockIdx.x] = ts;
+  }
+}
+
+// One workgroup: exclusive scans of the chunk totals, in place; the grand
+// totals after the last chunk.
+__global__ __launch_bounds__(1024) void k_bscan(BatchArgs b, uint32_t n_chunks) {
+  __shared__ uint32_t sh_c[16], sh_s[16], base_c, base_s;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) base_c = base_s = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 <= n_chunks; c0 += 1024) {
+    const uint32_t c = c0 + tid;
+    const uint32_t vc = c < n_chunks ? b.chunk_cnt[c] : 0u, vs = c < n_chunks ? b.chunk_seq[c] : 0u;
+    const uint32_t ic = wave_incl_sum(vc, lane), is = wave_incl_sum(vs, lane);
     if (lane == 63) {
-      sh_cnt[w] = ic;
-      sh_seq[w] = is;
+      sh_c[w] = ic;
+      sh_s[w] = is;
     }
     __syncthreads();
-    uint32_t oc = base_cnt, os = base_seq, tc = 0, ts = 0;
+    uint32_t oc = base_c + ic - vc, os = base_s + is - vs, tc = 0, ts = 0;
     for (uint32_t k = 0; k < 16; k++) {
       if (k < w) {
-        oc += sh_cnt[k];
-        os += sh_seq[k];
+        oc += sh_c[k];
+        os += sh_s[k];
       }
-      tc += sh_cnt[k];
-      ts += sh_seq[k];
+      tc += sh_c[k];
+      ts += sh_s[k];
     }
-    const uint32_t pos = oc + ic - f, seq = os + is - ns;
-    if (j < b.n_blocks) b.pre[j] = pos;
-    if (f) {
-      const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
-      PlanEntry e{};
-      e.block = blk;
-      e.seq_base = seq;
-      e.dst = (uint64_t)(*b.pin_base + pos) * b.B;
-      e.pay = ld64(be);
-      e.n_seq = ns;
-      e.dep_off = ld32(be + 20);
-      e.dep_cnt = ld32(be + 24);
-      const uint8_t* d = b.arch + e.pay;
-      e.n_lit = ld32(d + 4);
-      for (uint32_t t = 0; t < 3; t++)
-        e.raw[t] = d[kSDesc * t] == 0 ? e.pay + ld32(d + kSDesc * t + 12) : kCoded;
-      b.plan[pos] = e;
+    if (c <= n_chunks) {
+      b.chunk_cnt[c] = oc;  // chunk n_chunks receives the grand totals
+      b.chunk_seq[c] = os;
     }
     __syncthreads();
     if (tid == 0) {
-      base_cnt += tc;
-      base_seq += ts;
+      base_c += tc;
+      base_s += ts;
     }
     __syncthreads();
   }
-  for (uint32_t l = tid; l <= b.depth; l += 1024) b.lvl_dev[l] = l < b.depth ? b.pre[b.lstart[l]] : base_cnt;
-  if (tid == 0) *b.n_plan_dev = base_cnt;
+}
+
+__global__ __launch_bounds__(kCompactChunk) void k_bwrite(BatchArgs b, uint32_t n_chunks) {
+  const uint32_t j = blockIdx.x * kCompactChunk + threadIdx.x;
+  uint32_t blk, f, ns, oc, os, tc, ts;
+  need_fields(b, j, blk, f, ns);
+  chunk_scan(f, ns, oc, os, tc, ts);
+  const uint32_t pos = b.chunk_cnt[blockIdx.x] + oc, seq = b.chunk_seq[blockIdx.x] + os;
+  if (j < b.n_blocks) {
+    b.pre[j] = pos;
+    // the first position of a level: that level's plan start
+    const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
+    const uint32_t lv = ld32(be + 16);
+    if (b.lstart[lv] == j) b.lvl_dev[lv] = pos;
+  }
+  if (f) {
+    const uint8_t* be = b.arch + kHdr + (uint64_t)kBlk * blk;
+    PlanEntry e{};
+    e.block = blk;
+    e.seq_base = seq;
+    e.dst = (uint64_t)(*b.pin_base + pos) * b.B;
+    e.pay = ld64(be);
+    e.n_seq = ns;
+    e.dep_off = ld32(be + 20);
+    e.dep_cnt = ld32(be + 24);
+    const uint8_t* d = b.arch + e.pay;
+    e.n_lit = ld32(d + 4);
+    for (uint32_t t = 0; t < 3; t++)
+      e.raw[t] = d[kSDesc * t] == 0 ? e.pay + ld32(d + kSDesc * t + 12) : kCoded;
+    b.plan[pos] = e;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t total = b.chunk_cnt[n_chunks];
+    b.lvl_dev[b.depth] = total;
+    *b.n_plan_dev = total;
+  }
 }
 
 // One workgroup per request: copy [lo, hi) from the decoded slots.
@@ -1389,6 +1516,11 @@ __global__ __launch_bounds__(256) void k_bgather(BatchArgs b, DecodeArgs a) {
   if (hi <= lo || hi > b.n_total) return;
   uint8_t* dst = reinterpret_cast<uint8_t*>(b.desc[1] + b.desc[4 + 3 * r]);
   copy_range(a, b.loc, lo, hi - lo, dst);
+}
+
+__global__ void k_put_range(uint64_t* desc, uint64_t d_out, uint64_t lo, uint64_t hi) {
+  const uint64_t v[5] = {1, d_out, lo, hi, 0};
+  if (threadIdx.x < 5) desc[threadIdx.x] = v[threadIdx.x];
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
@@ -1499,14 +1631,25 @@ hipError_t launch_batch_mark(const BatchArgs& b, hipStream_t s) {
 }
 
 hipError_t launch_batch_close(const BatchArgs& b, uint32_t level, uint32_t width, hipStream_t s) {
-  const uint32_t g = (width + 255) / 256;
+  const uint32_t g = (width + 3) / 4;  // four wavefronts per workgroup, one per block
   if (g == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bclose, dim3(g < 1024 ? g : 1024), dim3(256), 0, s, b, level);
+  hipLaunchKernelGGL(k_bclose, dim3(g < 4096 ? g : 4096), dim3(256), 0, s, b, level);
   return hipGetLastError();
 }
 
+uint32_t batch_compact_chunks(uint32_t n_blocks) { return (n_blocks + kCompactChunk - 1) / kCompactChunk; }
+
 hipError_t launch_batch_compact(const BatchArgs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcompact, dim3(1), dim3(1024), 0, s, b);
+  const uint32_t nc = batch_compact_chunks(b.n_blocks);
+  if (nc == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bcount, dim3(nc), dim3(kCompactChunk), 0, s, b);
+  hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, b, nc);
+  hipLaunchKernelGGL(k_bwrite, dim3(nc), dim3(kCompactChunk), 0, s, b, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_range(uint64_t* desc, uint64_t d_out, uint64_t lo, uint64_t hi, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_range, dim3(1), dim3(64), 0, s, desc, d_out, lo, hi);
   return hipGetLastError();
 }
 

@@ -108,7 +108,8 @@ void launch(dim3 grid, dim3 block, hipStream_t s, std::function<void()> body);
 #define __builtin_amdgcn_readlane(v, l) ((int)::simt::readlane((uint32_t)(v), (uint32_t)(l)))
 #define __builtin_amdgcn_readfirstlane(v) ((int)::simt::readfirstlane((uint32_t)(v)))
 #define __builtin_amdgcn_s_sleep(n) ::simt::spin_pause()
-#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_fence(order, ...) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_s_barrier() ::simt::syncthreads()
 #define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier()
 #define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
 

@@ -45,6 +45,8 @@ def lib():
         L.ace_batch_run.argtypes = [vp, vp, u32, vp, vp]
         L.ace_batch_destroy.argtypes = [vp]
         L.ace_batch_destroy.restype = None
+        L.ace_plan_bytes.argtypes = [vp, u64p]
+        L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
         L.simt_stream_create.restype = vp
         _lib = L
     return _lib
@@ -106,6 +108,24 @@ class Archive:
         _check(lib().ace_decode_all(self._h, _p(out), self.n_total, _p(ws), ws.size, t, None))
         _check(lib().ace_check(_p(ws), None))
         return out[:self.n_total].tobytes()
+
+    def seek_device(self, lo, hi, tuning=None):
+        """ace_seek planned on the device: the plan attached, and a workspace
+        of the size that selects device planning."""
+        L = lib()
+        if getattr(self, "_plan", None) is None:
+            b = C.c_uint64(0)
+            _check(L.ace_plan_bytes(self._h, C.byref(b)))
+            self._plan = np.zeros(max(b.value, 1), dtype=np.uint8)
+            _check(L.ace_archive_attach_plan(self._h, _p(self._plan), b.value, None))
+        b = C.c_uint64(0)
+        _check(L.ace_batch_workspace_bytes(self._h, 1, C.byref(b)))
+        out = np.zeros(max(hi - lo, 1), dtype=np.uint8)
+        ws = np.zeros(b.value, dtype=np.uint8)
+        t = C.byref(Tuning(**tuning)) if tuning else None
+        _check(L.ace_seek(self._h, lo, hi, _p(out), _p(ws), ws.size, t, None))
+        _check(L.ace_check(_p(ws), None))
+        return out[:hi - lo].tobytes()
 
     def seek(self, lo, hi, tuning=None):
         out = np.zeros(max(hi - lo, 1), dtype=np.uint8)

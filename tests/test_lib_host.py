@@ -88,7 +88,12 @@ def test_plan_bytes_and_attach_errors(lib):
     L = lib.lib()
     pb = C.c_uint64()
     assert L.ace_plan_bytes(h, C.byref(pb)) == 0
-    assert pb.value == 64 * 25  # one 64-byte entry per block
+    info = C.c_uint64(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+    assert L.ace_archive_info(h, *[C.byref(v) for v in info]) == 0
+    nb, depth = info[2].value, info[3].value
+    assert nb == 25
+    # one 64-byte entry per block, then the blocks by level and the level bounds
+    assert pb.value == 64 * nb + 4 * nb + 4 * (depth + 1)
     assert L.ace_archive_attach_plan(h, C.c_void_p(0x1000), pb.value - 1, None) == lib.E_NOSPACE
     assert L.ace_archive_attach_plan(h, None, pb.value, None) == lib.E_ARG
     L.ace_archive_close(h)

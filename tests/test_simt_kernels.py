@@ -48,6 +48,9 @@ if n <= (4 << 20):
     lo_r, hi_r = gen.seek_requests(n, 9, 3, max_len=3 * B)
     got_b = simt_lib.seek_batch_graph(arc, lo_r, hi_r, dict(mode=mode if mode != 3 else 1))
     assert all(g == x[int(l):int(h)] for g, l, h in zip(got_b, lo_r, hi_r)), "batch graph differs"
+    # single seeks planned on the device (the plan attached)
+    for l, h in list(zip(lo_r, hi_r))[:4] + [(0, n), (n - 1, n)]:
+        assert arc.seek_device(int(l), int(h), dict(mode=mode)) == x[int(l):int(h)], "device-planned seek differs"
 print("OK", arc.n_blocks, arc.depth)
 """
 
