@@ -589,23 +589,38 @@ __device__ __forceinline__ uint32_t orel_pack(uint64_t o, uint64_t bs) {
 
 // Slow path: the address of the byte at block-relative p, following sources
 // back to a literal, a resolved span, an earlier tile of this block or an
-// earlier block; null when the byte is to be written as zero (a failed
-// format rule, or an earlier block that was never published).  Reads LDS,
-// the offset stream and (outside whole-archive decodes) the location table.
+// earlier block (each step moves strictly backwards, so the walk ends), and
+// in run the number of bytes from p on whose sources lie consecutively from
+// that address (at least 1: the walk stops narrowing it at segment ends, a
+// period's wrap, the earlier tiles' end and the current block's start).
+// Null when the bytes are to be written as zeros (a failed format rule, or an
+// earlier block that was never published).  ext: the address lies in an
+// earlier block.  Reads LDS and (outside whole-archive decodes, or for
+// offsets too far back) the location table and the offset stream.
 template <uint32_t kThreads>
-__device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kThreads>& sm,
-                                       const BlockCtx& c, uint32_t p, uint32_t& n_ext) {
+__device__ const uint8_t* resolve_run(const DecodeArgs& a, const ExpandSmem<kThreads>& sm, const BlockCtx& c,
+                                      uint32_t p, uint32_t& run, bool& ext) {
+  uint32_t lim = 0xFFFFFFFFu;
+  ext = false;
   for (;;) {
     const uint32_t s = find_seq(sm.dst, c.cnt, p);
     const uint32_t fl = sm.dfl[s] >> 24;
-    if (fl & kPoison) return nullptr;
     const uint32_t r = p - sm.dst[s];
-    const uint32_t Ls = sm.lm[s] & 0xFFFFu;
-    if (r < Ls) return c.lit + sm.lit[s] + r;
+    const uint32_t Ls = sm.lm[s] & 0xFFFFu, Ms = sm.lm[s] >> 16;
+    if (fl & kPoison) {
+      run = min(lim, Ls + Ms > r ? Ls + Ms - r : 1u);
+      return nullptr;
+    }
+    if (r < Ls) {
+      run = min(lim, Ls - r);
+      return c.lit + sm.lit[s] + r;
+    }
     const uint32_t ii = r - Ls, d = sm.dfl[s] & 0xFFFFFFu;
     const uint32_t im = ii < d ? ii : ii % d;
+    lim = min(lim, Ms > d ? min(Ms - ii, d - im) : Ms - ii);
     if (!(fl & kUnres)) {
-      if (fl & kExt) n_ext++;
+      run = lim;
+      ext = (fl & kExt) != 0;
       return reinterpret_cast<const uint8_t*>(sm.src0[s] + im);
     }
     // the source offset, kept beside the sequence (read back from the token
@@ -616,28 +631,35 @@ __device__ const uint8_t* resolve_addr(const DecodeArgs& a, const ExpandSmem<kTh
                        : c.ow == 4 ? (uint64_t)ld32(c.offs + 4ull * k) : ld64(c.offs + 8ull * k);
     const uint64_t src = o + im;
     if (src < c.bs) {
-      if (!c.ext_ok) return nullptr;
-      n_ext++;
+      if (!c.ext_ok) {
+        run = 1;
+        return nullptr;
+      }
       const uint64_t blk = blk_of(a, src);
+      const uint64_t room = a.loc_linear ? c.bs - src : (blk + 1) * a.B - src;  // contiguous bytes there
+      run = (uint32_t)min((uint64_t)lim, room);
+      ext = true;
       return reinterpret_cast<const uint8_t*>(blk_loc(a, blk)) + (src - blk * a.B);
     }
     const uint32_t q = (uint32_t)(src - c.bs);
-    if (q < c.d0) return c.out + q;
+    if (q < c.d0) {
+      run = min(lim, c.d0 - q);
+      return c.out + q;
+    }
     p = q;
   }
 }
 
-// Block-relative position of slow byte u of the tile: slot k's slow bytes
-// end at sm.ptr[k] (its match bytes, numbered in sequence order).
+// The slot holding slow byte u of the tile: slot k's slow bytes (its match
+// bytes, numbered in sequence order) end at sm.ptr[k].
 template <uint32_t kThreads>
-__device__ __forceinline__ uint32_t slow_pos(const ExpandSmem<kThreads>& sm, const BlockCtx& c, uint32_t u) {
+__device__ __forceinline__ uint32_t slow_slot(const ExpandSmem<kThreads>& sm, const BlockCtx& c, uint32_t u) {
   uint32_t lo = 0, hi = c.cnt;  // first slot whose slow-byte end exceeds u
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
     if (sm.ptr[mid] > u) hi = mid; else lo = mid + 1;
   }
-  const uint32_t Mk = sm.lm[lo] >> 16, Lk = sm.lm[lo] & 0xFFFFu;
-  return sm.dst[lo] + Lk + (u - (sm.ptr[lo] - Mk));
+  return lo;
 }
 
 // 16 bytes from any byte address (one global load: this target's global
@@ -1125,29 +1147,33 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       lds_barrier();  // the marks of the next round are written after every read of this one
     }
     // ---- slow pass: the match bytes of slow sequences (spans that straddle
-    // sequences, tiles or non-adjacent blocks), one byte per thread, each
-    // followed back to its origin (never to this tile's output)
-    // (four bytes per thread at a time: their addresses first, then the
-    // four loads in flight together, then the stores)
-    for (uint32_t u0 = tid; u0 < n_slow; u0 += 4 * kThreads) {
-      uint32_t pp[4];
-      const uint8_t* qq[4];
+    // sequences, tiles or non-adjacent blocks), each thread an equal share of
+    // consecutive ones, followed back to their origin (never to this tile's
+    // output) a run of consecutive sources at a time
+    if (n_slow) {
+      const uint32_t per = (n_slow + kThreads - 1) / kThreads;
+      uint32_t u = tid * per;
+      const uint32_t u1 = min(u + per, n_slow);
+      uint32_t k = u < u1 ? slow_slot<kThreads>(sm, c, u) : 0u;
+      while (u < u1) {
+        const uint32_t Mk = sm.lm[k] >> 16, end_k = sm.ptr[k];
+        const uint32_t p = sm.dst[k] + (sm.lm[k] & 0xFFFFu) + (u - (end_k - Mk));
+        uint32_t run;
+        bool ext;
+        const uint8_t* q = resolve_run<kThreads>(a, sm, c, p, run, ext);
+        const uint32_t n = min(min(run, u1 - u), end_k - u);
+        if (ext) n_ext += n;
+        for (uint32_t i = 0; i < n; i += 4) {
+          uint8_t v[4];
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
-        const uint32_t u = u0 + j * kThreads;
-        pp[j] = 0;
-        qq[j] = nullptr;
-        if (u < n_slow) {
-          pp[j] = slow_pos<kThreads>(sm, c, u);
-          qq[j] = resolve_addr<kThreads>(a, sm, c, pp[j], n_ext);
+          for (uint32_t j = 0; j < 4; j++) v[j] = (q && i + j < n) ? ld8(q + i + j) : (uint8_t)0;
+#pragma unroll
+          for (uint32_t j = 0; j < 4; j++)
+            if (i + j < n) st8(c.out + p + i + j, v[j]);
         }
+        u += n;
+        while (u < u1 && sm.ptr[k] <= u) k++;  // on to the next slow slot
       }
-      uint8_t vv[4];
-#pragma unroll
-      for (uint32_t j = 0; j < 4; j++) vv[j] = qq[j] ? ld8(qq[j]) : (uint8_t)0;
-#pragma unroll
-      for (uint32_t j = 0; j < 4; j++)
-        if (u0 + j * kThreads < n_slow) st8(c.out + pp[j], vv[j]);
     }
     // the next tile reads this tile's output and rewrites the tables
     if (t0 + kSeq < n_seq) __syncthreads();

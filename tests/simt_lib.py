@@ -158,3 +158,17 @@ def seek_batch_graph(arc, lo, hi, tuning=None):
     _check(L.ace_check(_p(ws), None))
     L.ace_batch_destroy(h)
     return [out[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs, ln)]
+
+
+def decode_all_ext(arc, tuning=None):
+    """Whole-archive decode; returns (bytes, the workspace's count of match
+    bytes read from earlier blocks)."""
+    L = lib()
+    out = np.zeros(max(arc.n_total, 1), dtype=np.uint8)
+    ws = arc.workspace()
+    t = C.byref(Tuning(**tuning)) if tuning else None
+    _check(L.ace_decode_all(arc._h, _p(out), arc.n_total, _p(ws), ws.size, t, None))
+    _check(L.ace_check(_p(ws), None))
+    ext = C.c_uint64(0)
+    _check(L.ace_read_counters(_p(ws), None, C.byref(ext)))
+    return out[:arc.n_total].tobytes(), ext.value

@@ -72,3 +72,73 @@ def test_cpu_build_of_kernels_matches_oracle(case):
         r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
                            env=dict(os.environ, SIMT_RESIDENT=resident))
         assert r.returncode == 0 and "OK" in r.stdout, (resident, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+
+
+def _ext_bytes_reference(orc, a: bytes) -> int:
+    """Match bytes whose origin, followed back through this block's own
+    literals and matches, lies in an earlier block (the decode's reads from
+    earlier blocks, with every block expanded as one tile)."""
+    import numpy as np
+    info = orc.info(a)
+    B, nb = info["block_size"], info["n_blocks"]
+    total = 0
+    for b in range(nb):
+        lit, L, M, O = orc.block_tokens(a, b)
+        L, M, O = L.astype(np.int64), M.astype(np.int64), O.astype(np.int64)
+        bs = b * B
+        start = np.concatenate([[0], np.cumsum(L + M)[:-1]])
+        mstart = bs + start + L  # absolute start of each match
+        d = mstart - O
+        k = np.repeat(np.arange(len(M)), M)  # every match byte: its sequence
+        i = np.arange(len(k)) - np.repeat(np.cumsum(M) - M, M)
+        src = O[k] + i % d[k]
+        live = np.ones(len(k), dtype=bool)
+        while live.any():
+            ext = live & (src < bs)
+            total += int(ext.sum())
+            live &= ~ext
+            q = src[live] - bs
+            s = np.searchsorted(start, q, side="right") - 1
+            r = q - start[s]
+            in_match = r >= L[s]
+            idx = np.where(live)[0]
+            live[idx[~in_match]] = False  # a literal: not from an earlier block
+            idx = idx[in_match]
+            s, r = s[in_match], r[in_match]
+            ii = r - L[s]
+            src[idx] = O[s] + ii % d[s]
+    return total
+
+
+@pytest.mark.parametrize("name,n,B,mm", [("genome", 6 << 20, 16384, 20), ("mixed", 2_000_001, 16384, 16),
+                                         ("text", 500_000, 4096, 12)])
+def test_ext_counter_matches_origin_count(orc, name, n, B, mm):
+    """The workspace counter of match bytes read from earlier blocks (the
+    S_ext term of the algorithmic bytes) equals the count of match bytes
+    whose origin lies in an earlier block, with 512-thread workgroups (one
+    tile per block for these archives)."""
+    code = r"""
+import sys
+sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
+import gen, simt_lib
+from paper_2606_24531_amd import encode
+x = gen.by_name(%(name)r, %(n)d, 41)
+a = encode(x, block_size=%(B)d, interleave=32, min_match=%(mm)d, hash_len=%(mm)d, max_level=8)
+open(%(path)r, "wb").write(a)
+arc = simt_lib.Archive(a)
+y, ext = simt_lib.decode_all_ext(arc, dict(mode=1, waves_per_block=8))
+assert y == x
+print("EXT", ext)
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "a.bin")
+        r = subprocess.run([sys.executable, "-c", code % dict(root=ROOT, tests=HERE, name=name, n=n, B=B, mm=mm,
+                                                              path=path)],
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-2000:]
+        ext = int(r.stdout.split("EXT")[1].split()[0])
+        a = open(path, "rb").read()
+    info = orc.info(a)
+    assert max(orc.block_facts(a)[1]) <= 1024  # one tile per block
+    assert ext == _ext_bytes_reference(orc, a)
