@@ -223,32 +223,36 @@ def main():
     _log("generated %d bytes of %s in %.1fs" % (len(x), args.profile, time.time() - t0))
     x_dev = torch.from_numpy(np.frombuffer(x, dtype=np.uint8).copy()).to(dev)
     tuned = None
+    # the launch shape is tuned on the encoded archive itself unless given
+    shape_given = bool(args.mode or args.waves_per_block or args.per_wave or args.grid >= 0)
     if args.interleave == 0:
+        # the interleave width is an archive parameter: picked on a 32 MiB
+        # sample, re-encoded per candidate
         from paper_2606_24531_amd.autotune import tune
         t0 = time.time()
         tuned = tune(x[:min(len(x), 32 << 20)], args.profile, block_size=args.block,
                      min_match=args.min_match, max_level=args.max_level, log=_log)
         args.interleave = tuned["interleave"]
-        if not args.mode:
-            args.mode = tuned["mode"]
-            if args.grid < 0:
-                args.grid = tuned["grid_wgs"]
-        if not args.waves_per_block:
-            args.waves_per_block = tuned["waves_per_block"]
-        if not args.per_wave:
-            args.per_wave = tuned["blocks_per_wg"]
-        _log("autotune (%.1fs): W=%d, mode %d, %s waves per block, %d streams per wave, grid %s" % (
-            time.time() - t0, args.interleave, args.mode, args.waves_per_block or "auto", args.per_wave,
-            args.grid if args.grid > 0 else "full"))
-    if not args.mode:
-        args.mode = 1
-    args.grid = max(args.grid, 0)
+        _log("autotune (%.1fs): W=%d on the sample" % (time.time() - t0, args.interleave))
     enc = dict(interleave=args.interleave, min_match=args.min_match, hash_len=args.min_match, max_chain=32)
     t0 = time.time()
     a = cached_archive(args, x, args.block, args.max_level, enc)
     enc_s = time.time() - t0
     _log("encoded to %d bytes (ratio %.3f) in %.1fs" % (len(a), len(x) / len(a), enc_s))
     arc = Archive(a, device=dev)
+    shape_tuned = None
+    if not shape_given and tuned is not None:
+        from paper_2606_24531_amd.autotune import tune_archive
+        t0 = time.time()
+        shape_tuned = tune_archive(arc, x_dev, reps=5, log=_log)
+        args.mode, args.waves_per_block = shape_tuned["mode"], shape_tuned["waves_per_block"]
+        args.per_wave, args.grid = shape_tuned["blocks_per_wg"], shape_tuned["grid_wgs"]
+        _log("autotune on the archive (%.1fs): mode %d, %s waves per block, %d streams per wave, grid %s" % (
+            time.time() - t0, args.mode, args.waves_per_block or "auto", args.per_wave,
+            args.grid if args.grid > 0 else "full"))
+    if not args.mode:
+        args.mode = 1
+    args.grid = max(args.grid, 0)
     tuning = dict(mode=args.mode, waves_per_block=args.waves_per_block, blocks_per_wg=args.per_wave,
                   grid_wgs=args.grid)
     stream = torch.cuda.current_stream()
@@ -326,6 +330,12 @@ def main():
             "waves_per_block": args.waves_per_block or "auto",
             "streams_per_wave": args.per_wave or (2 if args.interleave <= 32 else 1),
             "autotuned": tuned is not None, "encode_s": round(enc_s, 1),
+            "autotune": None if tuned is None else {
+                "interleave_on_sample": {"chosen": tuned["interleave"], "sample_bytes": min(len(x), 32 << 20)},
+                "shape_on_archive": None if shape_tuned is None else {
+                    "chosen": {k: shape_tuned[k] for k in ("mode", "waves_per_block", "blocks_per_wg", "grid_wgs")},
+                    "candidates_ms": [{k: r[k] for k in ("mode", "waves_per_block", "blocks_per_wg", "grid_wgs", "ms")}
+                                      for r in shape_tuned["all"]]}},
             "dag": _dag_facts(a),
             "mode": {1: "entropy launch, then one expansion launch per level, one stream",
                      2: "entropy launch, then one persistent expansion launch for every level",

@@ -12,6 +12,8 @@ Whole-archive decode (`tune`): searches, on a sample of the workload,
     the first levels' expansion; 2: one persistent launch for all levels)
     and, for mode 2, the grid (every workgroup the device holds at once, or
     half of them).
+The launch shape alone (`tune_archive`): the same candidates timed on a
+resident archive of the workload itself (no re-encoding).
 Batched seeks (`tune_batch`): the same launch-shape space for a replayed batch
 graph, timed on a sample batch of requests.
 
@@ -116,6 +118,27 @@ def tune(sample: bytes, profile: str, block_size: int = 16384, min_match: int = 
     best = min(results, key=lambda r: r["ms"])
     _store(cache_path, key, {"best": best, "all": results, "time": time.time(),
                              "sample_bytes": len(sample)})
+    return best
+
+
+def tune_archive(arc, expect, reps: int = 5, log=None) -> dict:
+    """The fastest launch shape (mode, waves per block, streams per wave,
+    grid) for whole-archive decodes of an archive already resident, timed on
+    the archive itself; expect is the original bytes on the device.  Every
+    candidate's output is compared with it before it is ranked."""
+    import torch
+
+    grid_full = _grid_full(torch)
+    W = arc.interleave or 64
+    results = []
+    for c in candidates(W, grid_full):
+        ms = _time_decode(arc, c, reps, torch, expect)
+        results.append(dict(ms=ms, **c))
+        if log:
+            log("tune on the archive: mode=%d waves/block=%d streams/wave=%d grid=%d: %.3f ms" % (
+                c["mode"], c["waves_per_block"], c["blocks_per_wg"], c["grid_wgs"], ms))
+    best = dict(min(results, key=lambda r: r["ms"]))
+    best["all"] = results
     return best
 
 

@@ -407,27 +407,29 @@ __global__ __launch_bounds__(64) void k_rans(DecodeArgs a, uint32_t plan_lo, uin
 //     resolved span, so a chain of n such matches takes log2(n) rounds.
 // Output is then produced in pieces: each literal run and each resolved
 // match is cut into 16-byte pieces from its own first byte (the last piece
-// shorter).  A piece is one 16-byte load at any byte alignment (global
-// loads and stores take any alignment on this target; a load is moved back
-// when the bytes after the piece are not known readable), or two when a
-// periodic match wraps inside it, and one store of exactly its bytes; a
-// match whose period is shorter than 16 bytes, or whose readable window is
-// too small, is read byte by byte.  Pieces write disjoint bytes, so every
-// thread takes four of them per round with all loads in flight before any
-// store, whatever sequences they belong to.  Spans that straddle sequences
-// or blocks take the slow path: follow the source back until it reaches a
-// literal, a resolved span, an earlier tile or an earlier block (each step
-// moves strictly backwards), one byte per thread.
+// shorter; a match repeating a span of 16 bytes or more is cut period by
+// period).  A piece is one 16-byte load at any byte alignment (global loads
+// and stores take any alignment on this target; a load is moved back when
+// the bytes after the piece are not known readable) and one store of
+// exactly its bytes; a match whose period is shorter than 16 bytes, or
+// whose readable window is too small, is read byte by byte.  Pieces write
+// disjoint bytes, so every thread takes kPer of them per round with all
+// loads in flight before any store, whatever sequences they belong to.
+// Spans that straddle sequences or blocks take the slow path: follow the
+// source back until it reaches a literal, a resolved span, an earlier tile
+// or an earlier block (each step moves strictly backwards), a run of bytes
+// with consecutive sources at a time.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPoison = 1u, kSlow = 2u, kPend = 4u, kExt = 8u;
 constexpr uint32_t kUnres = kPoison | kSlow | kPend;  // flags of a span without an address
-constexpr uint32_t kDepCache = 896;  // dependency lists cached in LDS per block (longer: read from HBM)
+constexpr uint32_t kDepCache = 800;  // dependency lists cached in LDS per block (longer: read from HBM)
 constexpr uint32_t kMaxJumps = 12;   // pointer-doubling rounds (chains up to 4096)
+constexpr uint32_t kPer = 2;         // output pieces per thread per round
 
 template <uint32_t kThreads>
 struct ExpandSmem {
   static constexpr uint32_t kSeq = 2 * kThreads;    // sequences per tile (two per thread)
-  static constexpr uint32_t kRound = 4 * kThreads;  // output pieces per round (four per thread)
+  static constexpr uint32_t kRound = kPer * kThreads;  // output pieces per round (kPer per thread)
   uint32_t cseq[kRound];  // marks: the sequence whose first piece is each piece of the round (0 = none)
   uint32_t pfx[kSeq];     // index of the sequence's first output piece in the tile
   uint32_t dst[kSeq];     // block-relative start of the sequence
@@ -438,7 +440,7 @@ struct ExpandSmem {
   uint32_t ptr[kSeq];     // pending span: span of sequence (ptr >> 16) from offset (ptr & 0xFFFF)
   uint64_t src0[kSeq];    // address of the first byte of a resolved span
   uint32_t deps[kDepCache];
-  uint32_t scan[32];
+  uint32_t scan[kPer * kThreads / 64 > 32 ? kPer * kThreads / 64 : 32];
 };
 
 // A workgroup barrier that orders LDS accesses only: global loads and stores
@@ -499,21 +501,21 @@ __device__ __forceinline__ void wg_scan4(uint32_t (&v)[4], uint32_t (&t)[4], uin
   }
 }
 
-// Running maximum over kRound = 4 * kThreads values held strided: thread t
-// holds the values at positions t + j * kThreads (j < 4).  In place,
+// Running maximum over N * kThreads values held strided: thread t holds the
+// values at positions t + j * kThreads (j < N).  In place,
 // v[j] = max(carry, every value at or before its position); returns the
 // maximum of all of them and carry.  One barrier (none for one wavefront);
 // the caller must order any earlier reads of sh before it.
-template <uint32_t kThreads>
-__device__ __forceinline__ uint32_t wg_max_scan_strided4(uint32_t (&v)[4], uint32_t carry, uint32_t* sh) {
+template <uint32_t kThreads, uint32_t N>
+__device__ __forceinline__ uint32_t wg_max_scan_strided(uint32_t (&v)[N], uint32_t carry, uint32_t* sh) {
   constexpr uint32_t kW = kThreads / 64;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (uint32_t j = 0; j < 4; j++) v[j] = wave_incl_max(v[j]);
+  for (uint32_t j = 0; j < N; j++) v[j] = wave_incl_max(v[j]);
   uint32_t run = carry;
   if (kW == 1) {
 #pragma unroll
-    for (uint32_t j = 0; j < 4; j++) {
+    for (uint32_t j = 0; j < N; j++) {
       const uint32_t tot = lane63(v[j]);
       v[j] = max(v[j], run);
       run = max(run, tot);
@@ -522,14 +524,14 @@ __device__ __forceinline__ uint32_t wg_max_scan_strided4(uint32_t (&v)[4], uint3
   }
   if (lane == 63) {
 #pragma unroll
-    for (uint32_t j = 0; j < 4; j++) sh[4 * w + j] = v[j];
+    for (uint32_t j = 0; j < N; j++) sh[N * w + j] = v[j];
   }
   lds_barrier();
 #pragma unroll
-  for (uint32_t j = 0; j < 4; j++) {
+  for (uint32_t j = 0; j < N; j++) {
     uint32_t before = run, tot = run;
     for (uint32_t q = 0; q < kW; q++) {
-      const uint32_t x = sh[4 * q + j];
+      const uint32_t x = sh[N * q + j];
       if (q < w) before = max(before, x);
       tot = max(tot, x);
     }
@@ -546,6 +548,36 @@ __device__ __forceinline__ uint32_t find_seq(const uint32_t* sdst, uint32_t cnt,
     if (sdst[mid] <= p) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// n / d for n < 2^20 and d >= 1: a reciprocal estimate, then corrected by
+// one either way (the estimate is within one of the quotient).
+__device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
+  uint32_t q = (uint32_t)((float)n * __builtin_amdgcn_rcpf((float)d));
+  if (q * d > n) q--;
+  else if ((q + 1) * d <= n) q++;
+  return q;
+}
+
+// The same for a position p before the end of sequence `from` (sources
+// usually lie a few sequences back): steps back 1, 2, 4, ... sequences until
+// one starts at or before p, then a binary search within the last step.
+__device__ __forceinline__ uint32_t find_seq_before(const uint32_t* sdst, uint32_t from, uint32_t p) {
+  if (sdst[from] <= p) return from;
+  uint32_t hi = from, step = 1;
+  while (true) {
+    const uint32_t lo = hi > step ? hi - step : 0u;
+    if (sdst[lo] <= p) {
+      uint32_t a = lo, b = hi;  // sdst[a] <= p < sdst[b]
+      while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (sdst[mid] <= p) a = mid; else b = mid;
+      }
+      return a;
+    }
+    hi = lo;
+    step <<= 1;
+  }
 }
 
 // Index of c in the ascending list, or -1.
@@ -599,11 +631,10 @@ __device__ __forceinline__ uint32_t orel_pack(uint64_t o, uint64_t bs) {
 // offsets too far back) the location table and the offset stream.
 template <uint32_t kThreads>
 __device__ const uint8_t* resolve_run(const DecodeArgs& a, const ExpandSmem<kThreads>& sm, const BlockCtx& c,
-                                      uint32_t p, uint32_t& run, bool& ext) {
+                                      uint32_t s, uint32_t p, uint32_t& run, bool& ext) {
   uint32_t lim = 0xFFFFFFFFu;
   ext = false;
   for (;;) {
-    const uint32_t s = find_seq(sm.dst, c.cnt, p);
     const uint32_t fl = sm.dfl[s] >> 24;
     const uint32_t r = p - sm.dst[s];
     const uint32_t Ls = sm.lm[s] & 0xFFFFu, Ms = sm.lm[s] >> 16;
@@ -616,7 +647,7 @@ __device__ const uint8_t* resolve_run(const DecodeArgs& a, const ExpandSmem<kThr
       return c.lit + sm.lit[s] + r;
     }
     const uint32_t ii = r - Ls, d = sm.dfl[s] & 0xFFFFFFu;
-    const uint32_t im = ii < d ? ii : ii % d;
+    const uint32_t im = ii < d ? ii : ii - d * udiv_small(ii, d);  // ii < 2^16
     lim = min(lim, Ms > d ? min(Ms - ii, d - im) : Ms - ii);
     if (!(fl & kUnres)) {
       run = lim;
@@ -646,6 +677,7 @@ __device__ const uint8_t* resolve_run(const DecodeArgs& a, const ExpandSmem<kThr
       run = min(lim, c.d0 - q);
       return c.out + q;
     }
+    s = find_seq_before(sm.dst, s, q);  // the source lies before this sequence
     p = q;
   }
 }
@@ -776,15 +808,6 @@ __device__ __forceinline__ uint32_t win_pack(uint64_t back, uint64_t fwd) {
   return (uint32_t)(back < 31 ? back : 31) | ((uint32_t)(fwd < (1ull << 26) ? fwd : (1ull << 26)) << 5);
 }
 
-// n / d for n < 2^20 and d >= 1: a reciprocal estimate, then corrected by
-// one either way (the estimate is within one of the quotient).
-__device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
-  uint32_t q = (uint32_t)((float)n * __builtin_amdgcn_rcpf((float)d));
-  if (q * d > n) q--;
-  else if ((q + 1) * d <= n) q++;
-  return q;
-}
-
 // Output pieces of a match of m bytes (m < 2^16) whose byte i is span byte
 // i mod d: a match that repeats its span (m > d) with d >= 16 is cut period
 // by period, each period into 16-byte pieces from its start; any other match
@@ -826,7 +849,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
   // reads, right after reading them), ordered before the first marks by the
   // barriers of the token phase
 #pragma unroll
-  for (uint32_t j = 0; j < 4; j++) sm.cseq[tid + j * kThreads] = 0;
+  for (uint32_t j = 0; j < kPer; j++) sm.cseq[tid + j * kThreads] = 0;
   for (uint32_t t0 = 0; t0 < n_seq; t0 += kSeq) {
     // ---- two sequences per thread: tokens, scans, first classification
     uint32_t L[2] = {0, 0}, M[2] = {0, 0};
@@ -1040,10 +1063,10 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       n_piece = ct[1] + ct[3];
       lds_barrier();
     }
-    // ---- pieces, four per thread per round: thread t takes pieces
+    // ---- pieces, kPer per thread per round: thread t takes pieces
     // t + j * kThreads of the round.  Each sequence marks its first piece;
     // a running maximum over the round's pieces gives every piece its
-    // sequence.  All four pieces' loads are issued before any is stored.
+    // sequence.  All of a thread's loads are issued before any is stored.
     uint32_t carry = 0;  // the last sequence marked in earlier rounds
     for (uint32_t p0 = 0; p0 < n_piece; p0 += kRound) {
 #pragma unroll
@@ -1056,17 +1079,17 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         }
       }
       lds_barrier();
-      uint32_t sqv[4];
+      uint32_t sqv[kPer];
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
+      for (uint32_t j = 0; j < kPer; j++) {
         sqv[j] = sm.cseq[tid + j * kThreads];
         sm.cseq[tid + j * kThreads] = 0;
       }
-      carry = wg_max_scan_strided4<kThreads>(sqv, carry, sm.scan);
-      uint4 v1[4];
-      uint32_t dsto[4], len[4], sh1[4];
+      carry = wg_max_scan_strided<kThreads, kPer>(sqv, carry, sm.scan);
+      uint4 v1[kPer];
+      uint32_t dsto[kPer], len[kPer], sh1[kPer];
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
+      for (uint32_t j = 0; j < kPer; j++) {
         const uint32_t p = p0 + tid + j * kThreads;
         const bool on = p < n_piece;
         const uint32_t sq = sqv[j] < c.cnt ? sqv[j] : c.cnt - 1;
@@ -1134,7 +1157,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
       // assemble and store: the load shifted down by sh1 (or zeros);
       // exactly len bytes written
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++) {
+      for (uint32_t j = 0; j < kPer; j++) {
         if (!len[j]) continue;
         uint32_t w[4] = {v1[j].x, v1[j].y, v1[j].z, v1[j].w};
         if (sh1[j] == 0x100u) {
@@ -1160,7 +1183,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         const uint32_t p = sm.dst[k] + (sm.lm[k] & 0xFFFFu) + (u - (end_k - Mk));
         uint32_t run;
         bool ext;
-        const uint8_t* q = resolve_run<kThreads>(a, sm, c, p, run, ext);
+        const uint8_t* q = resolve_run<kThreads>(a, sm, c, k, p, run, ext);
         const uint32_t n = min(min(run, u1 - u), end_k - u);
         if (ext) n_ext += n;
         for (uint32_t i = 0; i < n; i += 4) {
@@ -1199,7 +1222,8 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
 }
 
 template <uint32_t kThreads>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_expand(DecodeArgs a, uint32_t plan_lo, int level) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThreads == 128 ? 6 : 4))) void k_expand(
+    DecodeArgs a, uint32_t plan_lo, int level) {
   __shared__ ExpandSmem<kThreads> sm;
   // host-planned: one block per workgroup; device-planned: the level's plan
   // range from device memory, strided over the grid (one call site, so the
