@@ -184,9 +184,11 @@ def main():
                     help="archive sizes as a fraction of 4/2/1/1 GiB")
     ap.add_argument("--serve-rates", default="1000,5000,20000,100000")
     ap.add_argument("--serve-count", type=int, default=3000)
-    ap.add_argument("--serve-keep", type=int, default=-1,
+    ap.add_argument("--serve-keep", default="-1",
                     help="serving: keep this many of each archive's lowest dependency levels "
-                         "decoded per slot (captured batch graphs); -1 = plain batched seeks")
+                         "decoded per slot in its batch graphs (-1: none); 'host': host-planned "
+                         "batched seeks instead of graphs; a comma-separated list runs each "
+                         "setting in turn on the same archives")
     ap.add_argument("--suite", default="",
                     help="instead of the headline decode, run the other workloads and print one "
                          "JSON line each: genome1m (1 MiB genome, decode + every block sought with "
@@ -299,12 +301,18 @@ def main():
     _log("phases: entropy %.3f ms, match %.3f ms (dominant: %s)" % (ms_ent, ms_mat, dom))
 
     if args.calib:
+        # counter calibration, each a kernel of its own with known bytes:
+        # a fill (256 MiB written with 16-byte stores), a sum over 64-bit
+        # words (256 MiB read), a copy (256 MiB read and 256 MiB written)
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
-        src.fill_(1)      # 256 MiB written with 16-byte stores
+        src.fill_(1)
         torch.cuda.synchronize()
-        _ = src.view(torch.int32).sum()  # 256 MiB read
+        _ = src.view(torch.int64).sum()
         torch.cuda.synchronize()
-        _log("calibration fill and sum of 256 MiB done")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del dst
+        _log("calibration fill, sum and copy of 256 MiB done")
 
     workload = "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
         args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level)
@@ -502,14 +510,31 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
         t_one = time.perf_counter() - t
         assert y1 == x
         del y1
+        # single seeks on one core: the oracle's seek (its closure, decoded in
+        # order) on the first requests of the seek list, bounded to ~10 s
+        lo_s, hi_s = gen.seek_requests(len(x), 200, 4, max_len=4 << 20)
+        seek_ms = []
+        t_end = time.perf_counter() + 10.0
+        for i in range(len(lo_s)):
+            if seek_ms and time.perf_counter() > t_end:
+                break
+            t = time.perf_counter()
+            got = oracle.seek(a, int(lo_s[i]), int(hi_s[i]))
+            seek_ms.append(1e3 * (time.perf_counter() - t))
+            assert got == x[int(lo_s[i]):int(hi_s[i])]
         result["cpu_baseline"] = dict({
             "value": round(len(x) / t_all / 1e9, 4), "unit": "GB/s", "cores": used, "kind": "oracle",
             "sample": "one full decode of the same archive, the blocks of each dependency level "
                       "decoded in parallel (OpenMP)",
             "one_core_GBs": round(len(x) / t_one / 1e9, 4),
+            "one_core_seek_p50_ms": round(float(np.percentile(seek_ms, 50)), 3),
+            "one_core_seek_p99_ms": round(float(np.percentile(seek_ms, 99)), 3),
+            "seek_sample": "the first %d requests of the seek list (seed 4), oracle seek on one core"
+                           % len(seek_ms),
             "oracle_flags": " ".join(oracle.CFLAGS)}, **cpu_facts())
-        _log("cpu oracle: %.3f GB/s on %d threads, %.3f GB/s on one" % (
-            result["cpu_baseline"]["value"], used, result["cpu_baseline"]["one_core_GBs"]))
+        _log("cpu oracle: %.3f GB/s on %d threads, %.3f GB/s on one; one-core seek p50 %.1f ms over %d" % (
+            result["cpu_baseline"]["value"], used, result["cpu_baseline"]["one_core_GBs"],
+            result["cpu_baseline"]["one_core_seek_p50_ms"], len(seek_ms)))
 
     print(json.dumps(result), flush=True)
 
@@ -532,6 +557,7 @@ def serve_main(args):
     for name, full in sizes.items():
         n = int(full * args.serve_scale)
         t0 = time.time()
+        _log("%s: generating %d bytes" % (name, n))
         x = gen.by_name(name, n, seeds[name])
         a = encode(x, block_size=args.block, interleave=args.interleave or 64, min_match=mm[name],
                    hash_len=mm[name], max_chain=32, max_level=args.max_level)
@@ -540,41 +566,48 @@ def serve_main(args):
         _log("%s: %d bytes, ratio %.3f, %.1fs" % (name, n, n / len(a), time.time() - t0))
         del x
     rates = [float(r) for r in args.serve_rates.split(",")]
-    runs = []
-    keep = args.serve_keep if args.serve_keep >= 0 else None
     budget = 32 << 30
-    backend = GpuBackend(arcs, slots=4, keep_levels=keep, max_batch=4096, batch_bytes=budget)
-    dev_bytes = backend.device_bytes()
-    _log("device memory held by the server: %s, output budget %d" % (dev_bytes, budget))
-    for rate in rates:
-        # every 97th result is checked against the oracle's seek of the
-        # compressed archive after the run; results are released as they
-        # complete, which returns their bytes to the budget
-        sample = {}
-        srv = Server(backend, budget_bytes=budget, slots=4, max_batch=4096, auto_release=True,
-                     on_done=lambda r: r.rid % 97 == 0 and sample.__setitem__(r.rid, r.result.cpu()))
-        reqs, wall = poisson_run(srv, list(arcs), n_total, rate=rate, count=args.serve_count,
-                                 seed=int(rate), min_len=16, max_len=16 << 20)
-        torch.cuda.synchronize()
-        rep = latency_report(reqs, wall)
-        ok = True
-        for r in reqs:
-            if r.rid in sample:
-                solo = arcs[r.archive].seek(r.lo, r.hi)
-                ok = ok and bool(torch.equal(solo.cpu(), sample[r.rid]))
-        rep.update(offered_req_per_s=rate, batches=srv.batches, peak_out_bytes=srv.peak_used,
-                   sampled_results_equal_solo_seek=ok, n_sampled=len(sample), **limiter(srv))
-        runs.append(rep)
-        _log("rate %.0f/s: p50 %.3f ms p99 %.3f ms, %.0f req/s, limiter %s" % (
-            rate, rep["p50_ms"], rep["p99_ms"], rep["req_per_s"], rep["limiter"]))
-    print(json.dumps({
-        "metric": "seek latency p50/p99 vs throughput (serving loop)", "unit": "ms",
-        "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
-        "config": {"workload": "resident genome/fastq/text/mixed archives at %.4g of 4/2/1/1 GiB, "
-                               "Poisson arrivals, 16 B..16 MiB log-uniform, 32 GiB budget, 4 slots"
-                               % args.serve_scale,
-                   "kept_levels": keep, "output_budget_bytes": budget, "device_bytes": dev_bytes},
-        "runs": runs}), flush=True)
+    for keep_arg in str(args.serve_keep).split(","):
+        host = keep_arg.strip() == "host"
+        keep = None if host or int(keep_arg) < 0 else int(keep_arg)
+        runs = []
+        backend = GpuBackend(arcs, slots=4, keep_levels=keep, max_batch=4096, batch_bytes=budget,
+                             host_planned=host)
+        dev_bytes = backend.device_bytes()
+        _log("%s, kept levels %s: device memory held by the server %s, output budget %d" % (
+            "host-planned batches" if host else "batch graphs", keep, dev_bytes, budget))
+        for rate in rates:
+            # every 97th result is compared with a solo seek of the same range
+            # after the run; results are released as they complete, which
+            # returns their bytes to the budget
+            sample = {}
+            srv = Server(backend, budget_bytes=budget, slots=4, max_batch=4096, auto_release=True,
+                         on_done=lambda r: r.rid % 97 == 0 and sample.__setitem__(r.rid, r.result.cpu()))
+            reqs, wall = poisson_run(srv, list(arcs), n_total, rate=rate, count=args.serve_count,
+                                     seed=int(rate), min_len=16, max_len=16 << 20)
+            torch.cuda.synchronize()
+            rep = latency_report(reqs, wall)
+            ok = True
+            for r in reqs:
+                if r.rid in sample:
+                    solo = arcs[r.archive].seek(r.lo, r.hi)
+                    ok = ok and bool(torch.equal(solo.cpu(), sample[r.rid]))
+            rep.update(offered_req_per_s=rate, batches=srv.batches, peak_out_bytes=srv.peak_used,
+                       sampled_results_equal_solo_seek=ok, n_sampled=len(sample), **limiter(srv))
+            runs.append(rep)
+            _log("rate %.0f/s: p50 %.3f ms p99 %.3f ms, %.0f req/s, limiter %s" % (
+                rate, rep["p50_ms"], rep["p99_ms"], rep["req_per_s"], rep["limiter"]))
+        print(json.dumps({
+            "metric": "seek latency p50/p99 vs throughput (serving loop)", "unit": "ms",
+            "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+            "config": {"workload": "resident genome/fastq/text/mixed archives at %.4g of 4/2/1/1 GiB, "
+                                   "Poisson arrivals, 16 B..16 MiB log-uniform, 32 GiB budget, 4 slots"
+                                   % args.serve_scale,
+                       "planning": "host" if host else "device (batch graphs)",
+                       "kept_levels": keep, "output_budget_bytes": budget, "device_bytes": dev_bytes},
+            "runs": runs}), flush=True)
+        del backend
+        torch.cuda.empty_cache()
 
 
 def _dag_facts(a: bytes) -> dict:

@@ -717,7 +717,7 @@ __device__ __forceinline__ uint32_t pick4(const uint32_t (&y)[8], uint32_t i, ui
   return q == 0 ? y[i] : q == 1 ? y[i + 1] : q == 2 ? y[i + 2] : y[i + 3];
 }
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t b) {  // b in 0..24 step 8
-  return b ? (lo >> b) | (hi << (32 - b)) : lo;
+  return __builtin_amdgcn_alignbyte(hi, lo, b >> 3);  // bytes b/8.. of hi:lo
 }
 __device__ __forceinline__ void shift_down16(uint32_t (&x)[4], uint32_t s) {
   const uint32_t q = s >> 2, b = 8 * (s & 3);
@@ -1162,7 +1162,7 @@ __device__ __forceinline__ void expand_block(const DecodeArgs& a, uint32_t i, Ex
         uint32_t w[4] = {v1[j].x, v1[j].y, v1[j].z, v1[j].w};
         if (sh1[j] == 0x100u) {
           w[0] = w[1] = w[2] = w[3] = 0u;
-        } else {
+        } else if (sh1[j] != 0) {  // a load moved back (rare): bytes to line up
           shift_down16(w, sh1[j]);
         }
         store_bytes(c.out + dsto[j], w, len[j]);

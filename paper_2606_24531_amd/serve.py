@@ -5,21 +5,22 @@ Section 9).  Requests name an archive and an absolute byte range.  A request
 is admitted once its output bytes fit the output budget; admitted requests
 are grouped per archive into a batch as soon as one of K in-flight slots is
 free; each slot owns a HIP stream and a workspace, so batches on different
-slots overlap on the device.  A batch is one seek_batch call (one
-dependency-ordered decode of the union of the requests' closures, then one
-gather), or, with keep_levels, one replay of a captured batch graph per
-(slot, archive) whose lowest dependency levels stay decoded (ace_batch_pin),
-so closures stop there.  Latency is measured from a request's scheduled
+slots overlap on the device.  A batch is one replay of a captured batch
+graph per (slot, archive): the union of the requests' closures is planned on
+the device, decoded level by level, and gathered; with keep_levels the
+graph's lowest dependency levels stay decoded (ace_batch_pin), so closures
+stop there.  A host-planned backend runs one seek_batch call per batch
+instead.  Latency is measured from a request's scheduled
 arrival to the completion of its batch, so queueing is included.
 
 Device memory is bounded up front.  A result is a view of its batch's output
 buffer; the batch's bytes stay charged to the output budget until the
 consumer has released every request of the batch (Server.release, or
 auto_release after an on_done callback), so outputs never hold more than the
-budget.  Every workspace is allocated when the backend is built (per slot,
-sized by the library's bound for a batch of max_batch requests filling the
-budget; or one captured batch graph per slot and archive with kept levels)
-and reported by device_bytes().
+budget.  Every workspace is allocated when the backend is built (one
+captured batch graph per slot and archive; or, host-planned, one workspace
+per slot sized by the library's bound for a batch of max_batch requests
+filling the budget) and reported by device_bytes().
 
 The device work goes through a backend object so the scheduling logic can
 be exercised without a GPU; GpuBackend is the real one.
@@ -59,27 +60,28 @@ class _Batch:
 
 
 class GpuBackend:
-    """Slots on HIP streams, decoding with libaceseek's batched seek.  Every
-    workspace is allocated here: one per slot, sized by the library's bound
-    for max_batch ranges of at most batch_bytes in all (the plain path), or
-    one captured batch graph per (slot, archive) whose lowest keep_levels
-    levels stay decoded."""
+    """Slots on HIP streams.  Every workspace is allocated here.  By default
+    each (slot, archive) owns a captured batch graph (device-side planning,
+    one replay per batch), whose lowest keep_levels levels stay decoded when
+    keep_levels is given; with host_planned, each slot instead owns one
+    workspace sized by the library's bound for max_batch ranges of at most
+    batch_bytes in all, and a batch is one host-planned seek_batch call."""
 
     def __init__(self, archives: dict, slots: int, device="cuda:0", keep_levels=None, max_batch: int = 4096,
-                 batch_bytes: int = 1 << 30):
+                 batch_bytes: int = 1 << 30, host_planned: bool = False):
         import torch
         self.torch = torch
         self.archives = archives
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.ws = [None] * slots
-        # kept levels: a batch graph per (slot, archive), its lowest levels decoded once
         self.batches = {}
-        if keep_levels is not None:
+        if not host_planned:
             for slot in range(slots):
                 for name, arc in archives.items():
                     bt = arc.batch(max_batch, stream=self.streams[slot])
-                    bt.pin(min(int(keep_levels), arc.depth))
+                    if keep_levels:
+                        bt.pin(min(int(keep_levels), arc.depth))
                     self.batches[(slot, name)] = bt
         else:
             need = max(arc.workspace_bound(max_batch, batch_bytes) for arc in archives.values())
@@ -149,8 +151,11 @@ class Server:
         self.peak_used = 0
         self.batches = 0
         # scheduling passes, and those that found every slot busy or the
-        # oldest pending request not fitting the budget (what limits a run)
+        # oldest pending request not fitting the budget; host seconds spent
+        # launching and finishing batches (what limits a run)
         self.passes = self.passes_slots_full = self.passes_budget_full = 0
+        self.host_s = 0.0
+        self.t_first = None
 
     def submit(self, archive: str, lo: int, hi: int, t_arrival: float = None) -> Request:
         with self.lock:
@@ -174,9 +179,13 @@ class Server:
         """One scheduling pass; returns True if anything is still in progress."""
         with self.lock:
             # completions free slots; budget comes back as results are released
+            if self.t_first is None:
+                self.t_first = time.perf_counter()
             for slot, (h, reqs, nb) in list(self.inflight.items()):
                 if self.backend.poll(h):
+                    t_h = time.perf_counter()
                     views = self.backend.finish(h)
+                    self.host_s += time.perf_counter() - t_h
                     t = time.perf_counter()
                     batch = _Batch(nb, len(reqs))
                     for r, v in zip(reqs, views):
@@ -204,7 +213,9 @@ class Server:
                 name = min(names, key=lambda n: self.admitted[n][0].t_arrival)
                 q = self.admitted[name]
                 reqs = [q.popleft() for _ in range(min(len(q), self.max_batch))]
+                t_h = time.perf_counter()
                 h = self.backend.launch(slot, name, reqs)
+                self.host_s += time.perf_counter() - t_h
                 self.inflight[slot] = (h, reqs, sum(r.nbytes for r in reqs))
                 self.batches += 1
             busy = bool(self.inflight or self.pending or any(self.admitted.values()))
@@ -264,12 +275,21 @@ def poisson_run(server: Server, names, n_total: dict, rate: float, count: int, s
 
 
 def limiter(server: Server) -> dict:
-    """Shares of scheduling passes that found admitted work waiting for a
-    slot (device-bound) or arrived work waiting for budget (memory-bound)."""
+    """What held a run back: the share of wall time the scheduler spent in
+    the host part of launching and finishing batches (host-bound), and the
+    shares of scheduling passes that found admitted work waiting for a slot
+    (device-bound) or arrived work waiting for budget (memory-bound)."""
     n = max(server.passes, 1)
     slots, budget = server.passes_slots_full / n, server.passes_budget_full / n
-    name = "slots" if slots >= budget and slots > 0.05 else "budget" if budget > 0.05 else "arrivals"
-    return {"passes": server.passes, "slots_full_share": round(slots, 4),
+    wall = time.perf_counter() - server.t_first if server.t_first else 0.0
+    host = server.host_s / wall if wall > 0 else 0.0
+    if host > 0.5:
+        name = "host"
+    elif slots >= budget and slots > 0.05:
+        name = "slots"
+    else:
+        name = "budget" if budget > 0.05 else "arrivals"
+    return {"passes": server.passes, "host_share": round(host, 4), "slots_full_share": round(slots, 4),
             "budget_full_share": round(budget, 4), "limiter": name}
 
 

@@ -112,6 +112,8 @@ void launch(dim3 grid, dim3 block, hipStream_t s, std::function<void()> body);
 #define __builtin_amdgcn_s_barrier() ::simt::syncthreads()
 #define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier()
 #define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
+#define __builtin_amdgcn_alignbyte(hi, lo, k) \
+  ((uint32_t)(((((uint64_t)(uint32_t)(hi)) << 32) | (uint32_t)(lo)) >> (8 * ((uint32_t)(k) & 3u))))
 
 inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t m, uint32_t base) {
   const uint32_t l = ::simt::lane_id();

@@ -1,7 +1,8 @@
 """Continuous batching on the GPU: requests arriving while others run are
 admitted into free slots (each slot its own HIP stream and workspace), and
-every result is byte-identical alone and in the mix, with plain batched
-seeks and with captured batch graphs that keep level 0 decoded."""
+every result is byte-identical alone and in the mix, with captured batch
+graphs (device-side planning), with graphs that keep level 0 decoded, and
+with host-planned batched seeks."""
 import numpy as np
 import pytest
 
@@ -11,8 +12,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("keep", [None, 1], ids=["plain", "kept-level-0"])
-def test_results_same_alone_and_in_mix(orc, keep):
+@pytest.mark.parametrize("keep,host", [(None, False), (1, False), (None, True)],
+                         ids=["graphs", "graphs-kept-level-0", "host-planned"])
+def test_results_same_alone_and_in_mix(orc, keep, host):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2606_24531_amd import Archive, encode
@@ -21,7 +23,7 @@ def test_results_same_alone_and_in_mix(orc, keep):
           "text": gen.text(2 << 20, 53)}
     arcs = {k: Archive(encode(v, block_size=16384, interleave=32, min_match=16, hash_len=16,
                               max_level=8), device="cuda:0") for k, v in xs.items()}
-    backend = GpuBackend(arcs, slots=3, keep_levels=keep, max_batch=64, batch_bytes=8 << 20)
+    backend = GpuBackend(arcs, slots=3, keep_levels=keep, max_batch=64, batch_bytes=8 << 20, host_planned=host)
     # the consumer copies each result out as it completes and releases it,
     # which returns its bytes to the budget
     got = {}

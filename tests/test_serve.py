@@ -91,7 +91,9 @@ def test_poisson_driver_reports(orc, corpus):
         assert got[r.rid] == xs[r.archive][r.lo:r.hi]
     assert srv.used == 0
     lim = limiter(srv)
-    assert lim["passes"] > 0 and lim["limiter"] in ("slots", "budget", "arrivals")
+    # the fake backend decodes on the host inside launch: host time is counted
+    assert lim["passes"] > 0 and lim["host_share"] > 0
+    assert lim["limiter"] in ("host", "slots", "budget", "arrivals")
 
 
 def test_held_results_keep_their_budget(orc, corpus):
