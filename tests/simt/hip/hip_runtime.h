@@ -112,6 +112,19 @@ void launch(dim3 grid, dim3 block, hipStream_t s, std::function<void()> body);
 #define __builtin_amdgcn_s_barrier() ::simt::syncthreads()
 #define __builtin_amdgcn_wave_barrier() ::simt::wave_barrier()
 #define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
+// v_perm_b32: byte i of the result is byte sel_i of src0:src1 (src1 the low
+// dword); selectors 0..7 pick bytes, 12 gives 0x00, 13 gives 0xFF
+inline uint32_t simt_perm(uint32_t src0, uint32_t src1, uint32_t sel) {
+  const uint64_t v = ((uint64_t)src0 << 32) | src1;
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < 4; i++) {
+    const uint32_t k = (sel >> (8 * i)) & 0xFFu;
+    const uint32_t b = k < 8 ? (uint32_t)(v >> (8 * k)) & 0xFFu : k == 13 ? 0xFFu : 0u;
+    r |= b << (8 * i);
+  }
+  return r;
+}
+#define __builtin_amdgcn_perm(src0, src1, sel) simt_perm((uint32_t)(src0), (uint32_t)(src1), (uint32_t)(sel))
 #define __builtin_amdgcn_alignbyte(hi, lo, k) \
   ((uint32_t)(((((uint64_t)(uint32_t)(hi)) << 32) | (uint32_t)(lo)) >> (8 * ((uint32_t)(k) & 3u))))
 

@@ -78,6 +78,8 @@ uint32_t dpp_one(const Lane* const* w, uint32_t l, uint32_t old, int ctl, int ro
   if (ctl >= 0x111 && ctl <= 0x11F) {
     const uint32_t k = (uint32_t)ctl - 0x110;
     if (pos >= k) src = (int)(l - k);
+  } else if (ctl >= 0 && ctl <= 0xFF) {  // quad_perm: lane q of each quad reads lane (ctl >> 2q) & 3
+    src = (int)((l & ~3u) + (((uint32_t)ctl >> (2 * (l & 3))) & 3u));
   } else if (ctl == 0x142) {  // row_bcast:15
     if (row > 0) src = (int)(16 * (row - 1) + 15);
   } else if (ctl == 0x143) {  // row_bcast:31
