@@ -145,6 +145,57 @@ def decode_entry(arc, a, x_dev, tuning, steps, warmup, label):
                 rans_decoded=sum(v["rans_raw"] for v in st.values()), out=out, ws=ws)
 
 
+def gather_calibration(dev) -> dict:
+    """The rate HBM serves scattered whole 128-byte lines, the access pattern
+    of match sources in earlier blocks: 8 Mi rows at uniform random indices
+    of a 4 GiB buffer, read only (folded per thread) and copied out
+    contiguously, by the calibration library's gather kernel; the best grid
+    of a small sweep, each timed over 5 launches with events on the stream
+    the launches run on."""
+    import ctypes
+    import torch
+    path = os.path.join(ROOT, "paper_2606_24531_amd", "libacecalib.so")
+    if not os.path.exists(path):
+        raise RuntimeError("%s is not built (run __graft_entry__.build())" % path)
+    cl = ctypes.CDLL(path)
+    cl.acecalib_gather_lines.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p]
+    cl.acecalib_gather_lines.restype = ctypes.c_int
+    cl.acecalib_threads.argtypes = [ctypes.c_uint32]
+    cl.acecalib_threads.restype = ctypes.c_uint64
+    src_rows, n = 32 << 20, 8 << 20
+    src = torch.empty(src_rows * 128, dtype=torch.uint8, device=dev)
+    src.fill_(5)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    idx = torch.randint(0, src_rows, (n,), generator=g, dtype=torch.int64).to(torch.int32).to(dev)
+    grids = (1024, 2048, 4096, 8192)
+    dst = torch.empty(max(n * 128, int(cl.acecalib_threads(max(grids))) * 16), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {"rows": n, "row_bytes": 128, "buffer_bytes": src_rows * 128}
+    for read_only, key in ((1, "read_only_GBs"), (0, "copy_GBs")):
+        best = 0.0
+        for grid in grids:
+            def launch():
+                rc = cl.acecalib_gather_lines(src.data_ptr(), src_rows, idx.data_ptr(), n, dst.data_ptr(),
+                                              read_only, grid, stream.cuda_stream)
+                if rc:
+                    raise RuntimeError("gather calibration launch failed: HIP error %d" % rc)
+            launch()
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for _ in range(5):
+                launch()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            sec = ev[0].elapsed_time(ev[1]) * 1e-3 / 5
+            moved = n * 128 * (1 if read_only else 2)
+            best = max(best, moved / sec / 1e9)
+        out[key] = round(best, 1)
+    del src, idx, dst
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,8 +248,9 @@ def main():
                     help="keep the generated input and the encoded archives in this folder and "
                          "reuse them when the same workload is asked for again (profiling runs)")
     ap.add_argument("--calib", action="store_true",
-                    help="also run the byte-counter calibration kernels (a 256 MiB fill: known "
-                         "bytes written; a 256 MiB sum: known bytes read) after the decode")
+                    help="also run the calibration kernels after the decode: for the byte counters a "
+                         "256 MiB fill, 64-bit sum and copy; for the scattered-line rate a gather of "
+                         "8 Mi random 128-byte rows (reported under 'calibration')")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -300,6 +352,7 @@ def main():
     dom = max(phase, key=lambda k: phase[k]["ms"])
     _log("phases: entropy %.3f ms, match %.3f ms (dominant: %s)" % (ms_ent, ms_mat, dom))
 
+    result_calib = None
     if args.calib:
         # counter calibration, each a kernel of its own with known bytes:
         # a fill (256 MiB written with 16-byte stores), a sum over 64-bit
@@ -313,10 +366,14 @@ def main():
         torch.cuda.synchronize()
         del dst
         _log("calibration fill, sum and copy of 256 MiB done")
+        result_calib = gather_calibration(dev)
+        _log("calibration gather of random 128-byte rows: read only %.0f GB/s, "
+             "copy %.0f GB/s (reads + writes)" % (result_calib["read_only_GBs"], result_calib["copy_GBs"]))
 
     workload = "%s %d MiB, %d KiB blocks, %d-way rANS, level cap %d" % (
         args.profile, args.size >> 20, args.block >> 10, args.interleave, args.max_level)
     dk = phase[dom]
+    traffic = measured_traffic(dk["kernel"], workload)
     result = {
         "metric": "2-layer decode GB/s (full archive)",
         "value": round(gbs, 2),
@@ -354,8 +411,10 @@ def main():
             "bound": "hbm", "kernel": dk["kernel"],
             "achieved": dk["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dk["kernel"], workload),
+            "traffic": traffic,
             "traffic_unit": "HBM bytes per step (all launches of the kernel)",
+            "traffic_GBs": None if traffic is None else round(traffic / (dk["ms"] * 1e-3) / 1e9, 1),
+            "traffic_frac": None if traffic is None else round(traffic / (dk["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "alg_bytes_per_step": dk["alg_bytes"],
             "phases": phase,
             "path": {"alg_bytes_per_step": alg_bytes, "achieved": round(achieved, 2),
@@ -365,6 +424,8 @@ def main():
         },
     }
 
+    if result_calib is not None:
+        result["calibration"] = result_calib
     return finish(args, result, x, x_dev, a, arc, tuning, enc, d)
 
 
