@@ -258,8 +258,29 @@ def mixed(n: int, seed: int) -> bytes:
     return b"".join(out)[:n]
 
 
+def tandem(n: int, seed: int) -> bytes:
+    """Tandem repeats: a copy of an earlier chunk (20..47 bytes) followed at
+    once by its last d bytes (1 <= d <= 15) repeated for 40..899 bytes, with
+    short random runs in between.  The second copy's period lies in the
+    bytes of the first, so in-block chains of short-period matches are
+    common (an edge case of the expansion, not a corpus of the paper)."""
+    rng = _rng(np.random.SeedSequence([seed, 5]))
+    out = bytearray(rng.integers(0, 256, 4096, dtype=np.uint8).tobytes())
+    while len(out) < n:
+        if rng.random() < 0.3:
+            out += rng.integers(0, 256, int(rng.integers(8, 64)), dtype=np.uint8).tobytes()
+        m = int(rng.integers(20, 48))
+        o = int(rng.integers(0, len(out) - m))
+        chunk = bytes(out[o:o + m])
+        d = int(rng.integers(1, 16))
+        rep = int(rng.integers(40, 900))
+        out += chunk + (chunk[-d:] * (rep // d + 1))[:rep]
+    return bytes(out[:n])
+
+
 PROFILES = {
     "genome": genome,
+    "tandem": tandem,
     "fastq": fastq,
     "text": text,
     "random": random_bytes,

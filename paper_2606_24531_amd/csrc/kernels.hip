@@ -128,7 +128,7 @@ struct RansGroup {
     u32x2 ring[2 * G];  // 2 chunks x G lanes x 8 B
     struct {
       unsigned long long starts[64];  // bit t set: a symbol's interval starts at slot t
-      uint8_t by_rank[256];           // k-th present symbol
+      uint8_t by_rank[4 + 256 + 8];   // k-th present symbol at byte k + 4 (read 8 bytes at a time)
     } b;
   } u;
 };
@@ -195,35 +195,41 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
       const uint32_t s = kSpl * g + j;
       sm.fc[s] = f[j] ? (f[j] << 16) | cum : 0u;
       if (f[j]) {
-        sm.u.b.by_rank[k++] = (uint8_t)s;
+        sm.u.b.by_rank[4 + k++] = (uint8_t)s;
         atomicOr(&sm.u.b.starts[cum >> 6], 1ull << (cum & 63));
       }
       cum += f[j];
     }
   }
   wave_sync();
-  // ---- slot -> symbol: lane g fills slots 4096/G * g onwards in order, the
-  // rank of the covering symbol advancing at every interval start
+  // ---- slot -> symbol: lane g fills slots 4096/G * g onwards, four slots
+  // (one word) at a time.  The symbol of slot t has rank (interval starts at
+  // or before t) - 1, so a word's four symbols have ranks prev + c_b, where
+  // prev is the rank just before the word and c_b counts the word's starts
+  // up to slot b (0..4).  The word is then one byte permute of the 8 rank
+  // bytes from prev on: c_b for all four b at once is the word's 4 start
+  // bits spread one per byte (a multiply) and prefix-summed across the bytes
+  // (a multiply by 0x01010101).  Ranks are stored 4 bytes in, so prev = -1
+  // (lane 0; slot 0 always starts an interval) stays in bounds.
   {
     constexpr uint32_t kWpl = 64 / G;  // 64-bit start words per lane
     uint32_t pc = 0;
 #pragma unroll
     for (uint32_t q = 0; q < kWpl; q++) pc += __popcll(sm.u.b.starts[kWpl * g + q]);
-    int rank = (int)(grp_incl_sum<G>(pc) - pc) - 1;
-    uint32_t cur = (on && rank >= 0) ? sm.u.b.by_rank[rank] : 0u;
+    uint32_t prev = grp_incl_sum<G>(pc) - pc + 3;  // rank before the lane's first slot, + 4
     uint32_t* out32 = reinterpret_cast<uint32_t*>(sm.sym) + 16 * kWpl * g;
+    const uint32_t* br32 = reinterpret_cast<const uint32_t*>(sm.u.b.by_rank);
     if (on) {
 #pragma unroll
       for (uint32_t q = 0; q < kWpl; q++) {
         const unsigned long long w = sm.u.b.starts[kWpl * g + q];
-        for (uint32_t r = 0; r < 16; r++) {
-          uint32_t word = 0;
 #pragma unroll
-          for (uint32_t b = 0; b < 4; b++) {
-            if ((w >> (4 * r + b)) & 1) cur = sm.u.b.by_rank[++rank];
-            word |= cur << (8 * b);
-          }
-          out32[16 * q + r] = word;
+        for (uint32_t r = 0; r < 16; r++) {
+          const uint32_t nib = (uint32_t)(w >> (4 * r)) & 0xFu;
+          const uint32_t c = ((nib * 0x00204081u) & 0x01010101u) * 0x01010101u;
+          const uint32_t lo = br32[prev >> 2], hi = br32[(prev >> 2) + 1];
+          out32[16 * q + r] = __builtin_amdgcn_perm(hi, lo, c + (prev & 3u) * 0x01010101u);
+          prev += __popc(nib);
         }
       }
     }

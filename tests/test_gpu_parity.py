@@ -51,6 +51,7 @@ CASES = [
     ("fastq", 600_000, 16384, 1, 4, 1, 20),           # one lane per stream
     ("genome", 500_000, 1000, 7, 0, 2, 20),           # non-power-of-two blocks, raw
     ("text", 100_000, 37, 3, 0, 0, 4),                # tiny blocks, thousands of them
+    ("tandem", 2_000_000, 16384, 32, 8, 0, 16),       # chains of short-period matches
     ("mixed", 1_500_007, 16384, 32, 8, 4, 16),        # 8-byte offsets (the >4 GiB width)
     ("genome", 700_003, 4096, 64, 0, 6, 20),          # 8-byte offsets, raw streams, uncapped
 ]

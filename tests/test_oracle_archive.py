@@ -8,7 +8,7 @@ import pytest
 import gen
 from harness import block_entry, header, stream_desc, three_phase
 
-PROFILES = [("genome", 20), ("fastq", 20), ("text", 16), ("random", 16), ("mixed", 16)]
+PROFILES = [("genome", 20), ("fastq", 20), ("text", 16), ("random", 16), ("mixed", 16), ("tandem", 16)]
 
 
 def test_fnv1a64_published_vectors(orc):

@@ -142,3 +142,49 @@ print("EXT", ext)
     info = orc.info(a)
     assert max(orc.block_facts(a)[1]) <= 1024  # one tile per block
     assert ext == _ext_bytes_reference(orc, a)
+
+
+def test_short_period_slow_matches(orc):
+    """Short-period matches whose span lies in the previous match (their
+    bytes resolved in the slow pass, period wrap by period wrap) decode to
+    the original bytes, and the earlier-block byte counter still equals the
+    origin count."""
+    import numpy as np
+    import gen
+    x = gen.by_name("tandem", 3_000_000, 5)
+    code = r"""
+import sys
+sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
+import simt_lib
+x = open(%(xpath)r, "rb").read()
+from paper_2606_24531_amd import encode
+a = encode(x, block_size=16384, interleave=32, min_match=16, hash_len=16, max_level=8)
+open(%(path)r, "wb").write(a)
+arc = simt_lib.Archive(a)
+y, ext = simt_lib.decode_all_ext(arc, dict(mode=1, waves_per_block=8))
+assert y == x
+assert arc.decode_all(dict(mode=1, waves_per_block=2)) == x
+print("EXT", ext)
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        path, xpath = os.path.join(td, "a.bin"), os.path.join(td, "x.bin")
+        open(xpath, "wb").write(x)
+        r = subprocess.run([sys.executable, "-c", code % dict(root=ROOT, tests=HERE, path=path, xpath=xpath)],
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-2000:]
+        ext = int(r.stdout.split("EXT")[1].split()[0])
+        a = open(path, "rb").read()
+    # the premise: many matches with a period under 16 whose span reaches
+    # back past their own literals into the sequence before
+    info = orc.info(a)
+    n_short = 0
+    for b in range(info["n_blocks"]):
+        lit, L, M, O = orc.block_tokens(a, b)
+        L, M, O = L.astype(np.int64), M.astype(np.int64), O.astype(np.int64)
+        mstart = b * info["block_size"] + np.concatenate([[0], np.cumsum(L + M)[:-1]]) + L
+        d = mstart - O
+        n_short += int(((M > d) & (d < 16) & (L < d)).sum())
+    assert n_short > 1000
+    assert max(orc.block_facts(a)[1]) <= 1024  # one tile per block at 512 threads
+    assert ext == _ext_bytes_reference(orc, a)
