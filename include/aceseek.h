@@ -130,6 +130,31 @@ void ace_archive_close(ace_archive* a);
 int ace_archive_info(const ace_archive* a, uint64_t* n_total, uint32_t* block_size,
                      uint32_t* n_blocks, uint32_t* depth);
 
+/* ---- out-of-core range decode (Section 7: when the archive is larger than
+ * device memory, ranges are decoded with only the blocks they need on the
+ * device) ----
+ * ace_archive_open_ooc: validates the archive in host memory as
+ * ace_archive_open does and keeps h_arch (caller-owned, unchanged and alive
+ * while the handle is used); nothing is uploaded.  Such a handle is taken by
+ * ace_seek_ooc, ace_seek_ooc_bytes, ace_archive_info and ace_archive_close;
+ * the calls that read a resident archive return ACE_E_ARG for it.
+ * ace_seek_ooc_bytes: the workspace ace_seek_ooc needs for [lo, hi) (0 for
+ * an empty range): the host-planned seek's, plus the staged dependency lists
+ * and payloads of the range's dependency closure, plus ACE_ARCH_PAD.
+ * ace_seek_ooc: writes exactly hi - lo bytes at d_out (device).  The host
+ * plans the closure, copies the planned blocks' dependency lists and
+ * payloads from h_arch into d_ws (device, ws_cap bytes) through a pinned
+ * staging buffer held by the handle, and the same kernels as ace_seek decode
+ * them there.  Returns once the work has finished on `stream` (calls on one
+ * handle take turns on its staging buffer).  Errors: ACE_E_ARG (a handle
+ * not opened out of core, null pointers), ACE_E_RANGE, ACE_E_NOSPACE (the
+ * needed size is in the message); the device's error word is read with
+ * ace_check(d_ws, stream) as after ace_seek. */
+int ace_archive_open_ooc(const uint8_t* h_arch, uint64_t len, ace_archive** out);
+int ace_seek_ooc_bytes(const ace_archive* a, uint64_t lo, uint64_t hi, uint64_t* bytes);
+int ace_seek_ooc(const ace_archive* a, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+                 uint64_t ws_cap, const ace_tuning* t, void* stream);
+
 /* Optional: the whole-archive decode plan (the blocks in dependency-level
  * order with the index fields the kernels need, 64 bytes per block, then the
  * block ids in that order and the level boundaries) kept resident on the

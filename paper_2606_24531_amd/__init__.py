@@ -6,8 +6,8 @@ The compute path is the C-ABI library libaceseek.so (HIP kernels); this
 package only marshals arguments.  Import fails loudly if the library has not
 been built.
 """
-from .aceseek import (Archive, AceError, EncodeParams, Tuning, encode, encode_bound,
-                      library_path)
+from .aceseek import (Archive, AceError, EncodeParams, OutOfCoreArchive, Tuning, encode,
+                      encode_bound, library_path)
 
-__all__ = ["Archive", "AceError", "EncodeParams", "Tuning", "encode", "encode_bound",
-           "library_path"]
+__all__ = ["Archive", "AceError", "EncodeParams", "OutOfCoreArchive", "Tuning", "encode",
+           "encode_bound", "library_path"]

@@ -23,7 +23,7 @@ EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_arch
            "ace_batch_pin",
            "ace_set_timing", "ace_last_timings", "ace_plan_bytes", "ace_archive_attach_plan",
            "ace_set_block_trace", "ace_seek_static", "ace_last_host_times",
-           "ace_workspace_bound"]
+           "ace_workspace_bound", "ace_archive_open_ooc", "ace_seek_ooc_bytes", "ace_seek_ooc"]
 
 
 class AceError(RuntimeError):
@@ -90,6 +90,9 @@ def lib():
         L.ace_last_host_times.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ace_plan_bytes.argtypes = [vp, u64p]
         L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
+        L.ace_archive_open_ooc.argtypes = [vp, u64, C.POINTER(vp)]
+        L.ace_seek_ooc_bytes.argtypes = [vp, u64, u64, u64p]
+        L.ace_seek_ooc.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
         _lib = L
     return _lib
 
@@ -391,6 +394,65 @@ class Archive:
     def check(self, ws=None, stream=None):
         """Synchronises and raises if the device flagged a corrupt stream."""
         ws = self._ws if ws is None else ws
+        if ws is None:
+            return
+        _check(lib().ace_check(C.c_void_p(ws.data_ptr()), _stream_ptr(stream)))
+
+
+class OutOfCoreArchive:
+    """An archive kept in host memory (ace_archive_open_ooc): each seek
+    copies only its dependency closure's payloads to the device."""
+
+    def __init__(self, data, device="cuda"):
+        import torch
+        self._torch = torch
+        host = np.frombuffer(data, dtype=np.uint8) if not isinstance(data, np.ndarray) else data
+        self._host = np.ascontiguousarray(host)  # the library reads it on every seek
+        self.nbytes = int(self._host.size)
+        self.device = torch.device(device)
+        h = C.c_void_p()
+        _check(lib().ace_archive_open_ooc(self._host.ctypes.data_as(C.c_void_p), self.nbytes, C.byref(h)))
+        self._h = h
+        n, B, nb, depth = C.c_uint64(0), C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
+        _check(lib().ace_archive_info(h, C.byref(n), C.byref(B), C.byref(nb), C.byref(depth)))
+        self.n_total, self.block_size, self.n_blocks, self.depth = n.value, B.value, nb.value, depth.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_archive_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, lo: int, hi: int) -> int:
+        b = C.c_uint64(0)
+        _check(lib().ace_seek_ooc_bytes(self._h, int(lo), int(hi), C.byref(b)))
+        return b.value
+
+    def seek(self, lo: int, hi: int, out=None, ws=None, tuning=None, stream=None):
+        """[lo, hi) as a device tensor; returns when the seek has finished."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty(max(hi - lo, 0), dtype=torch.uint8, device=self.device)
+        if ws is None:
+            need = self.workspace_bytes(lo, hi)
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.zeros(max(need, 256), dtype=torch.uint8, device=self.device)
+            ws = self._ws
+        _check(lib().ace_seek_ooc(self._h, int(lo), int(hi), C.c_void_p(out.data_ptr()),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), Archive._tuning(tuning),
+                                  _stream_ptr(stream)))
+        self._last_ws = ws
+        return out
+
+    def check(self, ws=None, stream=None):
+        """Raises if the device flagged a corrupt stream in the last seek."""
+        ws = getattr(self, "_last_ws", None) if ws is None else ws
         if ws is None:
             return
         _check(lib().ace_check(C.c_void_p(ws.data_ptr()), _stream_ptr(stream)))

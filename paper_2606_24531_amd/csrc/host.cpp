@@ -56,7 +56,7 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
 struct BlockInfo {
-  uint32_t n_seq, level, dep_off, dep_cnt, n_lit;
+  uint32_t n_seq, level, dep_off, dep_cnt, n_lit, plen;
   uint64_t pay;
   uint64_t raw[3];  // archive offset of each stream's data when stored raw, else kCoded
 };
@@ -76,10 +76,24 @@ struct ace_archive {
   const uint32_t* d_order = nullptr;  // with it: all blocks by level, then the level boundaries
   const uint32_t* d_lstart = nullptr;
   std::mutex pin_mu;
+  // out of core: the archive stays in host memory (h_arch, the caller's);
+  // each seek stages what it needs through a pinned buffer
+  const uint8_t* h_arch = nullptr;
+  std::mutex ooc_mu;
+  uint8_t* ooc_pinned = nullptr;
+  uint64_t ooc_pinned_cap = 0;
   ~ace_archive() {
     if (all_plan_pinned) (void)hipHostFree(all_plan_pinned);
+    if (ooc_pinned) (void)hipHostFree(ooc_pinned);
   }
 };
+
+// The entry points that read the archive on the device need it resident.
+static int need_resident(const ace_archive* A) {
+  if (A && !A->d_arch && A->h_arch)
+    return fail(ACE_E_ARG, "the archive was opened out of core: its ranges decode with ace_seek_ooc");
+  return ACE_OK;
+}
 
 static PlanEntry make_entry(const ace_archive* A, uint32_t b, uint64_t seq_base, uint64_t dst) {
   const BlockInfo& bi = A->blk[b];
@@ -139,6 +153,7 @@ static int validate(const uint8_t* a, uint64_t len, ace_archive* A) {
     bi.dep_off = h32(e + 20);
     bi.dep_cnt = h32(e + 24);
     bi.pay = pay;
+    bi.plen = plen;
     if (h32(e + 28) != 0) return fail(ACE_E_CORRUPT, "block %u: reserved field is not zero", b);
     if (pay % 16 || pay < pay_at || pay + plen > len || plen < 3 * kSDesc)
       return fail(ACE_E_CORRUPT, "block %u: payload outside the archive", b);
@@ -233,6 +248,16 @@ extern "C" int ace_archive_open(const uint8_t* h_arch, uint64_t len, const void*
     return fail(ACE_E_CORRUPT, "more than 2^32 sequences");
   }
   A->all_seq = seq;
+  *out = A;
+  return ACE_OK;
+}
+
+extern "C" int ace_archive_open_ooc(const uint8_t* h_arch, uint64_t len, ace_archive** out) {
+  if (!h_arch || !out) return fail(ACE_E_ARG, "null argument");
+  ace_archive* A = nullptr;
+  int rc = ace_archive_open(h_arch, len, nullptr, &A);
+  if (rc) return rc;
+  A->h_arch = h_arch;
   *out = A;
   return ACE_OK;
 }
@@ -432,7 +457,7 @@ static int run_launches(const ace_archive* A, const PlanEntry* entries, uint64_t
                         const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                         const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
                         hipStream_t s, bool entries_pinned, bool loc_linear,
-                        const PlanEntry* resident);
+                        const PlanEntry* resident, const uint8_t* arch);
 
 // Runs a host-built plan; with phase timing on, also records the host time
 // spent planning (since the call's entry) and enqueueing.
@@ -440,14 +465,14 @@ static int run(const ace_archive* A, const PlanEntry* entries, uint64_t n_plan,
                const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
                hipStream_t s, bool entries_pinned, bool loc_linear = false,
-               const PlanEntry* resident = nullptr) {
+               const PlanEntry* resident = nullptr, const uint8_t* arch = nullptr) {
   if (!g_timer.on)
     return run_launches(A, entries, n_plan, lstart, items, n_items, L, ws, dst_base, t, s, entries_pinned,
-                        loc_linear, resident);
+                        loc_linear, resident, arch);
   const auto t_run = std::chrono::steady_clock::now();
   g_timer.us_plan = std::chrono::duration<double, std::micro>(t_run - g_timer.t_enter).count();
   const int rc = run_launches(A, entries, n_plan, lstart, items, n_items, L, ws, dst_base, t, s,
-                              entries_pinned, loc_linear, resident);
+                              entries_pinned, loc_linear, resident, arch);
   g_timer.us_enqueue = us_since(t_run);
   return rc;
 }
@@ -456,15 +481,16 @@ static int run_launches(const ace_archive* A, const PlanEntry* entries, uint64_t
                         const std::vector<uint32_t>& lstart, const CopyItem* items, uint64_t n_items,
                         const Layout& L, uint8_t* ws, uint64_t dst_base, const ace_tuning* t,
                         hipStream_t s, bool entries_pinned, bool loc_linear,
-                        const PlanEntry* resident) {
+                        const PlanEntry* resident, const uint8_t* arch) {
   (void)entries_pinned;
+  if (!arch) arch = A->d_arch;  // an out-of-core seek passes its staged copy
   const uint32_t mode = t ? t->mode : 0;
   if (mode > 1 && mode != kModeOverlap && mode != kModePersistent) return fail(ACE_E_ARG, "unknown mode %u", mode);
   int rc = check_tuning(A, t);
   if (rc) return rc;
   const uint32_t waves = t ? t->waves_per_block : 0, per_wave = t ? t->blocks_per_wg : 0;
   DecodeArgs a{};
-  a.arch = A->d_arch;
+  a.arch = arch;
   a.plan = resident ? resident : reinterpret_cast<const PlanEntry*>(ws + L.plan);
   a.n_plan = (uint32_t)n_plan;
   a.B = A->B;
@@ -594,6 +620,7 @@ extern "C" int ace_decode_all(const ace_archive* A, uint8_t* d_out, uint64_t out
                               uint64_t ws_cap, const ace_tuning* t, void* stream) {
   timer_enter();
   if (!A || (!d_out && A->n) || !d_ws) return fail(ACE_E_ARG, "null argument");
+  if (int rc = need_resident(A)) return rc;
   if (out_cap < A->n) return fail(ACE_E_NOSPACE, "output needs %llu bytes", (unsigned long long)A->n);
   Layout L = layout(A, A->nb, A->all_seq, 0, 0);
   if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);
@@ -634,6 +661,7 @@ extern "C" int ace_plan_bytes(const ace_archive* A, uint64_t* bytes) {
 
 extern "C" int ace_archive_attach_plan(ace_archive* A, void* d_plan, uint64_t bytes, void* stream) {
   if (!A || (!d_plan && A->nb)) return fail(ACE_E_ARG, "null argument");
+  if (int rc = need_resident(A)) return rc;
   const uint64_t need = plan_bytes(A);
   if (bytes < need) return fail(ACE_E_NOSPACE, "the plan needs %llu bytes", (unsigned long long)need);
   if (A->nb == 0) return ACE_OK;
@@ -666,6 +694,7 @@ static int seek_impl(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_
                      bool allow_device = true) {
   timer_enter();
   if (!A) return fail(ACE_E_ARG, "null archive");
+  if (int rc = need_resident(A)) return rc;
   if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
                            (unsigned long long)hi);
   if (hi > A->n) return fail(ACE_E_RANGE, "range end %llu beyond %llu", (unsigned long long)hi,
@@ -719,6 +748,133 @@ extern "C" int ace_seek(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t*
   return seek_impl(A, lo, hi, d_out, d_ws, ws_cap, t, stream, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// out-of-core range decode
+// ---------------------------------------------------------------------------
+// An out-of-core seek is the host-planned seek with the archive bytes it
+// reads staged into its workspace: the dependency lists of the planned
+// blocks, then their payloads (each 16-aligned, ACE_ARCH_PAD readable bytes
+// after the last).  The kernels address the archive as base + offset (the
+// dependency array at the index's place, kHdr + 32 * n_blocks, payloads at
+// their offsets), so the plan entries get offsets into the staged copy and
+// the base is placed kHdr + 32 * n_blocks before it; the staged copy starts
+// at least that far into the workspace, so the base stays inside it.
+namespace {
+struct OocSeek {
+  std::vector<uint32_t> order, lstart;
+  std::vector<PlanEntry> entries;
+  std::vector<CopyItem> items;
+  std::vector<uint8_t> direct;
+  uint64_t seq = 0, n_slots = 0, deps_bytes = 0, pay_bytes = 0;
+  Layout L{};
+  uint64_t gap = 0, stage = 0, total = 0;
+};
+
+void ooc_plan(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, OocSeek& P) {
+  const uint32_t t0 = (uint32_t)(lo / A->B), t1 = (uint32_t)((hi - 1) / A->B);
+  std::vector<uint32_t> blocks;
+  close_range(A, t0, t1, blocks);
+  level_order(A, blocks, P.order, P.lstart);
+  P.entries.resize(P.order.size());
+  P.direct.assign(P.order.size(), 0);
+  for (size_t i = 0; i < P.order.size(); i++) {
+    const uint32_t b = P.order[i];
+    const uint64_t bs = (uint64_t)b * A->B, be = std::min<uint64_t>(bs + A->B, A->n);
+    P.direct[i] = b >= t0 && b <= t1 && bs >= lo && be <= hi;
+    if (!P.direct[i]) P.n_slots++;
+    P.entries[i] = make_entry(A, b, P.seq, 0);
+    P.seq += A->blk[b].n_seq;
+    P.deps_bytes += 4ull * A->blk[b].dep_cnt;
+    P.pay_bytes += align_up(A->blk[b].plen, 16);
+  }
+  for (uint32_t b : {t0, t1}) {
+    const uint64_t bs = (uint64_t)b * A->B, be = std::min<uint64_t>(bs + A->B, A->n);
+    if (bs >= lo && be <= hi) continue;
+    if (b == t1 && t1 == t0 && !P.items.empty()) continue;
+    const uint64_t s0 = std::max(lo, bs), s1 = std::min(hi, be);
+    P.items.push_back(CopyItem{s0, (uint64_t)(uintptr_t)d_out + (s0 - lo), (uint32_t)(s1 - s0), 0});
+  }
+  P.L = layout(A, P.order.size(), P.seq, P.n_slots, P.items.size());
+  P.gap = kHdr + (uint64_t)kBlk * A->nb;
+  P.stage = align_up(std::max(P.L.total, P.gap), 256);
+  P.total = P.stage + align_up(P.deps_bytes, 16) + P.pay_bytes + ACE_ARCH_PAD;
+}
+}  // namespace
+
+extern "C" int ace_seek_ooc_bytes(const ace_archive* A, uint64_t lo, uint64_t hi, uint64_t* bytes) {
+  if (!A || !bytes) return fail(ACE_E_ARG, "null argument");
+  if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
+                           (unsigned long long)hi);
+  if (hi > A->n) return fail(ACE_E_RANGE, "range end %llu beyond %llu", (unsigned long long)hi,
+                             (unsigned long long)A->n);
+  if (lo == hi) {
+    *bytes = 0;
+    return ACE_OK;
+  }
+  OocSeek P;
+  ooc_plan(A, lo, hi, nullptr, P);
+  *bytes = P.total;
+  return ACE_OK;
+}
+
+extern "C" int ace_seek_ooc(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out, void* d_ws,
+                            uint64_t ws_cap, const ace_tuning* t, void* stream) {
+  timer_enter();
+  if (!A) return fail(ACE_E_ARG, "null archive");
+  if (!A->h_arch) return fail(ACE_E_ARG, "the archive was not opened out of core (ace_archive_open_ooc)");
+  if (lo > hi) return fail(ACE_E_ARG, "inverted range [%llu, %llu)", (unsigned long long)lo,
+                           (unsigned long long)hi);
+  if (hi > A->n) return fail(ACE_E_RANGE, "range end %llu beyond %llu", (unsigned long long)hi,
+                             (unsigned long long)A->n);
+  if (lo == hi) return ACE_OK;
+  if (!d_out || !d_ws) return fail(ACE_E_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  OocSeek P;
+  ooc_plan(A, lo, hi, d_out, P);
+  if (ws_cap < P.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)P.total);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  uint64_t slot = 0;
+  for (size_t i = 0; i < P.order.size(); i++) {
+    const uint64_t bs = (uint64_t)P.order[i] * A->B;
+    P.entries[i].dst = P.direct[i] ? (uint64_t)(uintptr_t)d_out + (bs - lo)
+                                   : (uint64_t)(uintptr_t)(ws + P.L.slots) + (slot++) * A->B;
+  }
+  // one staging buffer per archive: calls on it take turns, each finished
+  // on its stream before the next one refills the buffer
+  ace_archive* M = const_cast<ace_archive*>(A);
+  std::lock_guard<std::mutex> g(M->ooc_mu);
+  const uint64_t staged = align_up(P.deps_bytes, 16) + P.pay_bytes;
+  if (M->ooc_pinned_cap < staged) {
+    if (M->ooc_pinned) (void)hipHostFree(M->ooc_pinned);
+    M->ooc_pinned = nullptr;
+    M->ooc_pinned_cap = 0;
+    void* p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, staged, hipHostMallocDefault));
+    M->ooc_pinned = static_cast<uint8_t*>(p);
+    M->ooc_pinned_cap = staged;
+  }
+  uint8_t* h = M->ooc_pinned;
+  uint64_t dpos = 0, ppos = align_up(P.deps_bytes, 16);
+  for (PlanEntry& e : P.entries) {
+    const BlockInfo& bi = A->blk[e.block];
+    memcpy(h + dpos, A->deps.data() + bi.dep_off, 4ull * bi.dep_cnt);
+    e.dep_off = (uint32_t)(dpos / 4);
+    dpos += 4ull * bi.dep_cnt;
+    memcpy(h + ppos, A->h_arch + bi.pay, bi.plen);
+    const uint64_t pay = P.gap + ppos;  // offset from the kernels' archive base
+    for (int k = 0; k < 3; k++)
+      if (e.raw[k] != kCoded) e.raw[k] = e.raw[k] - bi.pay + pay;
+    e.pay = pay;
+    ppos += align_up(bi.plen, 16);
+  }
+  HIP_TRY(hipMemcpyAsync(ws + P.stage, h, staged, hipMemcpyHostToDevice, s));
+  const int rc = run(A, P.entries.data(), P.entries.size(), P.lstart, P.items.data(), P.items.size(), P.L, ws, 0,
+                     t, s, false, false, nullptr, ws + P.stage - P.gap);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return ACE_OK;
+}
+
 static_assert(kStaticScratchBytes == ACE_STATIC_SCRATCH_BYTES, "the fixed scratch size the header states");
 
 extern "C" int ace_seek_static(const ace_archive* A, uint64_t lo, uint64_t hi, uint8_t* d_out,
@@ -748,6 +904,7 @@ extern "C" int ace_seek_batch(const ace_archive* A, const ace_range* r, uint32_t
                               const ace_tuning* t, void* stream) {
   timer_enter();
   if (!A || (n && (!r || !out_off))) return fail(ACE_E_ARG, "null argument");
+  if (int rc = need_resident(A)) return rc;
   std::vector<uint8_t> need(A->nb, 0);
   uint32_t top = 0;
   bool any = false;
@@ -1014,6 +1171,7 @@ extern "C" void ace_batch_destroy(ace_batch* b) {
 extern "C" int ace_batch_create(const ace_archive* A, uint32_t cap, void* d_ws, uint64_t ws_cap,
                                 const ace_tuning* t, void* stream, ace_batch** out) {
   if (!A || !d_ws || !out || cap == 0) return fail(ACE_E_ARG, "null argument or zero capacity");
+  if (int rc = need_resident(A)) return rc;
   if (!stream) return fail(ACE_E_ARG, "a batch needs a stream of its own: the default stream cannot be captured");
   const BatchLayout L = batch_layout(A, cap);
   if (ws_cap < L.total) return fail(ACE_E_NOSPACE, "workspace needs %llu bytes", (unsigned long long)L.total);

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "simt"))
 
 ARCH_PAD = 4096
+ACE_E_ARG = -1
 _lib = None
 
 
@@ -47,6 +48,9 @@ def lib():
         L.ace_batch_destroy.restype = None
         L.ace_plan_bytes.argtypes = [vp, u64p]
         L.ace_archive_attach_plan.argtypes = [vp, vp, u64, vp]
+        L.ace_archive_open_ooc.argtypes = [vp, u64, C.POINTER(vp)]
+        L.ace_seek_ooc_bytes.argtypes = [vp, u64, u64, u64p]
+        L.ace_seek_ooc.argtypes = [vp, u64, u64, vp, vp, u64, C.POINTER(Tuning), vp]
         L.simt_stream_create.restype = vp
         _lib = L
     return _lib
@@ -132,6 +136,41 @@ class Archive:
         ws = self.workspace([lo, hi])
         t = C.byref(Tuning(**tuning)) if tuning else None
         _check(lib().ace_seek(self._h, lo, hi, _p(out), _p(ws), ws.size, t, None))
+        _check(lib().ace_check(_p(ws), None))
+        return out[:hi - lo].tobytes()
+
+
+class OocArchive:
+    """An archive opened out of core by the CPU build: only what each seek
+    needs is staged into its workspace."""
+
+    def __init__(self, data: bytes):
+        self.host = np.frombuffer(data, dtype=np.uint8).copy()
+        h = C.c_void_p()
+        _check(lib().ace_archive_open_ooc(_p(self.host), len(data), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().ace_archive_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, lo, hi):
+        b = C.c_uint64(0)
+        _check(lib().ace_seek_ooc_bytes(self._h, lo, hi, C.byref(b)))
+        return b.value
+
+    def seek(self, lo, hi, tuning=None):
+        out = np.zeros(max(hi - lo, 1), dtype=np.uint8)
+        ws = np.zeros(max(self.workspace_bytes(lo, hi), 256), dtype=np.uint8)
+        t = C.byref(Tuning(**tuning)) if tuning else None
+        _check(lib().ace_seek_ooc(self._h, lo, hi, _p(out), _p(ws), ws.size, t, None))
         _check(lib().ace_check(_p(ws), None))
         return out[:hi - lo].tobytes()
 

@@ -188,3 +188,43 @@ print("EXT", ext)
     assert n_short > 1000
     assert max(orc.block_facts(a)[1]) <= 1024  # one tile per block at 512 threads
     assert ext == _ext_bytes_reference(orc, a)
+
+
+@pytest.mark.parametrize("case", [("genome", 1 << 20, 16384, 32, 0, 0, 20), ("mixed", 700_001, 16384, 64, 0, 4, 16),
+                                  ("genome", 200_003, 1000, 7, 0, 2, 20), ("text", 40_000, 37, 3, 0, 0, 4),
+                                  ("tandem", 500_000, 4096, 32, 8, 0, 16)],
+                         ids=lambda c: "%s-n%d-B%d-W%d-f%d" % (c[0], c[1], c[2], c[3], c[5]))
+def test_out_of_core_seeks(case):
+    """Seeks on an archive opened out of core (only each range's dependency
+    closure staged into the workspace) equal the original bytes, for every
+    mode; the calls that need a resident archive refuse such a handle."""
+    name, n, B, W, cap, flags, mm = case
+    code = r"""
+import sys
+sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
+import numpy as np, gen, simt_lib
+from paper_2606_24531_amd import encode
+name, n, B, W, cap, flags, mm = %(case)r
+x = gen.by_name(name, n, 23)
+a = encode(x, block_size=B, interleave=W, min_match=mm, hash_len=min(mm, 16), max_level=cap, flags=flags)
+arc = simt_lib.OocArchive(a)
+rng = np.random.default_rng(3)
+ranges = [(0, n), (n - 1, n), (B - 1, B + 1), (0, 1)]
+for _ in range(6):
+    lo = int(rng.integers(0, n))
+    ranges.append((lo, min(n, lo + int(rng.integers(1, 3 * B)))))
+for i, (lo, hi) in enumerate(ranges):
+    mode = (1, 2, 3)[i %% 3]
+    assert arc.seek(lo, hi, dict(mode=mode)) == x[lo:hi], (lo, hi, mode)
+assert arc.workspace_bytes(5, 5) == 0
+L = simt_lib.lib()
+out = np.zeros(n, dtype=np.uint8); ws = np.zeros(1 << 20, dtype=np.uint8)
+rc = L.ace_decode_all(arc._h, simt_lib._p(out), n, simt_lib._p(ws), ws.size, None, None)
+assert rc == simt_lib.ACE_E_ARG and b"out of core" in L.ace_last_error(), rc
+rc = L.ace_seek(arc._h, 0, 1, simt_lib._p(out), simt_lib._p(ws), ws.size, None, None)
+assert rc == simt_lib.ACE_E_ARG, rc
+print("OK")
+"""
+    r = subprocess.run([sys.executable, "-c", code % {"root": ROOT, "tests": HERE, "case": case}],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
