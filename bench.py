@@ -12,8 +12,9 @@ Also reported on the same line: the decode's bytes against the MI355X HBM
 roofline (algorithmic bytes = archive + output + match bytes read from
 earlier blocks), per kernel and for the whole path; the same corpus at 64 KiB
 blocks and uncapped; 100,000 seeks (length log-uniform 1 B..4 MiB) decoded as
-one replayed batch graph against one seek call per request; and the CPU
-oracle's decode rate on this host's cores.
+one replayed batch graph against one seek call per request; a range decode of
+blocks 0..1000 from the resident archive and out of core (archive in host
+memory); and the CPU oracle's decode rate on this host's cores.
 """
 import argparse
 import json
@@ -429,6 +430,66 @@ def main():
     return finish(args, result, x, x_dev, a, arc, tuning, enc, d)
 
 
+def range_decode_leg(a, arc, x_dev, tuning) -> dict:
+    """Range decode of blocks 0..1000 (the paper's at-scale range), from the
+    resident archive and out of core (the archive in host memory, the
+    range's closure staged per call), and single-block out-of-core seeks;
+    every output compared with the original.  Wall clock around calls that
+    are waited on, median of 5 (single blocks: 200 uniform blocks, seed 6)."""
+    import numpy as np
+    import torch
+    from paper_2606_24531_amd import OutOfCoreArchive
+    B = arc.block_size
+    lo, hi = 0, min(arc.n_total, 1001 * B)
+    dev = x_dev.device
+    out = torch.empty(hi - lo, dtype=torch.uint8, device=dev)
+    ws = torch.zeros(max(arc.seek_device_bytes(), arc.workspace_bytes([lo, hi])), dtype=torch.uint8, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t))
+
+    res = {"range": [lo, hi], "blocks": (hi - lo + B - 1) // B}
+    t_res = timed(lambda: arc.seek(lo, hi, out=out, ws=ws, tuning=tuning, plan="host"))
+    arc.check(ws)
+    res["resident_ms"] = round(1e3 * t_res, 4)
+    res["resident_equal"] = bool(torch.equal(out, x_dev[lo:hi]))
+    ooc = OutOfCoreArchive(a, device=dev)
+    t_ooc = timed(lambda: ooc.seek(lo, hi, out=out, tuning=tuning))
+    ooc.check()
+    res["ooc_ms"] = round(1e3 * t_ooc, 4)
+    res["ooc_equal"] = bool(torch.equal(out, x_dev[lo:hi]))
+    res["ooc_workspace_bytes"] = ooc.workspace_bytes(lo, hi)
+    rng = np.random.default_rng(6)
+    lat, ok, staged = [], True, []
+    for b in rng.integers(0, arc.n_blocks, 200):
+        l0, h0 = int(b) * B, min(arc.n_total, (int(b) + 1) * B)
+        t0 = time.perf_counter()
+        r = ooc.seek(l0, h0, out=out[:h0 - l0], tuning=tuning)
+        lat.append(time.perf_counter() - t0)
+        ok = ok and bool(torch.equal(r, x_dev[l0:h0]))
+        staged.append(ooc.workspace_bytes(l0, h0))
+    ooc.check()
+    ooc.close()
+    res["ooc_single_block"] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 4),
+                               "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+                               "workspace_bytes_p50": int(np.median(staged)), "outputs_equal_original": ok}
+    _log("range decode of blocks 0..1000: resident %.3f ms, out of core %.3f ms (workspace %.1f MB, equal %s/%s); "
+         "out-of-core single blocks p50 %.3f ms p99 %.3f ms" % (
+             res["resident_ms"], res["ooc_ms"], res["ooc_workspace_bytes"] / 1e6, res["resident_equal"],
+             res["ooc_equal"], res["ooc_single_block"]["p50_ms"], res["ooc_single_block"]["p99_ms"]))
+    del out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
     """The rest of the default line: the same corpus at 64 KiB blocks and
     uncapped, the batched-vs-plain seeks, and the CPU oracle baseline."""
@@ -554,6 +615,7 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
                      r["device_decode_ms_p50"]))
         del out
         torch.cuda.empty_cache()
+        result["range_decode"] = range_decode_leg(a, arc, x_dev, tuning)
 
     if not args.no_cpu_baseline:
         import oracle
