@@ -430,6 +430,37 @@ def main():
     return finish(args, result, x, x_dev, a, arc, tuning, enc, d)
 
 
+def encode_leg(x, enc) -> dict:
+    """The encoder's entropy step on the host and on the device, on the first
+    64 MiB of the workload: encode wall time with every stream left raw (the
+    parse and layout alone), with the host's rANS step and with the device's
+    (ENC_DEVICE_ENTROPY), median of 3 each; the two coded archives must be
+    equal.  Entropy time = coded encode - raw encode."""
+    import numpy as np
+    from paper_2606_24531_amd import aceseek
+    sample = x[:64 << 20]
+    kw = dict(enc)
+    flags = kw.pop("flags", 0) & ~3
+
+    def t(f):
+        ts, out = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            out = aceseek.encode(sample, flags=f, **kw)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    t_raw, _ = t(flags | 2)
+    t_host, a_host = t(flags)
+    t_dev, a_dev = t(flags | aceseek.ENC_DEVICE_ENTROPY)
+    res = {"sample_bytes": len(sample), "raw_s": round(t_raw, 3), "host_entropy_s": round(t_host, 3),
+           "device_entropy_s": round(t_dev, 3), "entropy_host_s": round(t_host - t_raw, 3),
+           "entropy_device_s": round(t_dev - t_raw, 3), "archives_equal": a_host == a_dev}
+    _log("encode of 64 MiB: parse and layout %.2f s; rANS step on the host %.2f s, on the device %.2f s "
+         "(archives equal: %s)" % (t_raw, t_host - t_raw, t_dev - t_raw, res["archives_equal"]))
+    return res
+
+
 def range_decode_leg(a, arc, x_dev, tuning) -> dict:
     """Range decode of blocks 0..1000 (the paper's at-scale range), from the
     resident archive and out of core (the archive in host memory, the
@@ -616,6 +647,7 @@ def finish(args, result, x, x_dev, a, arc, tuning, enc, d):
         del out
         torch.cuda.empty_cache()
         result["range_decode"] = range_decode_leg(a, arc, x_dev, tuning)
+        result["encode"] = encode_leg(x, dict(enc, block_size=args.block, max_level=args.max_level))
 
     if not args.no_cpu_baseline:
         import oracle

@@ -58,10 +58,15 @@ extern "C" {
  *  flags       bits 0-1, stream-mode policy: 0 = rANS only where smaller,
  *              1 = always rANS, 2 = always raw; bit 2 (ACE_ENC_WIDE_OFFSETS):
  *              store absolute offsets in 8 bytes even when every position
- *              fits in 4 (the width archives above 4 GiB need); other bits
- *              are ACE_E_ARG
+ *              fits in 4 (the width archives above 4 GiB need); bit 3
+ *              (ACE_ENC_DEVICE_ENTROPY): the rANS step of every stream runs
+ *              on the current device (one wavefront per stream, the same
+ *              archive bytes as the host's; the parse stays on the host;
+ *              device memory is allocated and freed within the call, and a
+ *              HIP failure returns ACE_E_HIP); other bits are ACE_E_ARG
  *  n_threads   host threads for the parse (0 = all cores) */
 #define ACE_ENC_WIDE_OFFSETS 4u
+#define ACE_ENC_DEVICE_ENTROPY 8u
 typedef struct {
   uint32_t block_size, interleave, min_match, hash_len, max_chain, max_level, flags, n_threads;
 } ace_encode_params;

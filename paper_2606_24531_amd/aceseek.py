@@ -15,6 +15,8 @@ _LIB = os.path.join(_HERE, "libaceseek.so")
 
 ARCH_PAD = 4096
 OK, E_ARG, E_RANGE, E_CORRUPT, E_NOSPACE, E_HIP, E_TIMEOUT, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+# encoder flags beside the stream-mode policy (bits 0-1)
+ENC_WIDE_OFFSETS, ENC_DEVICE_ENTROPY = 4, 8
 
 EXPORTS = ["ace_last_error", "ace_encode_bound", "ace_encode_archive", "ace_archive_open",
            "ace_archive_close", "ace_archive_info", "ace_workspace_bytes", "ace_decode_all",
@@ -116,7 +118,9 @@ def encode_bound(n: int, **kw) -> int:
 
 
 def encode(x, **kw) -> bytes:
-    """Host encoder of the library (multi-threaded)."""
+    """Host encoder of the library (multi-threaded parse); with
+    flags | ENC_DEVICE_ENTROPY the rANS step runs on the current GPU (same
+    archive bytes)."""
     p = _params(**kw)
     src = np.frombuffer(x, dtype=np.uint8) if not isinstance(x, np.ndarray) else x
     bound = encode_bound(len(src), **kw)

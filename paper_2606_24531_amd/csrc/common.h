@@ -73,6 +73,25 @@ struct DecodeArgs {
   unsigned long long* trace;
 };
 
+// Entropy coding of token streams on the device (the encoder's rANS step):
+// stream i has n[i] symbols at sym + sym_off[i]; its coded form (table,
+// W states, words) is written at out + out_off[i] (capacity 544 + 4 W +
+// 2 n[i]), its byte count to out_len[i] (0: the stream stays raw), with
+// scratch + scr_off[i] (2 n[i] bytes) for the words.  policy: 0 rANS when
+// smaller than raw, 1 always rANS, 2 always raw.
+struct EncArgs {
+  const uint8_t* sym;
+  const uint64_t* sym_off;
+  const uint32_t* n;
+  uint8_t* out;
+  const uint64_t* out_off;
+  uint16_t* scratch;
+  const uint64_t* scr_off;
+  uint32_t* out_len;
+  uint32_t W, policy, n_streams;
+};
+hipError_t launch_rans_encode(const EncArgs& e, hipStream_t s);
+
 // Device-side planning of a batch of seeks (captured once in a HIP graph).
 // Per call, `desc` holds: u64 n, u64 d_out, then n x (lo, hi, out_off).
 struct BatchArgs {

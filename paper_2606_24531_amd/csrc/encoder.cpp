@@ -38,7 +38,10 @@
 #include <thread>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/aceseek.h"
+#include "common.h"
 
 namespace {
 
@@ -311,6 +314,85 @@ uint32_t offset_width(uint64_t n, uint32_t flags) {
   return (n > (1ull << 32) || (flags & ACE_ENC_WIDE_OFFSETS)) ? 8u : 4u;
 }
 
+// The rANS step of every stream on the current device (the streams built,
+// each holding its raw symbols): one wavefront per stream, the same bytes
+// as code_stream.  Streams the device codes take mode 1 and the coded bytes.
+int device_entropy(std::vector<EncStream>& st, uint32_t W, uint32_t policy) {
+  const size_t ns = st.size();
+  if (ns == 0) return ACE_OK;
+  std::vector<uint64_t> sym_off(ns), out_off(ns), scr_off(ns);
+  std::vector<uint32_t> nsym(ns);
+  uint64_t a = 0, o = 0, w = 0;
+  for (size_t i = 0; i < ns; i++) {
+    nsym[i] = st[i].n_sym;
+    sym_off[i] = a;
+    out_off[i] = o;
+    scr_off[i] = w;
+    a += st[i].n_sym;
+    o += rup(544 + 4ull * W + 2ull * st[i].n_sym, 16);
+    w += st[i].n_sym;
+  }
+  std::vector<uint8_t> sym(a ? a : 1);
+  for (size_t i = 0; i < ns; i++)
+    if (st[i].n_sym) memcpy(sym.data() + sym_off[i], st[i].data.data(), st[i].n_sym);
+  uint8_t *d_sym = nullptr, *d_out = nullptr;
+  uint64_t *d_soff = nullptr, *d_ooff = nullptr, *d_woff = nullptr;
+  uint32_t *d_n = nullptr, *d_len = nullptr;
+  uint16_t* d_scr = nullptr;
+  auto release = [&]() {
+    for (void* q : {(void*)d_sym, (void*)d_out, (void*)d_soff, (void*)d_ooff, (void*)d_woff, (void*)d_n,
+                    (void*)d_len, (void*)d_scr})
+      if (q) (void)hipFree(q);
+  };
+  auto hip = [&](hipError_t r, const char* what) {
+    if (r == hipSuccess) return ACE_OK;
+    release();
+    return efail(ACE_E_HIP, "device entropy coding: %s: %s", what, hipGetErrorString(r));
+  };
+  int rc;
+  if ((rc = hip(hipMalloc((void**)&d_sym, sym.size()), "allocate symbols")) ||
+      (rc = hip(hipMalloc((void**)&d_out, o ? o : 16), "allocate output")) ||
+      (rc = hip(hipMalloc((void**)&d_scr, 2 * (w ? w : 1)), "allocate scratch")) ||
+      (rc = hip(hipMalloc((void**)&d_soff, 8 * ns), "allocate offsets")) ||
+      (rc = hip(hipMalloc((void**)&d_ooff, 8 * ns), "allocate offsets")) ||
+      (rc = hip(hipMalloc((void**)&d_woff, 8 * ns), "allocate offsets")) ||
+      (rc = hip(hipMalloc((void**)&d_n, 4 * ns), "allocate counts")) ||
+      (rc = hip(hipMalloc((void**)&d_len, 4 * ns), "allocate lengths")))
+    return rc;
+  if ((rc = hip(hipMemcpy(d_sym, sym.data(), sym.size(), hipMemcpyHostToDevice), "copy symbols")) ||
+      (rc = hip(hipMemcpy(d_soff, sym_off.data(), 8 * ns, hipMemcpyHostToDevice), "copy offsets")) ||
+      (rc = hip(hipMemcpy(d_ooff, out_off.data(), 8 * ns, hipMemcpyHostToDevice), "copy offsets")) ||
+      (rc = hip(hipMemcpy(d_woff, scr_off.data(), 8 * ns, hipMemcpyHostToDevice), "copy offsets")) ||
+      (rc = hip(hipMemcpy(d_n, nsym.data(), 4 * ns, hipMemcpyHostToDevice), "copy counts")))
+    return rc;
+  ace::EncArgs e{};
+  e.sym = d_sym;
+  e.sym_off = d_soff;
+  e.n = d_n;
+  e.out = d_out;
+  e.out_off = d_ooff;
+  e.scratch = d_scr;
+  e.scr_off = d_woff;
+  e.out_len = d_len;
+  e.W = W;
+  e.policy = policy;
+  e.n_streams = (uint32_t)ns;
+  if ((rc = hip(ace::launch_rans_encode(e, nullptr), "launch")) || (rc = hip(hipDeviceSynchronize(), "run")))
+    return rc;
+  std::vector<uint32_t> len(ns);
+  std::vector<uint8_t> out(o ? o : 16);
+  if ((rc = hip(hipMemcpy(len.data(), d_len, 4 * ns, hipMemcpyDeviceToHost), "copy lengths")) ||
+      (rc = hip(hipMemcpy(out.data(), d_out, out.size(), hipMemcpyDeviceToHost), "copy output")))
+    return rc;
+  release();
+  for (size_t i = 0; i < ns; i++) {
+    if (!len[i]) continue;  // stays raw
+    st[i].mode = 1;
+    st[i].data.assign(out.data() + out_off[i], out.data() + out_off[i] + len[i]);
+  }
+  return ACE_OK;
+}
+
 int check(uint64_t n, const ace_encode_params* p) {
   if (!p) return efail(ACE_E_ARG, "null parameters");
   if (p->block_size < 1 || p->block_size > (1u << 24)) return efail(ACE_E_ARG, "block_size outside 1..2^24");
@@ -318,7 +400,7 @@ int check(uint64_t n, const ace_encode_params* p) {
   if (p->hash_len < 1 || p->hash_len > 64) return efail(ACE_E_ARG, "hash_len outside 1..64");
   if (p->min_match < p->hash_len) return efail(ACE_E_ARG, "min_match below hash_len");
   if ((p->flags & 3) == 3) return efail(ACE_E_ARG, "unknown stream-mode policy");
-  if (p->flags & ~7u) return efail(ACE_E_ARG, "unknown flag bits 0x%x", p->flags & ~7u);
+  if (p->flags & ~15u) return efail(ACE_E_ARG, "unknown flag bits 0x%x", p->flags & ~15u);
   if (n > (1ull << 32)) return efail(ACE_E_ARG, "inputs above 4 GiB are not supported by this encoder");
   return ACE_OK;
 }
@@ -426,6 +508,7 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
   std::vector<uint32_t>().swap(C.prev);
   // streams, in parallel over blocks
   std::vector<EncStream> st(3 * nb);
+  const bool device = (p->flags & ACE_ENC_DEVICE_ENTROPY) != 0;
   parallel_for(nb, T, [&](uint64_t b) {
     const std::vector<Seq>& sq = seqs[b];
     std::vector<uint8_t> lit, lens(4 * sq.size()), offs(ow * sq.size());
@@ -437,10 +520,19 @@ extern "C" int ace_encode_archive(const uint8_t* x, uint64_t n, const ace_encode
       put16(&lens[4 * k + 2], sq[k].M);
       for (uint32_t i = 0; i < ow; i++) offs[ow * k + i] = (uint8_t)(sq[k].O >> (8 * i));
     }
+    if (device) {  // raw for now: coded on the device below
+      const std::vector<uint8_t>* v[3] = {&lit, &lens, &offs};
+      for (int t = 0; t < 3; t++) {
+        st[3 * b + t].n_sym = (uint32_t)v[t]->size();
+        st[3 * b + t].data = *v[t];
+      }
+      return;
+    }
     code_stream(lit.data(), (uint32_t)lit.size(), W, policy, st[3 * b]);
     code_stream(lens.data(), (uint32_t)lens.size(), W, policy, st[3 * b + 1]);
     code_stream(offs.data(), (uint32_t)offs.size(), W, policy, st[3 * b + 2]);
   });
+  if (device && (rc = device_entropy(st, W, policy))) return rc;
   // layout
   uint64_t n_deps = 0, depth = 0;
   for (uint64_t b = 0; b < nb; b++) {

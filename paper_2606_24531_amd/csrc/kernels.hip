@@ -323,6 +323,137 @@ __device__ __forceinline__ bool rans_decode_group(const uint8_t* src, uint32_t c
   return grp_any<G>(bad, h);
 }
 
+// ---------------------------------------------------------------------------
+// Entropy coding on the device (the encoder's rANS step, Section 2 and the
+// ANS layer of Section 9): one wavefront per stream, output byte for byte
+// that of the host encoder.  The frequencies are normalised to 4096 as the
+// host does it (f = max(1, floor(c * 4096 / n)), the deficit to the largest
+// f, ties to the lower symbol, any excess taken one at a time from the
+// largest f > 1); the symbols are coded last to first, lane j holding state
+// j (symbols j, j + W, ...), and a step's renormalisation words are numbered
+// in the order the host emits them (higher lanes first), so that the words
+// read forwards come out in the order the decoder consumes them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_rans_enc(EncArgs e) {
+  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t ftab[256], ctab[256];
+  const uint32_t i = blockIdx.x, lane = threadIdx.x;
+  if (i >= e.n_streams) return;
+  const uint32_t n = e.n[i], W = e.W;
+  if (n == 0 || e.policy == 2) {
+    if (lane == 0) e.out_len[i] = 0;
+    return;
+  }
+  const uint8_t* sym = e.sym + e.sym_off[i];
+  for (uint32_t s = lane; s < 256; s += 64) cnt[s] = 0;
+  wave_sync();
+  for (uint32_t k = lane; k < n; k += 64) atomicAdd(&cnt[ld8(sym + k)], 1u);
+  wave_sync();
+  // normalisation: lane owns symbols 4 lane .. 4 lane + 3
+  uint32_t f[4], sum = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; q++) {
+    const uint64_t c = cnt[4 * lane + q];
+    const uint64_t v = c * 4096ull / n;
+    f[q] = c ? (v < 1 ? 1u : (uint32_t)v) : 0u;
+    sum += f[q];
+  }
+  sum = uniform(wave_total(sum));
+  // the largest f above `floor_` (ties: lower symbol) as f << 8 | (255 - s)
+  auto largest = [&](uint32_t floor_) {
+    uint32_t key = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++)
+      if (f[q] > floor_) key = max(key, (f[q] << 8) | (255u - (4 * lane + q)));
+    return uniform(lane63(wave_incl_max(key)));
+  };
+  if (sum < 4096) {
+    const uint32_t best = 255u - (largest(0) & 0xFFu);
+    if (best >> 2 == lane) {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++)
+        if (q == (best & 3)) f[q] += 4096 - sum;
+    }
+  }
+  for (; sum > 4096; sum--) {
+    const uint32_t best = 255u - (largest(1) & 0xFFu);
+    if (best >> 2 == lane) {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++)
+        if (q == (best & 3)) f[q]--;
+    }
+  }
+  // cumulative frequencies and the table's size
+  const uint32_t fl = f[0] + f[1] + f[2] + f[3];
+  uint32_t cum = wave_incl_sum(fl, 0) - fl;
+  const uint32_t pl = (f[0] != 0) + (f[1] != 0) + (f[2] != 0) + (f[3] != 0);
+  uint32_t rank = wave_incl_sum(pl, 0) - pl;
+  const uint32_t present = uniform(wave_total(pl));
+  const uint32_t tsz = (32 + 2 * present + 3) & ~3u;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; q++) {
+    ftab[4 * lane + q] = f[q];
+    ctab[4 * lane + q] = cum;
+    cum += f[q];
+  }
+  wave_sync();
+  // code last symbol first; words go to the scratch from its end backwards
+  uint16_t* scr = e.scratch + e.scr_off[i];
+  uint32_t x = 65536u, emitted = 0;
+  const uint32_t steps = (n + W - 1) / W;
+  const uint64_t above = lane == 63 ? 0ull : ~0ull << (lane + 1);  // lanes above this one
+  for (uint32_t t = steps; t-- > 0;) {
+    const uint32_t k = t * W + lane;
+    const bool act = lane < W && k < n;
+    uint32_t fs = 1, cs = 0;
+    if (act) {
+      const uint32_t s = ld8(sym + k);
+      fs = ftab[s];
+      cs = ctab[s];
+    }
+    const bool emit = act && (uint64_t)x >= ((uint64_t)fs << 20);
+    const uint64_t m = __ballot(emit);
+    if (emit) {
+      const uint32_t r = emitted + (uint32_t)__popcll(m & above);  // the host's word index
+      scr[n - 1 - r] = (uint16_t)x;
+      x >>= 16;
+    }
+    emitted += (uint32_t)__popcll(m);
+    if (act) x = (x / fs) * 4096u + (x % fs) + cs;
+  }
+  const uint64_t size = tsz + 4ull * W + 2ull * emitted;
+  if (e.policy != 1 && size >= n) {
+    if (lane == 0) e.out_len[i] = 0;
+    return;
+  }
+  uint8_t* o = e.out + e.out_off[i];
+  // table: presence bitmap (lane l < 32 writes byte l), then f - 1 per
+  // present symbol in symbol order, then zero padding to 4 bytes
+  const uint32_t bits = (f[0] != 0) | ((f[1] != 0) << 1) | ((f[2] != 0) << 2) | ((f[3] != 0) << 3);
+  const uint32_t pair = bits | ((uint32_t)__shfl_xor((int)bits, 1, 64) << 4);  // lanes 2b, 2b + 1
+  if (!(lane & 1)) st8(o + (lane >> 1), (uint8_t)pair);
+#pragma unroll
+  for (uint32_t q = 0; q < 4; q++) {
+    if (f[q]) {
+      st8(o + 32 + 2 * rank, (uint8_t)(f[q] - 1));
+      st8(o + 33 + 2 * rank, (uint8_t)((f[q] - 1) >> 8));
+      rank++;
+    }
+  }
+  if (lane < tsz - 32 - 2 * present) st8(o + 32 + 2 * present + lane, 0);
+  if (lane < W) {
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) st8(o + tsz + 4 * lane + b, (uint8_t)(x >> (8 * b)));
+  }
+  uint8_t* wp = o + tsz + 4 * W;
+  for (uint32_t w = lane; w < emitted; w += 64) {
+    const uint32_t v = scr[n - emitted + w];
+    st8(wp + 2 * w, (uint8_t)v);
+    st8(wp + 2 * w + 1, (uint8_t)(v >> 8));
+  }
+  if (lane == 0) e.out_len[i] = (uint32_t)size;
+}
+
 // Kernel (a): grid (ceil(n_plan / (64/G)), 3); each wavefront decodes stream
 // t of 64/G consecutive plan entries.  LIT goes to lit + plan_index * B, LEN
 // to lens + 4 * seq_base and OFF to offs + ow * seq_base; raw streams are
@@ -1652,6 +1783,12 @@ static hipError_t launch_expand(const DecodeArgs& a, uint32_t grid, uint32_t pla
     case 8: hipLaunchKernelGGL(k_expand<512>, dim3(grid), dim3(512), 0, s, a, plan_lo, level); break;
     default: hipLaunchKernelGGL(k_expand<128>, dim3(grid), dim3(128), 0, s, a, plan_lo, level); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_rans_encode(const EncArgs& e, hipStream_t s) {
+  if (e.n_streams == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rans_enc, dim3(e.n_streams), dim3(64), 0, s, e);
   return hipGetLastError();
 }
 

@@ -228,3 +228,50 @@ print("OK")
     r = subprocess.run([sys.executable, "-c", code % {"root": ROOT, "tests": HERE, "case": case}],
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
+
+
+@pytest.mark.parametrize("case", [("genome", 1 << 20, 16384, 32, 0, 0), ("text", 300_000, 4096, 64, 8, 1),
+                                  ("mixed", 700_001, 16384, 7, 0, 4), ("fastq", 200_000, 16384, 64, 0, 2),
+                                  ("tandem", 400_000, 4096, 1, 8, 0), ("text", 40_000, 37, 3, 0, 0)],
+                         ids=lambda c: "%s-n%d-B%d-W%d-f%d" % (c[0], c[1], c[2], c[3], c[5]))
+def test_device_entropy_coding_matches_host(orc, case):
+    """The encoder's rANS step run by the device kernel (the CPU build of
+    it) gives the same archive bytes as the host's and the oracle's
+    encoder, for every stream-mode policy."""
+    name, n, B, W, cap, flags = case
+    code = r"""
+import sys
+sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
+import ctypes as C, numpy as np, gen, simt_lib
+from paper_2606_24531_amd import aceseek
+name, n, B, W, cap, flags = %(case)r
+x = gen.by_name(name, n, 29)
+L = simt_lib.lib()
+p = aceseek.EncodeParams(B, W, 16 if name != "genome" else 20, 16, 32, cap, flags | 8, 0)
+L.ace_encode_bound.argtypes = [C.c_uint64, C.POINTER(aceseek.EncodeParams), C.POINTER(C.c_uint64)]
+L.ace_encode_archive.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(aceseek.EncodeParams), C.c_void_p,
+                                 C.c_uint64, C.POINTER(C.c_uint64)]
+b = C.c_uint64(0)
+assert L.ace_encode_bound(n, C.byref(p), C.byref(b)) == 0
+src = np.frombuffer(x, dtype=np.uint8)
+out = np.zeros(b.value, dtype=np.uint8)
+ln = C.c_uint64(0)
+rc = L.ace_encode_archive(src.ctypes.data_as(C.c_void_p), n, C.byref(p), out.ctypes.data_as(C.c_void_p),
+                          out.size, C.byref(ln))
+assert rc == 0, (rc, L.ace_last_error())
+open(%(path)r, "wb").write(out[:ln.value].tobytes())
+print("OK")
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "a.bin")
+        r = subprocess.run([sys.executable, "-c", code % {"root": ROOT, "tests": HERE, "case": case, "path": path}],
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0 and "OK" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
+        got = open(path, "rb").read()
+    import gen
+    x = gen.by_name(name, n, 29)
+    mm = 16 if name != "genome" else 20
+    want = orc.encode(x, block_size=B, interleave=W, min_match=mm, hash_len=16, max_chain=32, max_level=cap,
+                      flags=flags)
+    assert got == want
