@@ -76,7 +76,7 @@ typedef struct {
   uint64_t lo, hi;
 } ace_range;
 
-/* Launch shape.  Zero fields take the library defaults; a value this build
+/* Launch shape.  Zero fields take the library defaults; a value the library
  * does not offer is ACE_E_ARG.
  *  waves_per_block  wavefronts cooperating on one block's match expansion:
  *                   1, 2, 4 or 8; each takes two sequences per lane per

@@ -340,7 +340,7 @@ hipError_t overlap_for(size_t n_levels, Overlap*& o) {
   return hipSuccess;
 }
 
-// Launch-shape fields of a tuning record that this build offers.
+// Launch-shape fields of a tuning record that the library offers.
 int check_tuning(const ace_archive* A, const ace_tuning* t) {
   if (!t) return ACE_OK;
   const uint32_t w = t->waves_per_block, p = t->blocks_per_wg;
@@ -854,20 +854,32 @@ extern "C" int ace_seek_ooc(const ace_archive* A, uint64_t lo, uint64_t hi, uint
     M->ooc_pinned_cap = staged;
   }
   uint8_t* h = M->ooc_pinned;
-  uint64_t dpos = 0, ppos = align_up(P.deps_bytes, 16);
+  // the dependency lists, then the payloads; each 4 MiB packed is copied
+  // while the host packs the next (the copies are asynchronous from pinned
+  // memory, and each reads only bytes already packed)
+  uint64_t dpos = 0;
   for (PlanEntry& e : P.entries) {
     const BlockInfo& bi = A->blk[e.block];
     memcpy(h + dpos, A->deps.data() + bi.dep_off, 4ull * bi.dep_cnt);
     e.dep_off = (uint32_t)(dpos / 4);
     dpos += 4ull * bi.dep_cnt;
+  }
+  constexpr uint64_t kChunk = 4ull << 20;
+  uint64_t sent = 0, ppos = align_up(P.deps_bytes, 16);
+  for (PlanEntry& e : P.entries) {
+    const BlockInfo& bi = A->blk[e.block];
     memcpy(h + ppos, A->h_arch + bi.pay, bi.plen);
     const uint64_t pay = P.gap + ppos;  // offset from the kernels' archive base
     for (int k = 0; k < 3; k++)
       if (e.raw[k] != kCoded) e.raw[k] = e.raw[k] - bi.pay + pay;
     e.pay = pay;
     ppos += align_up(bi.plen, 16);
+    if (ppos - sent >= kChunk) {
+      HIP_TRY(hipMemcpyAsync(ws + P.stage + sent, h + sent, ppos - sent, hipMemcpyHostToDevice, s));
+      sent = ppos;
+    }
   }
-  HIP_TRY(hipMemcpyAsync(ws + P.stage, h, staged, hipMemcpyHostToDevice, s));
+  if (staged > sent) HIP_TRY(hipMemcpyAsync(ws + P.stage + sent, h + sent, staged - sent, hipMemcpyHostToDevice, s));
   const int rc = run(A, P.entries.data(), P.entries.size(), P.lstart, P.items.data(), P.items.size(), P.L, ws, 0,
                      t, s, false, false, nullptr, ws + P.stage - P.gap);
   if (rc) return rc;

@@ -73,3 +73,22 @@ def test_out_of_core_stages_only_the_closure(dev, orc):
                           None, None)
     assert rc == aceseek.E_ARG and b"out of core" in L.ace_last_error()
     arc.close()
+
+
+def test_out_of_core_seek_writes_only_its_range(dev, orc):
+    """The paper's three-phase check on out-of-core seeks: the output buffer
+    is filled with a sentinel, the seek writes its range into the middle of
+    it, and the bytes around the range keep the sentinel."""
+    from paper_2606_24531_amd import OutOfCoreArchive
+    x = gen.by_name("genome", 1 << 20, 3)
+    a = orc.encode(x, block_size=16384, interleave=32, min_match=20, hash_len=16, max_level=0)
+    arc = OutOfCoreArchive(a, device=dev)
+    pad = 4096
+    for lo, hi in [(0, 16384), (16384 * 5 + 7, 16384 * 9 + 3), (len(x) - 100, len(x)), (12345, 12346)]:
+        buf = torch.full((hi - lo + 2 * pad,), 0xA5, dtype=torch.uint8, device=dev)
+        arc.seek(lo, hi, out=buf[pad:pad + hi - lo])
+        arc.check()
+        host = buf.cpu().numpy()
+        assert host[pad:pad + hi - lo].tobytes() == x[lo:hi]
+        assert (host[:pad] == 0xA5).all() and (host[pad + hi - lo:] == 0xA5).all(), (lo, hi)
+    arc.close()
