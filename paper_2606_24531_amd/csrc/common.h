@@ -61,6 +61,9 @@ struct DecodeArgs {
   uint32_t* lvl_claim;  // per slice and level: expansions claimed (slice-major rows)
   uint32_t lvl_row;     // words per slice row of lvl_claim
   uint32_t* lvl_seen;   // levels finished, in copies one 128-byte line apart
+  // per level and XCD: blocks done so far << 32 | workgroups expanding, then
+  // the blocks already written back (kMaxXcc of each per level)
+  unsigned long long* lvl_xcd;
   uint32_t max_polls;   // consecutive idle polls before a wait gives up
   // plan length (device-planned batches; null for host-planned calls) and
   // level boundaries in device memory (device-planned batches and the
@@ -124,20 +127,23 @@ hipError_t launch_expand_level(const DecodeArgs& a, uint32_t plan_lo, uint32_t p
 // the persistent level-by-level expansion (kernel (c)); grid 0 = as many
 // workgroups as the device holds at once.  Its counters (persist_sync_words
 // words from lvl_done, laid out by persist_sync) start at zero.
-constexpr uint32_t kPersistSlices = 8, kPersistReplicas = 64, kPersistLine = 32;
+constexpr uint32_t kPersistSlices = 8, kPersistReplicas = 64, kPersistLine = 32, kMaxXcc = 16;
 inline uint64_t persist_row(uint32_t n_lvl) { return (n_lvl + kPersistLine - 1ull) / kPersistLine * kPersistLine; }
 inline uint64_t persist_sync_words(uint32_t n_lvl) {
-  return (1 + kPersistSlices) * persist_row(n_lvl) + (uint64_t)kPersistReplicas * kPersistLine;
+  return (1 + kPersistSlices) * persist_row(n_lvl) + (uint64_t)kPersistReplicas * kPersistLine +
+         4ull * kMaxXcc * n_lvl;
 }
 // Points the kernel's counters into `words` (128-byte aligned, at least
 // persist_sync_words(a.n_lvl) words): finished counts, one row per level;
-// claim counts, one row per slice; the finished-level copies.
+// claim counts, one row per slice; the finished-level copies; per level,
+// 2 kMaxXcc 64-bit counters (two per XCD).
 inline void persist_sync(DecodeArgs& a, uint32_t* words) {
   const uint64_t row = persist_row(a.n_lvl);
   a.lvl_done = words;
   a.lvl_claim = words + row;
   a.lvl_row = (uint32_t)row;
   a.lvl_seen = words + (1 + kPersistSlices) * row;
+  a.lvl_xcd = reinterpret_cast<unsigned long long*>(a.lvl_seen + (uint64_t)kPersistReplicas * kPersistLine);
 }
 hipError_t launch_persistent(const DecodeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const DecodeArgs& a, const CopyItem* items, uint32_t n_items,

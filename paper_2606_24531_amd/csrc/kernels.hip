@@ -1419,6 +1419,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kThrea
 // polls); expansions then no longer read earlier blocks, so the launch always
 // drains (its output is then not valid, and ace_check reports the timeout).
 // ---------------------------------------------------------------------------
+// The XCD (accelerator complex die) this wave runs on: the XCC_ID hardware
+// register, bits 3:0.
+__device__ __forceinline__ uint32_t xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kMaxXcc - 1);
+}
+
 constexpr uint32_t kPersistThreads = 128;
 constexpr uint32_t kNoItem = 0xffffffffu;
 
@@ -1462,7 +1468,12 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
     if (blockIdx.x < size) {
       const uint32_t n_home = slice_size(size, home);
       uint32_t* home_claim = a.lvl_claim + (uint64_t)home * a.lvl_row + lvl;
-      if (tid == 0) sh_item[0] = claim_any(a, lvl, lo, size, home);
+      unsigned long long* xc = a.lvl_xcd + (uint64_t)lvl * 2 * kMaxXcc + xcc_id();
+      if (tid == 0) {
+        sh_item[0] = claim_any(a, lvl, lo, size, home);
+        // expanding on this XCD from now on (before any of this level's stores)
+        if (sh_item[0] != kNoItem) atomicAdd(xc, 1ull);
+      }
       __syncthreads();
       uint32_t item = sh_item[0], par = 0;
       // the levels below are complete: make their bytes visible here (only
@@ -1485,13 +1496,30 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
         item = sh_item[par];
       }
       if (mine) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // this workgroup's stores have reached its XCD's L2.  Leaving, it
+        // adds its blocks to the XCD's running count; the workgroup that
+        // leaves the XCD with none expanding writes that L2 back once (an
+        // agent-scope release, covering every block counted so far) and
+        // raises the XCD's written-back count to the running count, adding
+        // what it raised to the level's finished count.  A level is
+        // complete once every XCD holding its bytes has written them back.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (tid < kPersistReplicas) {  // wave 0: lane r raises copy r
-          uint32_t prev = 0;
-          if (tid == 0) prev = atomicAdd(a.lvl_done + lvl, mine);
+          uint32_t add = 0, prev = 0;
+          if (tid == 0) {
+            const unsigned long long old = atomicAdd(xc, ((unsigned long long)mine << 32) - 1ull);
+            if ((uint32_t)old == 1u) {
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+              const unsigned long long total = (old >> 32) + mine;
+              const unsigned long long was = atomicMax(xc + kMaxXcc, total);
+              add = total > was ? (uint32_t)(total - was) : 0u;
+              if (add) prev = atomicAdd(a.lvl_done + lvl, add);
+            }
+          }
+          add = __shfl(add, 0);
           prev = __shfl(prev, 0);
-          if (prev + mine == size) {
+          if (add && prev + add == size) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_fetch_max(a.lvl_seen + tid * kPersistLine, lvl + 1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);

@@ -203,6 +203,19 @@ template <typename T, typename U>
 inline T atomicExch(T* p, U v) {
   return __atomic_exchange_n(p, (T)v, __ATOMIC_SEQ_CST);
 }
+template <typename T, typename U, typename V>
+inline T atomicCAS(T* p, U expected, V desired) {
+  T e = (T)expected;
+  __atomic_compare_exchange_n(p, &e, (T)desired, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+  return e;  // the value found (equal to expected when the exchange happened)
+}
+// s_getreg: the XCC_ID register (20) reads as the workgroup index mod 8,
+// the round-robin placement of workgroups over eight XCDs; other
+// registers read as 0
+inline uint32_t simt_getreg(uint32_t imm) {
+  return (imm & 63u) == 20u ? (uint32_t)(::simt::block_idx().x % 8u) : 0u;
+}
+#define __builtin_amdgcn_s_getreg(imm) simt_getreg((uint32_t)(imm))
 
 // ---- runtime API (synchronous: every call completes before it returns,
 // except for work recorded under stream capture, which a graph replays)
