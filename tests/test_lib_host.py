@@ -200,3 +200,39 @@ def test_workspace_bound_covers_every_batch(lib):
     assert need(np.array([0], dtype=np.uint64), np.array([len(x)], dtype=np.uint64)) <= bound(1, len(x))
     assert L.ace_workspace_bound(None, 1, 1, C.byref(C.c_uint64())) == lib.E_ARG
     L.ace_archive_close(h)
+
+
+def test_out_of_core_handle_errors(lib):
+    """Out-of-core handles: argument and range errors before any device
+    work, the workspace size covers the staged closure, and the calls that
+    need a resident archive refuse the handle (and ace_seek_ooc refuses a
+    resident one)."""
+    x = gen.text(200_000, 4)
+    a = lib.encode(x, block_size=4096, interleave=8, min_match=8, hash_len=8)
+    L = lib.lib()
+    host = np.frombuffer(a, dtype=np.uint8)
+    h = C.c_void_p()
+    assert L.ace_archive_open_ooc(None, len(a), C.byref(h)) == lib.E_ARG
+    assert L.ace_archive_open_ooc(host.ctypes.data_as(C.c_void_p), 10, C.byref(h)) == lib.E_CORRUPT
+    assert L.ace_archive_open_ooc(host.ctypes.data_as(C.c_void_p), len(a), C.byref(h)) == 0
+    b = C.c_uint64()
+    assert L.ace_seek_ooc_bytes(h, 10, 5, C.byref(b)) == lib.E_ARG
+    assert L.ace_seek_ooc_bytes(h, 0, len(x) + 1, C.byref(b)) == lib.E_RANGE
+    assert L.ace_seek_ooc_bytes(h, 7, 7, C.byref(b)) == 0 and b.value == 0
+    assert L.ace_seek_ooc_bytes(h, 4096 * 30 + 5, 4096 * 30 + 9, C.byref(b)) == 0
+    one = b.value
+    assert L.ace_seek_ooc_bytes(h, 0, len(x), C.byref(b)) == 0
+    # the whole range stages every payload: at least the archive's payload bytes
+    assert b.value >= len(a) - (64 + 32 * 49) and b.value >= one
+    dummy = C.c_void_p(0x1000)
+    assert L.ace_seek_ooc(h, 0, 10, dummy, dummy, 16, None, None) == lib.E_NOSPACE
+    assert b"workspace needs" in L.ace_last_error()
+    assert L.ace_seek(h, 0, 10, dummy, dummy, 1 << 30, None, None) == lib.E_ARG
+    assert b"out of core" in L.ace_last_error()
+    assert L.ace_decode_all(h, dummy, len(x), dummy, 1 << 30, None, None) == lib.E_ARG
+    L.ace_archive_close(h)
+    rc, r = _open(lib, a)
+    assert rc == 0
+    assert L.ace_seek_ooc(r, 0, 10, dummy, dummy, 1 << 30, None, None) == lib.E_ARG
+    assert b"not opened out of core" in L.ace_last_error()
+    L.ace_archive_close(r)
