@@ -1520,7 +1520,9 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
           add = __shfl(add, 0);
           prev = __shfl(prev, 0);
           if (add && prev + add == size) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            // no fence here: every XCD holding the level's bytes wrote them
+            // back before its add, and this raise is issued after the add
+            // that returned the level complete
             __hip_atomic_fetch_max(a.lvl_seen + tid * kPersistLine, lvl + 1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
           }
